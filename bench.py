@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""HOTRG contraction throughput on one MI355X.
+
+Workload (one "step" of this benchmark = one full HOTRG solve, every row of
+the hot path): 2D Ising, J = 1, bond dimension D = 48, 30 alternating
+coarse-graining steps, temperatures cycling through 16 evenly spaced values
+in [2.0, 2.5].  The initial tensor is built from the temperature (128 bytes
+of input); all intermediates stay in HBM.
+
+value = algorithmic contraction FLOPs of the timed solves (O(D^7) order,
+eigensolve excluded from the count but not from the time) / wall time of
+the timed region.  Also reported: per-solve latency p50/p99, per-stage GPU
+times from HIP events on the solve's stream, the roofline of the dominant
+kernel (the Y product) and the FP64 CPU oracle on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc"}
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(dmax: int, nsteps_sample: int, temperature: float):
+    """The FP64 oracle, as it stands, on the first steps of one solve of the
+    same workload (steps 1..nsteps_sample; the last is a full D^7 step)."""
+    from oracle import hotrg as oracle
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    oracle.solve("ising", 2, temperature, dmax, nsteps_sample, keep_tensor=False)
+    dt = time.perf_counter() - t0
+    flops = sum(oracle.contraction_flops(*d) for d in oracle.step_dims(2, 2, dmax, nsteps_sample))
+    return {
+        "value": flops / dt / 1e12,
+        "unit": "TFLOP/s",
+        "cores": threads or os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"first {nsteps_sample} of 30 steps of one D={dmax} Ising solve at T={temperature:.4f} "
+                  f"({flops:.3e} contraction FLOPs in {dt:.2f} s, FP64 NumPy/LAPACK)",
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--dmax", type=int, default=48)
+    ap.add_argument("--nsteps", type=int, default=30, help="coarse-graining steps per solve")
+    ap.add_argument("--cpu-sample-steps", type=int, default=7)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2602_05900_amd import accounting, binding, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    temps = workloads.temperature_grid(2.0, 2.5, 16)
+    stream = torch.cuda.Stream(device=dev)
+    kw = dict(model="ising", q=2, dmax=args.dmax, precision=args.precision, max_steps=args.nsteps)
+    ws = torch.empty(binding.workspace_bytes(temperature=float(temps[0]), **kw), dtype=torch.uint8, device=dev)
+    solve = binding.Solve(temperature=float(temps[0]), stream=stream, workspace=ws, **kw)
+    solve.set_timing(True)
+
+    flops_solve = accounting.solve_flops(2, args.dmax, args.nsteps)
+    dims = accounting.step_dims(2, 2, args.dmax, args.nsteps)
+    y_flops = sum(accounting.stage_flops(*d)["y"] for d in dims)
+
+    def run_one(i):
+        T = float(temps[i % len(temps)])
+        solve.reset(temperature=T, **kw)
+        solve.coarse_grain(args.nsteps)
+        lnz = solve.log_z()
+        st, nt = solve.stage_times()
+        return T, lnz, st
+
+    for w in range(args.warmup):
+        run_one(w)
+        print(f"# warmup solve {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    lat, stage_sum, results = [], {k: 0.0 for k in binding.STAGES}, []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        T, lnz, st = run_one(args.warmup + i)
+        lat.append(time.perf_counter() - t0)
+        for k, v in st.items():
+            stage_sum[k] += v
+        results.append((T, lnz))
+        print(f"# solve {i + 1}/{args.steps}: T={T:.4f} lnZ/N={lnz:.15f} {lat[-1] * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    total_flops = flops_solve * args.steps
+    value = total_flops / wall / 1e12
+    y_ms = stage_sum["y"]
+    achieved = y_flops * args.steps / (y_ms * 1e-3) / 1e12 if y_ms > 0 else None
+    peak = PEAK_TFLOPS[args.precision]
+    hw_achieved = achieved * PRODUCTS[args.precision] if achieved else None
+    contraction_ms = stage_sum["env"] + stage_sum["x"] + stage_sum["y"] + stage_sum["tp"]
+
+    line = {
+        "metric": "HOTRG contraction TFLOP/s at D=48 (FP64 vs mixed); p50/p99 solve latency",
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"HOTRG 2D Ising J=1, D={args.dmax}, {args.nsteps} steps per solve, "
+                        f"T cycling over 16 values in [2.0, 2.5]; one step of this benchmark = one solve",
+            "dmax": args.dmax,
+            "coarse_grain_steps": args.nsteps,
+            "contraction_precision": args.precision,
+            "eigensolve": "FP64",
+            "flops_per_solve": flops_solve,
+        },
+        "p50_solve_ms": percentile(lat, 50) * 1e3,
+        "p99_solve_ms": percentile(lat, 99) * 1e3,
+        "solves_per_s": args.steps / wall,
+        "stage_ms_per_solve": {k: v / args.steps for k, v in stage_sum.items()},
+        "contraction_kernel_tflops": total_flops / (contraction_ms * 1e-3) / 1e12 if contraction_ms else None,
+        "roofline": {
+            "kernel": "gemm_nt (Y = X . T, the D^7 product)",
+            "bound": "mfma",
+            "achieved": hw_achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": hw_achieved / peak if hw_achieved else None,
+            "traffic": None,
+            "algorithmic_flops_per_solve": y_flops,
+            "launches": args.nsteps * args.steps,
+        },
+        "lnz_per_site": {f"{T:.6f}": v for T, v in results},
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))
+    solve.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * hotrg.h — C ABI of the MI355X (gfx950) HOTRG coarse-graining library.
+ *
+ * The library evaluates the partition function of a 2D square-lattice
+ * classical model written as the contraction of a network of identical
+ * rank-4 tensors, Z = Tr T^N (Sec. II.A, Eq. (2)), by the higher-order tensor
+ * renormalization group: at each step two neighbouring tensors are merged
+ * along one lattice direction, the two parallel bonds are fused, and the fused
+ * bond is truncated to at most D states by the leading eigenvectors of the
+ * environment matrix, to which the higher-order SVD reduces (Sec. II.A).  The
+ * contractions run as hand-written MFMA kernels; the truncation eigensolve,
+ * the per-step normalisation and the ln Z accumulation are always FP64.
+ *
+ * Conventions used by every entry point
+ *   - A local tensor is T[l, r, d, u] with dims [Dx, Dx, Dy, Dy], row-major,
+ *     u fastest (l, r: the x bond; d, u: the y bond).
+ *   - A step stacks two copies along y, fuses the two x legs (bottom first),
+ *     keeps D' = min(D, Dx^2) states, normalises by c_n = max|T'| and then
+ *     exchanges x and y, so the next step merges the other direction.  The
+ *     dims go (Dx, Dy) -> (Dy, D').
+ *   - After n steps the tensor stands for a periodic torus of 2^n sites,
+ *     2^floor(n/2) sites along x by 2^ceil(n/2) along y.
+ *
+ * Memory and streams: the caller owns the device workspace (one allocation
+ * of hotrg_workspace_bytes(), e.g. a torch uint8 tensor) and the HIP stream;
+ * every kernel of a solve is enqueued on that stream and nothing is
+ * allocated on the device per step.  The library owns only the host handle,
+ * its events and the eigensolver context, which it creates at init.
+ *
+ * Errors: every int-returning call returns HOTRG_OK (0) or a negative
+ * status.  Errors detected on the device (non-finite or non-positive c_n, a
+ * failed eigensolve) are latched in a device status word; the first one
+ * sticks and is returned by the next synchronising call (hotrg_log_z,
+ * hotrg_step_info, hotrg_copy_tensor).  No C++ exception crosses this ABI.
+ * Distinct handles are independent and may be driven from different host
+ * threads; one handle must not be used from two threads at once.
+ */
+#ifndef HOTRG_H
+#define HOTRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HOTRG_OK          0
+#define HOTRG_EINVAL     -1  /* invalid argument or parameter set           */
+#define HOTRG_ENOMEM     -2  /* workspace smaller than hotrg_workspace_bytes */
+#define HOTRG_EHIP       -3  /* a HIP runtime call failed                    */
+#define HOTRG_EEIG       -4  /* the FP64 eigensolve reported failure         */
+#define HOTRG_ENONFINITE -5  /* c_n or the final trace not finite or <= 0    */
+#define HOTRG_ESTATE     -6  /* call not valid in the handle's state         */
+#define HOTRG_ENODEV     -7  /* no HIP device                                */
+
+/* ---- models and contraction precisions -------------------------------- */
+#define HOTRG_ISING   0  /* q = 2, H = -J sum s s'                              */
+#define HOTRG_POTTS   1  /* q states, H = -J sum delta(s, s')                  */
+#define HOTRG_CUSTOM  2  /* caller-supplied initial tensor (FP64, host memory) */
+
+#define HOTRG_FP64    0  /* contractions in FP64 MFMA                          */
+#define HOTRG_FP32    1  /* contractions in FP32 MFMA, FP32 accumulation       */
+#define HOTRG_BF16X3  2  /* operands split in 2 BF16 terms, 3 products, FP32 acc */
+#define HOTRG_BF16X6  3  /* operands split in 3 BF16 terms, 6 products, FP32 acc */
+
+#define HOTRG_MAX_STEPS 60  /* total steps per handle (2^60 sites)            */
+#define HOTRG_MAX_DIM   96  /* largest bond dimension accepted                */
+
+/* Stage indices of hotrg_stage_times(). */
+#define HOTRG_STAGE_PERMUTE 0  /* operand re-layouts of T (D^4)               */
+#define HOTRG_STAGE_ENV     1  /* half environments and E (GEMMs)             */
+#define HOTRG_STAGE_EIG     2  /* FP64 eigensolve of E, isometry selection    */
+#define HOTRG_STAGE_X       3  /* X = U . T (GEMM)                            */
+#define HOTRG_STAGE_Y       4  /* Y = X . T (GEMM, the D^7 term)              */
+#define HOTRG_STAGE_TP      5  /* T' = Y . U (GEMM)                           */
+#define HOTRG_STAGE_NORM    6  /* max|T'|, scaling, ln Z accumulation         */
+#define HOTRG_NUM_STAGES    7
+
+typedef struct hotrg_solve hotrg_solve;  /* opaque host handle */
+
+typedef struct hotrg_params {
+    int model;           /* HOTRG_ISING, HOTRG_POTTS or HOTRG_CUSTOM           */
+    int q;               /* spin states: 2 for Ising, 2..16 for Potts         */
+    double coupling;     /* J > 0 (ferromagnetic), k_B = 1                    */
+    double temperature;  /* T > 0                                             */
+    int dmax;            /* bond dimension D, 1..HOTRG_MAX_DIM                */
+    int precision;       /* HOTRG_FP64, HOTRG_FP32, HOTRG_BF16X3, HOTRG_BF16X6 */
+    const double* custom_tensor; /* HOTRG_CUSTOM: host T[l,r,d,u], row-major,
+                                    dims [Dx, Dx, Dy, Dy]; read during init only */
+    int custom_dx;       /* HOTRG_CUSTOM: Dx (1..HOTRG_MAX_DIM)               */
+    int custom_dy;       /* HOTRG_CUSTOM: Dy (1..HOTRG_MAX_DIM)               */
+    int max_steps;       /* steps the handle may take in total; sizes the
+                            workspace (0 = HOTRG_MAX_STEPS)                   */
+} hotrg_params;
+
+/* Bytes of device workspace one solve with these parameters needs, for any
+ * number of steps up to p->max_steps.  Dominated by the two D^5
+ * intermediates X and Y (Sec. II.B: the coarse-grained matrices are D^2 on
+ * a side).  Pure host arithmetic; returns 0 for an invalid parameter set. */
+size_t hotrg_workspace_bytes(const hotrg_params* p);
+
+/* Builds the initial local tensor of Eq. (2) and readies a solve.
+ *   p          parameters (copied; custom_tensor is read before returning)
+ *   workspace  device pointer, 256-byte aligned, >= hotrg_workspace_bytes(p)
+ *              bytes; owned by the caller, must outlive the handle
+ *   ws_bytes   size of that allocation
+ *   stream     hipStream_t on which all work of this solve is enqueued
+ *              (NULL = the legacy default stream)
+ *   out        receives the new handle
+ * For Ising/Potts, T0[x,x',y,y'] = sum_s Q[s,x]Q[s,x']Q[s,y]Q[s,y'] with Q
+ * the symmetric square root of the bond Boltzmann weight matrix; T0 is
+ * normalised by c_0 = max|T0| and ln c_0 starts the ln Z accumulator.  T0
+ * and the device state are copied on the stream, which init synchronises.
+ * Errors: EINVAL (parameters, NULL pointers, misaligned workspace),
+ * ENOMEM (ws_bytes too small), ENODEV, EHIP. */
+int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes,
+                      void* stream, hotrg_solve** out);
+
+/* Restarts an existing handle on a new parameter set (a new temperature,
+ * model or bond dimension) without creating a new one: the initial tensor is
+ * rebuilt exactly as in hotrg_init_tensor, the step count and the device
+ * status are cleared, and the handle's workspace, eigensolver context and
+ * timing events are kept.  Synchronises the handle's stream first.
+ * Errors: EINVAL (parameters), ENOMEM (the handle's workspace or eigensolver
+ * context is too small for p: create a new handle instead), EHIP. */
+int hotrg_reset(hotrg_solve* s, const hotrg_params* p);
+
+/* Enqueues nsteps >= 0 coarse-graining steps (Sec. II.A: coarse-grain the
+ * bonds of one direction and truncate them), continuing the x/y alternation
+ * of earlier calls.  Asynchronous: returns once the work is enqueued.
+ * Errors: EINVAL (nsteps < 0 or the total would exceed max_steps),
+ * ESTATE (handle already failed), EHIP, EEIG (eigensolver launch failure). */
+int hotrg_coarse_grain(hotrg_solve* s, int nsteps);
+
+/* Synchronises the stream and returns ln Z / N of the torus reached so far:
+ *   ln Z/N = ln c_0 + sum_n ln(c_n) / 2^n + ln(sum_{x,y} T[x,x,y,y]) / 2^n_steps
+ * lnz_per_site receives that value, log2_sites (may be NULL) the number of
+ * steps taken (N = 2^log2_sites).  The free energy per site is
+ * -temperature * lnz_per_site.
+ * Errors: any latched device error; ENONFINITE if the final trace is <= 0. */
+int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites);
+
+/* Synchronises and reports diagnostics of step n (1..steps taken): the
+ * normalisation c_n = max|T'|, the truncation error (discarded eigenvalue
+ * weight over total weight of E) and the relative gap at the cut
+ * (lam[D'-1] - lam[D']) / lam[0] (+inf when nothing is cut).  n = 0 gives
+ * c_0 and zeros.  Any output pointer may be NULL.  Errors: EINVAL, latched. */
+int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err,
+                    double* cut_gap);
+
+/* Synchronises and copies the current normalised tensor (FP64) to host
+ * memory `host` of `capacity` doubles; dims receives {Dx, Dy} (the tensor
+ * has Dx*Dx*Dy*Dy entries, layout as above).  Errors: EINVAL (capacity too
+ * small: dims are still filled in), latched errors. */
+int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]);
+
+/* Per-stage timing with HIP events recorded on the solve's stream.
+ * hotrg_set_timing(s, 1) starts recording for the steps enqueued afterwards
+ * (it allocates the events, so call it before the timed region);
+ * hotrg_stage_times synchronises and writes the summed GPU milliseconds of
+ * each stage (HOTRG_NUM_STAGES values, indices HOTRG_STAGE_*) over the steps
+ * recorded since timing was enabled, and the number of such steps. */
+int hotrg_set_timing(hotrg_solve* s, int enable);
+int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed);
+
+/* Per-kernel timing of the Y contraction (the D^7 GEMM): summed GPU ms and
+ * launch count over the recorded steps, from events around that launch. */
+int hotrg_gemm_y_time(hotrg_solve* s, double* ms, int* launches);
+
+/* Releases the host handle and its events.  Waits for the solve's enqueued
+ * work to finish first.  The caller then frees the workspace.  NULL is a
+ * no-op. */
+void hotrg_destroy(hotrg_solve* s);
+
+/* Short description of a status code (static string). */
+const char* hotrg_strerror(int status);
+
+/* ---- device/runtime queries ------------------------------------------- */
+/* Number of visible HIP devices (0 without a GPU).  Returns HOTRG_OK. */
+int hotrg_device_count(int* count);
+/* Version of the HIP runtime this library is bound to (hipRuntimeGetVersion). */
+int hotrg_runtime_version(int* version);
+
+/* ---- contraction building block (kernel unit tests) -------------------- */
+/* Index-mapped matrix product, the one contraction kernel every step uses:
+ *   C[map(m, n)] = alpha * sum_k A[m*lda + k] * B[n*ldb + k]
+ * for 0 <= m < M, 0 <= n < N, 0 <= k < K (both operands K-contiguous).  The
+ * output map writes the fused-index target layout directly, with no
+ * separate permute (the permute-free layout of Sec. II.B, Eq. (3)):
+ *   map(m, n) = (m / sm) * rs_hi + (m % sm) * rs_lo
+ *             + (n / sn) * cs_hi + (n % sn) * cs_lo.
+ * precision selects the MFMA path (HOTRG_FP64 / HOTRG_FP32 / HOTRG_BF16X3 /
+ * HOTRG_BF16X6).  A, B and C are device pointers in FP64; for the reduced
+ * precisions the library rounds/splits the operands into an internal copy
+ * inside `scratch` (device memory of hotrg_gemm_scratch_bytes() bytes, may be
+ * NULL for HOTRG_FP64) and writes C in FP64.  Enqueued on `stream`.
+ * Errors: EINVAL (sizes < 0, NULL, sm or sn < 1), EHIP. */
+size_t hotrg_gemm_scratch_bytes(int precision, int M, int N, int K);
+int hotrg_gemm_nt(int precision, int M, int N, int K,
+                  const double* A, long lda, const double* B, long ldb,
+                  double* C, double alpha,
+                  long sm, long rs_hi, long rs_lo, long sn, long cs_hi, long cs_lo,
+                  void* scratch, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOTRG_H */

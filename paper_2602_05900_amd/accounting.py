@@ -1,0 +1,45 @@
+"""Algorithmic work of a HOTRG solve: FLOPs of the contractions per step in
+the O(D^7) order (two half environments, E, X, Y, T') and the minimum HBM
+bytes of the Y product.  The eigensolve, normalisation and trace are not
+counted (they are timed separately).  Host arithmetic only.
+"""
+from __future__ import annotations
+
+
+def step_dims(d0x: int, d0y: int, dmax: int, nsteps: int):
+    """(Dx, Dy, D') entering each step; D' = min(D, Dx^2); (Dx, Dy) <- (Dy, D')."""
+    out = []
+    dx, dy = d0x, d0y
+    for _ in range(nsteps):
+        dp = min(dmax, dx * dx)
+        out.append((dx, dy, dp))
+        dx, dy = dy, dp
+    return out
+
+
+def stage_flops(dx: int, dy: int, dp: int) -> dict:
+    return {
+        "env": 4.0 * dx**3 * dy**3 + 2.0 * dx**4 * dy**2,
+        "x": 2.0 * dp * dx**3 * dy**2,
+        "y": 2.0 * dp * dx**3 * dy**3,
+        "tp": 2.0 * dp**2 * dx**2 * dy**2,
+    }
+
+
+def step_flops(dx: int, dy: int, dp: int) -> float:
+    return sum(stage_flops(dx, dy, dp).values())
+
+
+def solve_flops(q: int, dmax: int, nsteps: int) -> float:
+    return sum(step_flops(*d) for d in step_dims(q, q, dmax, nsteps))
+
+
+def y_flops(q: int, dmax: int, nsteps: int) -> float:
+    return sum(stage_flops(*d)["y"] for d in step_dims(q, q, dmax, nsteps))
+
+
+def y_bytes(dx: int, dy: int, dp: int, elem_bytes: int) -> float:
+    """Compulsory HBM traffic of one Y product: read X (D' Dx^2 Dy^2) and the
+    re-laid-out T (Dx^2 Dy^2) once, write Y (D' Dx^2 Dy^2) once."""
+    n5 = dp * dx * dx * dy * dy
+    return float(elem_bytes) * (2 * n5 + dx * dx * dy * dy)

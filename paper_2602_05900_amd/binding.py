@@ -1,0 +1,249 @@
+"""ctypes binding of libhotrg.so (include/hotrg.h), argument marshalling only.
+
+Every step of a solve runs in the library's HIP kernels on the device; this
+module only converts Python values to C arguments and takes device memory and
+streams from PyTorch.  There is no CPU fallback: if the built library is
+missing the import of any entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads torch's HIP runtime first; the library then binds to it)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhotrg.so")
+
+# status codes
+OK, EINVAL, ENOMEM, EHIP, EEIG, ENONFINITE, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
+# models and precisions
+ISING, POTTS, CUSTOM = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+MODELS = {"ising": ISING, "potts": POTTS, "custom": CUSTOM}
+MAX_STEPS = 60
+STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm"]
+
+EXPORTS = [
+    "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain", "hotrg_log_z",
+    "hotrg_step_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
+    "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
+    "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
+]
+
+
+class HotrgError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_strerror(status)} ({status})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int),
+        ("q", ctypes.c_int),
+        ("coupling", ctypes.c_double),
+        ("temperature", ctypes.c_double),
+        ("dmax", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("custom_tensor", ctypes.POINTER(ctypes.c_double)),
+        ("custom_dx", ctypes.c_int),
+        ("custom_dy", ctypes.c_int),
+        ("max_steps", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhotrg.so (built by paper_2602_05900_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_05900_amd.build` "
+                          "(there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_size_t, c_long, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_long, ctypes.c_void_p
+    P = ctypes.POINTER
+    lib.hotrg_workspace_bytes.argtypes = [P(Params)]
+    lib.hotrg_workspace_bytes.restype = c_size_t
+    lib.hotrg_init_tensor.argtypes = [P(Params), c_void_p, c_size_t, c_void_p, P(c_void_p)]
+    lib.hotrg_reset.argtypes = [c_void_p, P(Params)]
+    lib.hotrg_coarse_grain.argtypes = [c_void_p, c_int]
+    lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
+    lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
+    lib.hotrg_copy_tensor.argtypes = [c_void_p, P(c_double), c_size_t, P(c_int)]
+    lib.hotrg_set_timing.argtypes = [c_void_p, c_int]
+    lib.hotrg_stage_times.argtypes = [c_void_p, P(c_double), P(c_int)]
+    lib.hotrg_gemm_y_time.argtypes = [c_void_p, P(c_double), P(c_int)]
+    lib.hotrg_destroy.argtypes = [c_void_p]
+    lib.hotrg_destroy.restype = None
+    lib.hotrg_strerror.argtypes = [c_int]
+    lib.hotrg_strerror.restype = ctypes.c_char_p
+    lib.hotrg_device_count.argtypes = [P(c_int)]
+    lib.hotrg_runtime_version.argtypes = [P(c_int)]
+    lib.hotrg_gemm_scratch_bytes.argtypes = [c_int, c_int, c_int, c_int]
+    lib.hotrg_gemm_scratch_bytes.restype = c_size_t
+    lib.hotrg_gemm_nt.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long,
+                                  c_void_p, c_double, c_long, c_long, c_long, c_long, c_long, c_long,
+                                  c_void_p, c_void_p]
+    for name in EXPORTS:
+        getattr(lib, name)  # every declared entry point must resolve
+    _lib = lib
+    return lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load().hotrg_strerror(status).decode()
+    except ImportError:
+        return "unknown"
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise HotrgError(status, what)
+
+
+def device_count() -> int:
+    n = ctypes.c_int(0)
+    _check(load().hotrg_device_count(ctypes.byref(n)), "hotrg_device_count")
+    return n.value
+
+
+def runtime_version() -> int:
+    v = ctypes.c_int(0)
+    _check(load().hotrg_runtime_version(ctypes.byref(v)), "hotrg_runtime_version")
+    return v.value
+
+
+def make_params(model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
+                precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0) -> tuple:
+    """hotrg_params plus the host array it points to (kept alive by the caller)."""
+    p = Params()
+    p.model = MODELS[model]
+    p.q = q
+    p.coupling = coupling
+    p.temperature = temperature
+    p.dmax = dmax
+    p.precision = PRECISIONS[precision]
+    p.max_steps = max_steps
+    keep = None
+    if model == "custom":
+        import numpy as np
+        keep = np.ascontiguousarray(tensor, dtype=np.float64)
+        if keep.ndim != 4 or keep.shape[0] != keep.shape[1] or keep.shape[2] != keep.shape[3]:
+            raise ValueError("custom tensor must have dims [Dx, Dx, Dy, Dy]")
+        p.custom_tensor = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.custom_dx, p.custom_dy = keep.shape[0], keep.shape[2]
+    return p, keep
+
+
+def workspace_bytes(**kw) -> int:
+    p, _keep = make_params(**kw)
+    return int(load().hotrg_workspace_bytes(ctypes.byref(p)))
+
+
+class Solve:
+    """One HOTRG solve on the device.  Workspace: a torch uint8 tensor of
+    hotrg_workspace_bytes(); stream: a torch.cuda.Stream (default: current)."""
+
+    def __init__(self, model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
+                 precision: str = "fp64", coupling: float = 1.0, tensor=None, stream=None,
+                 workspace=None, device="cuda", max_steps: int = 0):
+        lib = load()
+        self._lib = lib
+        p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps)
+        nbytes = lib.hotrg_workspace_bytes(ctypes.byref(p))
+        if nbytes == 0:
+            raise HotrgError(EINVAL, "hotrg_workspace_bytes")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.workspace = workspace
+        self.temperature = temperature
+        h = ctypes.c_void_p()
+        _check(lib.hotrg_init_tensor(ctypes.byref(p), ctypes.c_void_p(workspace.data_ptr()),
+                                     ctypes.c_size_t(workspace.numel()),
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+               "hotrg_init_tensor")
+        del keep
+        self._h = h
+
+    def reset(self, model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
+              precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0) -> "Solve":
+        """Restart this handle (same workspace, stream and eigensolver context)."""
+        p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps)
+        _check(self._lib.hotrg_reset(self._h, ctypes.byref(p)), "hotrg_reset")
+        del keep
+        self.temperature = temperature
+        return self
+
+    def coarse_grain(self, nsteps: int) -> "Solve":
+        _check(self._lib.hotrg_coarse_grain(self._h, int(nsteps)), "hotrg_coarse_grain")
+        return self
+
+    def log_z(self) -> float:
+        v = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(self._lib.hotrg_log_z(self._h, ctypes.byref(v), ctypes.byref(n)), "hotrg_log_z")
+        return v.value
+
+    def free_energy(self) -> float:
+        return -self.temperature * self.log_z()
+
+    def step_info(self, n: int):
+        c, e, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.hotrg_step_info(self._h, int(n), ctypes.byref(c), ctypes.byref(e), ctypes.byref(g)),
+               "hotrg_step_info")
+        return c.value, e.value, g.value
+
+    def tensor(self):
+        import numpy as np
+        dims = (ctypes.c_int * 2)()
+        self._lib.hotrg_copy_tensor(self._h, None, 0, dims)
+        dx, dy = dims[0], dims[1]
+        out = np.empty((dx, dx, dy, dy), dtype=np.float64)
+        _check(self._lib.hotrg_copy_tensor(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           out.size, dims), "hotrg_copy_tensor")
+        return out
+
+    def set_timing(self, enable: bool = True):
+        _check(self._lib.hotrg_set_timing(self._h, 1 if enable else 0), "hotrg_set_timing")
+
+    def stage_times(self):
+        ms = (ctypes.c_double * len(STAGES))()
+        n = ctypes.c_int()
+        _check(self._lib.hotrg_stage_times(self._h, ms, ctypes.byref(n)), "hotrg_stage_times")
+        return dict(zip(STAGES, list(ms))), n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hotrg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_nt(A, B, C, M, N, K, lda, ldb, out_map, precision: str = "fp64", alpha: float = 1.0, stream=None):
+    """Index-mapped product on the device (torch float64 CUDA tensors):
+    C[map(m,n)] = alpha * sum_k A[m*lda+k] B[n*ldb+k],
+    out_map = (sm, rs_hi, rs_lo, sn, cs_hi, cs_lo)."""
+    lib = load()
+    prec = PRECISIONS[precision]
+    st = stream if stream is not None else torch.cuda.current_stream(C.device)
+    nbytes = lib.hotrg_gemm_scratch_bytes(prec, M, N, K)
+    scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=C.device) if nbytes else None
+    sm, rs_hi, rs_lo, sn, cs_hi, cs_lo = out_map
+    _check(lib.hotrg_gemm_nt(prec, M, N, K, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(B.data_ptr()), ldb,
+                             ctypes.c_void_p(C.data_ptr()), alpha, sm, rs_hi, rs_lo, sn, cs_hi, cs_lo,
+                             ctypes.c_void_p(scratch.data_ptr() if scratch is not None else 0),
+                             ctypes.c_void_p(st.cuda_stream)), "hotrg_gemm_nt")
+    return scratch

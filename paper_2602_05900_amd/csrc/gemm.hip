@@ -1,0 +1,264 @@
+// Index-mapped "NT" matrix product on gfx950 matrix cores:
+//   C[map(m, n)] = alpha * sum_k A[m*lda + k] * B[n*ldb + k]
+//
+// Every contraction of a HOTRG step (half environments, E, X = U.T,
+// Y = X.T, T' = Y.U) is this one kernel with different operand strides and
+// output maps.  The output map writes each result straight into the fused-
+// index layout the next stage reads, so no contraction result is ever
+// permuted afterwards (the permute-free mapping of Sec. II.B, Eq. (3)).
+//
+// The paper's quad-tile scheme splits every index into a small in-block part
+// and a block index, multiplies all 2x2 blocks at once and then sums over the
+// K blocks (Sec. II.B, Eq. (4)).  On a CDNA4 compute unit the same split is
+// a 16x16xk MFMA fragment product per wavefront (the in-block part) and an
+// LDS-staged loop over K tiles (the block sum); workgroup tiles are spread
+// over all 256 CUs instead of over FPGA DSP slices.
+//
+// Layout: a workgroup of WAVES_M x WAVES_N wavefronts owns a BM x BN tile of
+// C; each wave owns (BM/WAVES_M) x (BN/WAVES_N) as 16x16 MFMA fragments.
+// K is consumed in BK-wide tiles, double-buffered in LDS (rows padded so the
+// 16-row fragment reads hit distinct banks), with the next tile's global
+// loads in flight while the current one is multiplied.  Tiles are assigned
+// so that the workgroups one XCD runs together share the same A rows
+// (workgroup i runs on XCD i mod 8), keeping the big operand's re-reads in
+// that XCD's L2.
+#include "common.h"
+
+namespace hotrg {
+
+// ---------------------------------------------------------------- MFMA ops
+
+template <typename T> struct Mma;
+
+template <> struct Mma<double> {
+    using acc_t = d4;
+    // v_mfma_f64_16x16x4_f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+    // the result rows interleave: D[(l/16) + 4r][l%16] is component r of lane l
+    // (measured on gfx950).
+    __device__ static acc_t run(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int group, int r) { return group + 4 * r; }
+};
+
+template <> struct Mma<float> {
+    using acc_t = f4;
+    // v_mfma_f32_16x16x4_f32: same A/B lane layout as the f64 form; the
+    // result is blocked: D[4*(l/16) + r][l%16] is component r of lane l.
+    __device__ static acc_t run(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int group, int r) { return 4 * group + r; }
+};
+
+// ---------------------------------------------------------------- stores
+
+__device__ __forceinline__ void split_store(__bf16* base, size_t plane, int nplanes, long off, float v) {
+    // v = hi + mid + lo, each rounded to nearest-even bf16 in fp32 arithmetic
+    __bf16 h = (__bf16)v;
+    base[off] = h;
+    float r = v - (float)h;
+    __bf16 m = (__bf16)r;
+    base[off + plane] = m;
+    if (nplanes == 3) {
+        float r2 = r - (float)m;
+        base[off + 2 * plane] = (__bf16)r2;
+    }
+}
+
+struct Store {
+    void* ptr;
+    size_t plane;
+    int fmt;  // Fmt
+    double alpha;
+    template <typename V>
+    __device__ __forceinline__ void operator()(long off, V v) const {
+        switch (fmt) {
+            case (int)Fmt::F64: static_cast<double*>(ptr)[off] = alpha * (double)v; break;
+            case (int)Fmt::F32: static_cast<float*>(ptr)[off] = (float)(alpha * (double)v); break;
+            case (int)Fmt::BF16x2: split_store(static_cast<__bf16*>(ptr), plane, 2, off, (float)(alpha * (double)v)); break;
+            default: split_store(static_cast<__bf16*>(ptr), plane, 3, off, (float)(alpha * (double)v)); break;
+        }
+    }
+};
+
+__device__ __forceinline__ long map_row(const OutMap& mp, unsigned m) {
+    unsigned sm = (unsigned)mp.sm;
+    unsigned hi = m / sm;
+    return (long)hi * mp.rs_hi + (long)(m - hi * sm) * mp.rs_lo;
+}
+__device__ __forceinline__ long map_col(const OutMap& mp, unsigned n) {
+    unsigned sn = (unsigned)mp.sn;
+    unsigned hi = n / sn;
+    return (long)hi * mp.cs_hi + (long)(n - hi * sn) * mp.cs_lo;
+}
+
+// ---------------------------------------------------------------- kernel
+
+template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
+void gemm_nt_kernel(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb,
+                    int M, int N, int K, Store store, OutMap mp,
+                    int tiles_m, int tiles_n, int per_xcd)
+{
+    using Op = Mma<T>;
+    using acc_t = typename Op::acc_t;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    constexpr int WM = BM / WAVES_M;
+    constexpr int WN = BN / WAVES_N;
+    constexpr int FM = WM / 16;
+    constexpr int FN = WN / 16;
+    constexpr int PAD = sizeof(T) == 8 ? 2 : 4;
+    constexpr int LDK = BK + PAD;
+    constexpr int A_PER_T = BM * BK / NT;
+    constexpr int B_PER_T = BN * BK / NT;
+    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile/threads mismatch");
+    static_assert(NT % BK == 0, "a row of the K tile must be loaded by whole thread groups");
+
+    __shared__ T As[2][BM * LDK];
+    __shared__ T Bs[2][BN * LDK];
+
+    // XCD-aware tile order: consecutive tiles (same A rows, N fastest) go to
+    // workgroups that the dispatcher places on the same XCD.
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * per_xcd + (bid >> 3);
+    if (tile >= tiles_m * tiles_n) return;
+    const int tm = tile / tiles_n;
+    const int tn = tile - tm * tiles_n;
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WAVES_N;
+    const int wn = wave - wm * WAVES_N;
+
+    // global -> register staging: element e = tid + NT*i of the tile,
+    // row e / BK, column e % BK (BK consecutive threads read one row segment)
+    const int lrow = tid / BK;
+    const int lcol = tid - lrow * BK;
+    constexpr int ROWS_PER_PASS = NT / BK;
+
+    T ra[A_PER_T], rb[B_PER_T];
+
+    auto load_tile = [&](int k0) {
+        const int k = k0 + lcol;
+        const bool kin = k < K;
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int r = m0 + lrow + i * ROWS_PER_PASS;
+            ra[i] = (kin && r < M) ? A[(long)r * lda + k] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) {
+            const int r = n0 + lrow + i * ROWS_PER_PASS;
+            rb[i] = (kin && r < N) ? B[(long)r * ldb + k] : T(0);
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) As[buf][(lrow + i * ROWS_PER_PASS) * LDK + lcol] = ra[i];
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) Bs[buf][(lrow + i * ROWS_PER_PASS) * LDK + lcol] = rb[i];
+    };
+
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    const int nk = (K + BK - 1) / BK;
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+
+    const int frow = lane & 15;   // fragment row (A) / column (B) of this lane
+    const int fk = lane >> 4;     // k offset within a 4-wide MFMA step
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_tile((kt + 1) * BK);
+        const T* as = &As[buf][(wm * WM + frow) * LDK + fk];
+        const T* bs = &Bs[buf][(wn * WN + frow) * LDK + fk];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            T a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = as[i * 16 * LDK + kk];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = bs[j * 16 * LDK + kk];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = Op::run(a[i], b[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) store_tile(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: component r of each fragment holds row Op::row(lane/16, r), column lane%16
+    long coff[FN];
+    bool cin[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn * WN + j * 16 + frow;
+        cin[j] = n < N;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm * WM + i * 16 + Op::row(fk, r);
+            if (m >= M) continue;
+            const long roff = map_row(mp, (unsigned)m);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launcher
+
+template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N>
+static hipError_t run_gemm(const T* A, long lda, const T* B, long ldb, int M, int N, int K,
+                           const Store& st, const OutMap& mp, hipStream_t stream)
+{
+    const int tiles_m = (M + BM - 1) / BM;
+    const int tiles_n = (N + BN - 1) / BN;
+    const long tiles = (long)tiles_m * tiles_n;
+    const int per_xcd = (int)((tiles + 7) / 8);
+    const long grid = 8L * per_xcd;
+    if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, BK, WAVES_M, WAVES_N>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), 0, stream,
+                       A, lda, B, ldb, M, N, K, st, mp, tiles_m, tiles_n, per_xcd);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt(const Buf& A, long lda, const Buf& B, long ldb, const Buf& C,
+                          int M, int N, int K, double alpha, const OutMap& map,
+                          int products, hipStream_t stream)
+{
+    (void)products;
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (A.fmt != B.fmt || map.sm < 1 || map.sn < 1) return hipErrorInvalidValue;
+    Store st{C.ptr, C.plane, (int)C.fmt, alpha};
+    switch (A.fmt) {
+        case Fmt::F64:
+            return run_gemm<double, 128, 128, 16, 2, 2>(static_cast<const double*>(A.ptr), lda,
+                                                        static_cast<const double*>(B.ptr), ldb,
+                                                        M, N, K, st, map, stream);
+        case Fmt::F32:
+            return run_gemm<float, 128, 128, 32, 2, 2>(static_cast<const float*>(A.ptr), lda,
+                                                       static_cast<const float*>(B.ptr), ldb,
+                                                       M, N, K, st, map, stream);
+        default:
+            return hipErrorNotSupported;
+    }
+}
+
+}  // namespace hotrg

@@ -1,0 +1,630 @@
+// Host engine of the HOTRG library: parameter checking, workspace carving,
+// the per-step launch schedule on the caller's stream, the FP64 eigensolve,
+// and the C ABI declared in include/hotrg.h.
+//
+// One step on T[l,r,d,u] with dims [Dx,Dx,Dy,Dy], D' = min(D, Dx^2)
+// (Sec. II.A: merge two tensors along one direction, truncate the fused bond
+// by the decomposition the higher-order SVD reduces to):
+//   P1 = T as [(l,u),(r,d)]           (re-layout, D^4)
+//   P2 = T as [(l,d),(r,u)]           (re-layout, D^4)
+//   Ah[a1,b1,k,k'] = P1 P1^T          (half environment of the bottom copy)
+//   Bh[a2,b2,k,k'] = P2 P2^T          (half environment of the top copy)
+//   E[(a1a2),(b1b2)] = Ah Bh^T        (= M M^T, M never formed), symmetrised
+//   E = V diag(w) V^T  (FP64)         -> U = leading D' columns, sign-fixed
+//   P3 = T as [(d,r,u), l]; X[l,d,r1,a2,k] = Ux P3^T            (K = Dx)
+//   P4 = T as [(u,r), (l,d)]; Y[l,d,u,r1,r2] = X P4^T            (K = Dx Dy, the D^7 term)
+//   T'[d,u,l,r] = Y Ut^T  (written already x<->y exchanged)      (K = Dx^2)
+//   c_n = max|T'|, T' /= c_n, ln Z accumulator += ln(c_n) / 2^n
+// All products are the one index-mapped MFMA kernel (gemm.hip).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include "../../include/hotrg.h"
+#include "common.h"
+
+using namespace hotrg;
+
+namespace {
+
+constexpr int kMaxQ = 16;
+constexpr int kEventsPerStep = 10;
+
+struct StepDims {
+    int dx, dy, dp;
+};
+
+std::vector<StepDims> trajectory(int dx, int dy, int dmax, int nsteps) {
+    std::vector<StepDims> t;
+    t.reserve(nsteps);
+    for (int i = 0; i < nsteps; ++i) {
+        const int dp = std::min<long>(dmax, (long)dx * dx);
+        t.push_back({dx, dy, dp});
+        const int nx = dy;
+        dy = dp;
+        dx = nx;
+    }
+    return t;
+}
+
+Fmt fmt_of(int prec) {
+    switch (prec) {
+        case HOTRG_FP32: return Fmt::F32;
+        case HOTRG_BF16X3: return Fmt::BF16x2;
+        case HOTRG_BF16X6: return Fmt::BF16x3;
+        default: return Fmt::F64;
+    }
+}
+
+int products_of(int prec) { return prec == HOTRG_BF16X3 ? 3 : (prec == HOTRG_BF16X6 ? 6 : 1); }
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// bytes of a buffer of `count` elements in format f (planes 64-element aligned)
+size_t buf_bytes(Fmt f, size_t count) {
+    return (size_t)fmt_planes(f) * round_up(std::max<size_t>(count, 1), 64) * fmt_plane_elem_bytes(f);
+}
+
+struct Layout {
+    size_t nT = 0, nP = 0, nAB = 0, nE = 0, nW = 0, nU = 0, nX = 0;
+    size_t oState, oT, oPa, oPb, oAh, oBh, oE, oW, oEoff, oInfo, oUt, oUx, oX, oY, total;
+};
+
+int step_cap(const hotrg_params* p) { return p->max_steps > 0 ? p->max_steps : HOTRG_MAX_STEPS; }
+
+bool valid_params(const hotrg_params* p) {
+    if (!p) return false;
+    if (p->max_steps < 0 || p->max_steps > HOTRG_MAX_STEPS) return false;
+    if (p->dmax < 1 || p->dmax > HOTRG_MAX_DIM) return false;
+    if (p->precision < HOTRG_FP64 || p->precision > HOTRG_BF16X6) return false;
+    if (p->model == HOTRG_ISING) {
+        if (p->q != 2) return false;
+    } else if (p->model == HOTRG_POTTS) {
+        if (p->q < 2 || p->q > kMaxQ) return false;
+    } else if (p->model == HOTRG_CUSTOM) {
+        if (!p->custom_tensor) return false;
+        if (p->custom_dx < 1 || p->custom_dx > HOTRG_MAX_DIM) return false;
+        if (p->custom_dy < 1 || p->custom_dy > HOTRG_MAX_DIM) return false;
+        return true;
+    } else {
+        return false;
+    }
+    if (!(p->temperature > 0.0) || !isfinite(p->temperature)) return false;
+    if (!(p->coupling > 0.0) || !isfinite(p->coupling)) return false;
+    return true;
+}
+
+void initial_dims(const hotrg_params* p, int* dx, int* dy) {
+    if (p->model == HOTRG_CUSTOM) {
+        *dx = p->custom_dx;
+        *dy = p->custom_dy;
+    } else {
+        *dx = *dy = p->q;
+    }
+}
+
+Layout plan(const hotrg_params* p) {
+    Layout L;
+    int dx, dy;
+    initial_dims(p, &dx, &dy);
+    L.nT = (size_t)dx * dx * dy * dy;
+    for (const StepDims& s : trajectory(dx, dy, p->dmax, step_cap(p))) {
+        const size_t x = s.dx, y = s.dy, dp = s.dp;
+        L.nT = std::max(L.nT, std::max(x * x * y * y, y * y * dp * dp));
+        L.nP = std::max(L.nP, x * x * y * y);
+        L.nAB = std::max(L.nAB, x * x * y * y);
+        L.nE = std::max(L.nE, x * x * x * x);
+        L.nW = std::max(L.nW, x * x);
+        L.nU = std::max(L.nU, dp * x * x);
+        L.nX = std::max(L.nX, dp * x * x * y * y);
+    }
+    const Fmt f = fmt_of(p->precision);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = round_up(o + bytes, 256);
+        return at;
+    };
+    L.oState = take(sizeof(DevState));
+    L.oT = take(buf_bytes(Fmt::F64, L.nT));
+    L.oPa = take(buf_bytes(f, L.nP));
+    L.oPb = take(buf_bytes(f, L.nP));
+    L.oAh = take(buf_bytes(f, L.nAB));
+    L.oBh = take(buf_bytes(f, L.nAB));
+    L.oE = take(buf_bytes(Fmt::F64, L.nE));
+    L.oW = take(buf_bytes(Fmt::F64, L.nW));
+    L.oEoff = take(buf_bytes(Fmt::F64, L.nW));
+    L.oInfo = take(sizeof(int) * 64);
+    L.oUt = take(buf_bytes(f, L.nU));
+    L.oUx = take(buf_bytes(f, L.nU));
+    L.oX = take(buf_bytes(f, L.nX));
+    L.oY = take(buf_bytes(f, L.nX));
+    L.total = o;
+    return L;
+}
+
+Buf make_buf(char* base, size_t off, Fmt f, size_t count) {
+    return Buf{base + off, f, round_up(std::max<size_t>(count, 1), 64)};
+}
+
+// T0[x,x',y,y'] = sum_s Q[s,x]Q[s,x']Q[s,y]Q[s,y'], Q = W^(1/2).  W = a I + b 1 1^T
+// for both models (Ising: a = 2 sinh(beta J), b = exp(-beta J); Potts:
+// a = exp(beta J) - 1, b = 1), so Q = sqrt(a) I + (sqrt(a + q b) - sqrt(a)) / q 1 1^T.
+std::vector<double> model_tensor(const hotrg_params* p) {
+    const int q = p->q;
+    const double bj = p->coupling / p->temperature;
+    double a, b;
+    if (p->model == HOTRG_ISING) {
+        a = 2.0 * sinh(bj);
+        b = exp(-bj);
+    } else {
+        a = expm1(bj);
+        b = 1.0;
+    }
+    const double sa = sqrt(a);
+    const double off = (sqrt(a + q * b) - sa) / q;
+    std::vector<double> Q((size_t)q * q);
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) Q[(size_t)i * q + j] = off + (i == j ? sa : 0.0);
+    std::vector<double> T((size_t)q * q * q * q, 0.0);
+    for (int x = 0; x < q; ++x)
+        for (int xp = 0; xp < q; ++xp)
+            for (int y = 0; y < q; ++y)
+                for (int yp = 0; yp < q; ++yp) {
+                    double s = 0.0;
+                    for (int k = 0; k < q; ++k)
+                        s += Q[(size_t)k * q + x] * Q[(size_t)k * q + xp] * Q[(size_t)k * q + y] * Q[(size_t)k * q + yp];
+                    T[(((size_t)x * q + xp) * q + y) * q + yp] = s;
+                }
+    return T;
+}
+
+}  // namespace
+
+struct hotrg_solve {
+    hotrg_params p;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L;
+    Fmt fmt = Fmt::F64;
+    int products = 1;
+    int dx = 0, dy = 0, steps = 0;
+    int host_status = HOTRG_OK;
+    rocblas_handle rb = nullptr;
+    void* eig_ws = nullptr;
+    size_t eig_ws_bytes = 0;
+    bool timing = false;
+    int timed_from = 0;  // first step recorded with events
+    std::vector<hipEvent_t> ev;
+
+    DevState* state() const { return reinterpret_cast<DevState*>(ws + L.oState); }
+    double* T() const { return reinterpret_cast<double*>(ws + L.oT); }
+};
+
+#define HIP_TRY(s, x)                                  \
+    do {                                               \
+        if ((x) != hipSuccess) {                       \
+            if ((s)) (s)->host_status = HOTRG_EHIP;    \
+            return HOTRG_EHIP;                         \
+        }                                              \
+    } while (0)
+
+namespace {
+
+int read_state(hotrg_solve* s, DevState* out) {
+    HIP_TRY(s, hipMemcpyAsync(out, s->state(), sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return HOTRG_OK;
+}
+
+void record(hotrg_solve* s, int step_index, int slot) {
+    if (!s->timing) return;
+    const int i = step_index - s->timed_from;
+    if (i < 0 || (size_t)((i + 1) * kEventsPerStep) > s->ev.size()) return;
+    (void)hipEventRecord(s->ev[(size_t)i * kEventsPerStep + slot], s->stream);
+}
+
+int gemm(hotrg_solve* s, const Buf& A, long lda, const Buf& B, long ldb, const Buf& C, int M, int N, int K,
+         const OutMap& mp) {
+    HIP_TRY(s, launch_gemm_nt(A, lda, B, ldb, C, M, N, K, 1.0, mp, s->products, s->stream));
+    return HOTRG_OK;
+}
+
+int enqueue_step(hotrg_solve* s) {
+    const int n = s->steps + 1;       // 1-based step number
+    const int Dx = s->dx, Dy = s->dy;
+    const int Dp = (int)std::min<long>(s->p.dmax, (long)Dx * Dx);
+    const int nE = Dx * Dx;
+    const Fmt f = s->fmt;
+    const Layout& L = s->L;
+    char* w = s->ws;
+    const Buf Pa = make_buf(w, L.oPa, f, L.nP), Pb = make_buf(w, L.oPb, f, L.nP);
+    const Buf Ah = make_buf(w, L.oAh, f, L.nAB), Bh = make_buf(w, L.oBh, f, L.nAB);
+    const Buf Ut = make_buf(w, L.oUt, f, L.nU), Ux = make_buf(w, L.oUx, f, L.nU);
+    const Buf X = make_buf(w, L.oX, f, L.nX), Y = make_buf(w, L.oY, f, L.nX);
+    double* E = reinterpret_cast<double*>(w + L.oE);
+    double* W = reinterpret_cast<double*>(w + L.oW);
+    double* Eoff = reinterpret_cast<double*>(w + L.oEoff);
+    int* info = reinterpret_cast<int*>(w + L.oInfo) + (n < 64 ? n : 63);
+    const Buf Ebuf{E, Fmt::F64, 0};
+    const Buf Tbuf{s->T(), Fmt::F64, 0};
+    const int dims[4] = {Dx, Dx, Dy, Dy};
+    const int step_index = s->steps;
+    int rc;
+
+    // -- half environments and E
+    record(s, step_index, 0);
+    {
+        const int p1[4] = {0, 3, 1, 2};  // P1[l,u,r,d]
+        const int p2[4] = {0, 2, 1, 3};  // P2[l,d,r,u]
+        HIP_TRY(s, launch_permute4(s->T(), dims, p1, Pa, s->stream));
+        HIP_TRY(s, launch_permute4(s->T(), dims, p2, Pb, s->stream));
+    }
+    record(s, step_index, 1);
+    {
+        const int m = Dx * Dy;
+        const OutMap half{Dy, (long)Dx * Dy * Dy, Dy, Dy, (long)Dy * Dy, 1};  // -> [a,b,k,k']
+        if ((rc = gemm(s, Pa, m, Pa, m, Ah, m, m, m, half))) return rc;
+        if ((rc = gemm(s, Pb, m, Pb, m, Bh, m, m, m, half))) return rc;
+        const OutMap env{Dx, (long)Dx * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};  // -> E[(a1a2),(b1b2)]
+        if ((rc = gemm(s, Ah, (long)Dy * Dy, Bh, (long)Dy * Dy, Ebuf, nE, nE, Dy * Dy, env))) return rc;
+        HIP_TRY(s, launch_symmetrize(E, nE, s->stream));
+    }
+    record(s, step_index, 2);
+    // -- FP64 eigensolve and isometry
+    {
+        rocblas_status st = rocsolver_dsyevd(s->rb, rocblas_evect_original, rocblas_fill_upper, nE, E, nE, W,
+                                             Eoff, info);
+        if (st != rocblas_status_success) {
+            s->host_status = HOTRG_EEIG;
+            return HOTRG_EEIG;
+        }
+        HIP_TRY(s, launch_select_isometry(E, W, info, nE, Dx, Dp, Ut, Ux, s->state(), n, s->stream));
+    }
+    record(s, step_index, 3);
+    // -- X = U . T  -> X[l,d,r1,a2,k]
+    {
+        const int p3[4] = {2, 1, 3, 0};  // P3[d,r,u,l]
+        HIP_TRY(s, launch_permute4(s->T(), dims, p3, Pa, s->stream));
+    }
+    record(s, step_index, 4);
+    {
+        const OutMap xm{Dx, (long)Dy * Dx * Dx * Dy, Dy, Dy, (long)Dx * Dy, 1};
+        if ((rc = gemm(s, Ux, Dx, Pa, Dx, X, Dp * Dx, Dy * Dx * Dy, Dx, xm))) return rc;
+    }
+    record(s, step_index, 5);
+    // -- Y = X . T  -> Y[l,d,u,r1,r2]
+    {
+        const int p4[4] = {3, 1, 0, 2};  // P4[u,r,l,d]
+        HIP_TRY(s, launch_permute4(s->T(), dims, p4, Pb, s->stream));
+    }
+    record(s, step_index, 6);
+    {
+        const OutMap ym{Dx, (long)Dy * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};
+        if ((rc = gemm(s, X, (long)Dx * Dy, Pb, (long)Dx * Dy, Y, Dp * Dy * Dx, Dy * Dx, Dx * Dy, ym))) return rc;
+    }
+    record(s, step_index, 7);
+    // -- T' = Y . U  -> next T[d,u,l,r] (x <-> y exchanged), FP64
+    {
+        const OutMap tm{(long)Dy * Dy, Dp, (long)Dp * Dp, Dp, 0, 1};
+        if ((rc = gemm(s, Y, (long)Dx * Dx, Ut, (long)Dx * Dx, Tbuf, Dp * Dy * Dy, Dp, Dx * Dx, tm))) return rc;
+    }
+    record(s, step_index, 8);
+    HIP_TRY(s, launch_normalize(s->T(), (size_t)Dy * Dy * Dp * Dp, s->state(), n, s->stream));
+    record(s, step_index, 9);
+    s->dx = Dy;
+    s->dy = Dp;
+    s->steps = n;
+    return HOTRG_OK;
+}
+
+// Builds T0 for p on the host, normalises it by c_0 = max|T0|, uploads it and
+// a fresh device state (ln Z accumulator = ln c_0), and resets the step count.
+int upload_initial(hotrg_solve* s, const hotrg_params* p) {
+    initial_dims(p, &s->dx, &s->dy);
+    s->steps = 0;
+    s->timed_from = 0;
+    std::vector<double> T0;
+    if (p->model == HOTRG_CUSTOM) {
+        T0.assign(p->custom_tensor, p->custom_tensor + (size_t)s->dx * s->dx * s->dy * s->dy);
+    } else {
+        T0 = model_tensor(p);
+    }
+    double c0 = 0.0;
+    for (double v : T0) c0 = std::max(c0, fabs(v));
+    if (!(c0 > 0.0) || !isfinite(c0)) return HOTRG_ENONFINITE;
+    for (double& v : T0) v /= c0;
+    std::vector<char> hs(sizeof(DevState), 0);
+    DevState* h = reinterpret_cast<DevState*>(hs.data());
+    h->lnz_acc = log(c0);
+    h->c[0] = c0;
+    h->c_cur = c0;
+    if (hipMemcpyAsync(s->state(), h, sizeof(DevState), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->T(), T0.data(), T0.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return HOTRG_EHIP;
+    return HOTRG_OK;
+}
+
+// Largest eigensolver workspace over the environments n = Dx^2 of the solve.
+size_t eig_workspace_need(hotrg_solve* s, const hotrg_params* p) {
+    int dx, dy;
+    initial_dims(p, &dx, &dy);
+    std::vector<int> ns;
+    for (const StepDims& d : trajectory(dx, dy, p->dmax, step_cap(p))) ns.push_back(d.dx * d.dx);
+    std::sort(ns.begin(), ns.end());
+    ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+    size_t need = 0;
+    const Layout& L = s->L;
+    for (int n : ns) {
+        size_t sz = 0;
+        rocblas_start_device_memory_size_query(s->rb);
+        // the query validates its pointer arguments but does not touch them
+        rocsolver_dsyevd(s->rb, rocblas_evect_original, rocblas_fill_upper, n,
+                         reinterpret_cast<double*>(s->ws + L.oE), n, reinterpret_cast<double*>(s->ws + L.oW),
+                         reinterpret_cast<double*>(s->ws + L.oEoff), reinterpret_cast<int*>(s->ws + L.oInfo));
+        rocblas_stop_device_memory_size_query(s->rb, &sz);
+        need = std::max(need, sz);
+    }
+    return need;
+}
+
+int latched(const DevState& d) { return d.status; }
+
+}  // namespace
+
+extern "C" {
+
+size_t hotrg_workspace_bytes(const hotrg_params* p) {
+    if (!valid_params(p)) return 0;
+    return plan(p).total;
+}
+
+int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes, void* stream, hotrg_solve** out) {
+    if (!out) return HOTRG_EINVAL;
+    *out = nullptr;
+    if (!valid_params(p) || !workspace || ((uintptr_t)workspace & 255u)) return HOTRG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HOTRG_ENODEV;
+    const Layout L = plan(p);
+    if (ws_bytes < L.total) return HOTRG_ENOMEM;
+
+    hotrg_solve* s = new (std::nothrow) hotrg_solve();
+    if (!s) return HOTRG_EINVAL;
+    s->p = *p;
+    s->p.custom_tensor = nullptr;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->ws = static_cast<char*>(workspace);
+    s->ws_bytes = ws_bytes;
+    s->L = L;
+    s->fmt = fmt_of(p->precision);
+    s->products = products_of(p->precision);
+    initial_dims(p, &s->dx, &s->dy);
+
+    int rc = upload_initial(s, p);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+
+    // Eigensolver context bound to the caller's stream, with its device
+    // workspace sized once, here, for the largest environment of the solve.
+    if (rocblas_create_handle(&s->rb) != rocblas_status_success) {
+        delete s;
+        return HOTRG_EEIG;
+    }
+    rocblas_set_stream(s->rb, s->stream);
+    const size_t need = eig_workspace_need(s, p);
+    if (need > 0) {
+        if (hipMalloc(&s->eig_ws, need) != hipSuccess) {
+            rocblas_destroy_handle(s->rb);
+            delete s;
+            return HOTRG_EHIP;
+        }
+        s->eig_ws_bytes = need;
+        rocblas_set_workspace(s->rb, s->eig_ws, need);
+    }
+    *out = s;
+    return HOTRG_OK;
+}
+
+int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
+    if (!s || !valid_params(p)) return HOTRG_EINVAL;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return HOTRG_EHIP;
+    const Layout L = plan(p);
+    if (L.total > s->ws_bytes) return HOTRG_ENOMEM;
+    const Layout old = s->L;
+    s->L = L;
+    if (eig_workspace_need(s, p) > s->eig_ws_bytes) {
+        s->L = old;
+        return HOTRG_ENOMEM;
+    }
+    s->p = *p;
+    s->p.custom_tensor = nullptr;
+    s->fmt = fmt_of(p->precision);
+    s->products = products_of(p->precision);
+    s->host_status = HOTRG_OK;
+    return upload_initial(s, p);
+}
+
+int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
+    if (!s || nsteps < 0) return HOTRG_EINVAL;
+    if (s->host_status) return HOTRG_ESTATE;
+    if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
+    for (int i = 0; i < nsteps; ++i) {
+        const int rc = enqueue_step(s);
+        if (rc) return rc;
+    }
+    return HOTRG_OK;
+}
+
+int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites) {
+    if (!s || !lnz_per_site) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    HIP_TRY(s, launch_trace(s->T(), s->dx, s->dy, s->state(), s->stream));
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    if (!(d.trace > 0.0) || !isfinite(d.trace)) return HOTRG_ENONFINITE;
+    *lnz_per_site = d.lnz_acc + log(d.trace) * ldexp(1.0, -s->steps);
+    if (log2_sites) *log2_sites = s->steps;
+    return HOTRG_OK;
+}
+
+int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err, double* cut_gap) {
+    if (!s || n < 0 || n > s->steps) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    if (c_n) *c_n = d.c[n];
+    if (trunc_err) *trunc_err = n ? d.trunc_err[n] : 0.0;
+    if (cut_gap) *cut_gap = n ? d.cut_gap[n] : 0.0;
+    return HOTRG_OK;
+}
+
+int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]) {
+    if (!s || !dims) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    dims[0] = s->dx;
+    dims[1] = s->dy;
+    const size_t count = (size_t)s->dx * s->dx * s->dy * s->dy;
+    if (!host || capacity < count) return HOTRG_EINVAL;
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    HIP_TRY(s, hipMemcpyAsync(host, s->T(), count * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return HOTRG_OK;
+}
+
+int hotrg_set_timing(hotrg_solve* s, int enable) {
+    if (!s) return HOTRG_EINVAL;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    s->ev.clear();
+    s->timing = enable != 0;
+    s->timed_from = s->steps;
+    if (s->timing) {
+        const int n = (HOTRG_MAX_STEPS - s->steps) * kEventsPerStep;
+        s->ev.resize(n);
+        for (int i = 0; i < n; ++i) HIP_TRY(s, hipEventCreate(&s->ev[i]));
+    }
+    return HOTRG_OK;
+}
+
+static float elapsed(hotrg_solve* s, int step, int a, int b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, s->ev[(size_t)step * kEventsPerStep + a], s->ev[(size_t)step * kEventsPerStep + b]);
+    return ms;
+}
+
+int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed) {
+    if (!s || !ms) return HOTRG_EINVAL;
+    for (int i = 0; i < HOTRG_NUM_STAGES; ++i) ms[i] = 0.0;
+    const int nt = s->timing ? s->steps - s->timed_from : 0;
+    if (steps_timed) *steps_timed = nt;
+    if (!nt) return HOTRG_OK;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    for (int i = 0; i < nt; ++i) {
+        ms[HOTRG_STAGE_PERMUTE] += elapsed(s, i, 0, 1) + elapsed(s, i, 3, 4) + elapsed(s, i, 5, 6);
+        ms[HOTRG_STAGE_ENV] += elapsed(s, i, 1, 2);
+        ms[HOTRG_STAGE_EIG] += elapsed(s, i, 2, 3);
+        ms[HOTRG_STAGE_X] += elapsed(s, i, 4, 5);
+        ms[HOTRG_STAGE_Y] += elapsed(s, i, 6, 7);
+        ms[HOTRG_STAGE_TP] += elapsed(s, i, 7, 8);
+        ms[HOTRG_STAGE_NORM] += elapsed(s, i, 8, 9);
+    }
+    return HOTRG_OK;
+}
+
+int hotrg_gemm_y_time(hotrg_solve* s, double* ms, int* launches) {
+    if (!s || !ms) return HOTRG_EINVAL;
+    double st[HOTRG_NUM_STAGES];
+    int nt = 0;
+    const int rc = hotrg_stage_times(s, st, &nt);
+    if (rc) return rc;
+    *ms = st[HOTRG_STAGE_Y];
+    if (launches) *launches = nt;
+    return HOTRG_OK;
+}
+
+void hotrg_destroy(hotrg_solve* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->rb) rocblas_destroy_handle(s->rb);
+    if (s->eig_ws) (void)hipFree(s->eig_ws);
+    delete s;
+}
+
+const char* hotrg_strerror(int status) {
+    switch (status) {
+        case HOTRG_OK: return "ok";
+        case HOTRG_EINVAL: return "invalid argument";
+        case HOTRG_ENOMEM: return "workspace too small";
+        case HOTRG_EHIP: return "HIP runtime error";
+        case HOTRG_EEIG: return "eigensolver failure";
+        case HOTRG_ENONFINITE: return "non-finite or non-positive normalisation";
+        case HOTRG_ESTATE: return "handle in failed state";
+        case HOTRG_ENODEV: return "no HIP device";
+        default: return "unknown status";
+    }
+}
+
+int hotrg_device_count(int* count) {
+    if (!count) return HOTRG_EINVAL;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) n = 0;
+    *count = n;
+    return HOTRG_OK;
+}
+
+int hotrg_runtime_version(int* version) {
+    if (!version) return HOTRG_EINVAL;
+    return hipRuntimeGetVersion(version) == hipSuccess ? HOTRG_OK : HOTRG_EHIP;
+}
+
+size_t hotrg_gemm_scratch_bytes(int precision, int M, int N, int K) {
+    if (M < 0 || N < 0 || K < 0) return 0;
+    if (precision == HOTRG_FP64) return 0;
+    const Fmt f = fmt_of(precision);
+    return round_up(buf_bytes(f, (size_t)M * K), 256) + buf_bytes(f, (size_t)N * K);
+}
+
+int hotrg_gemm_nt(int precision, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
+                  double* C, double alpha, long sm, long rs_hi, long rs_lo, long sn, long cs_hi, long cs_lo,
+                  void* scratch, void* stream) {
+    if (M < 0 || N < 0 || K < 0 || sm < 1 || sn < 1 || !C) return HOTRG_EINVAL;
+    if (precision < HOTRG_FP64 || precision > HOTRG_BF16X6) return HOTRG_EINVAL;
+    if (K > 0 && (!A || !B || lda < K || ldb < K)) return HOTRG_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const OutMap mp{sm, rs_hi, rs_lo, sn, cs_hi, cs_lo};
+    const Buf Cb{C, Fmt::F64, 0};
+    if (precision == HOTRG_FP64) {
+        const Buf Ab{const_cast<double*>(A), Fmt::F64, 0}, Bb{const_cast<double*>(B), Fmt::F64, 0};
+        return launch_gemm_nt(Ab, lda, Bb, ldb, Cb, M, N, K, alpha, mp, 1, st) == hipSuccess ? HOTRG_OK : HOTRG_EHIP;
+    }
+    if (!scratch || ((uintptr_t)scratch & 255u)) return HOTRG_EINVAL;
+    const Fmt f = fmt_of(precision);
+    char* base = static_cast<char*>(scratch);
+    const Buf Ab = make_buf(base, 0, f, (size_t)M * K);
+    const Buf Bb = make_buf(base, round_up(buf_bytes(f, (size_t)M * K), 256), f, (size_t)N * K);
+    if (launch_convert2d(A, lda, M, K, Ab, st) != hipSuccess) return HOTRG_EHIP;
+    if (launch_convert2d(B, ldb, N, K, Bb, st) != hipSuccess) return HOTRG_EHIP;
+    return launch_gemm_nt(Ab, K, Bb, K, Cb, M, N, K, alpha, mp, products_of(precision), st) == hipSuccess
+               ? HOTRG_OK
+               : HOTRG_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,274 @@
+// Small D^4-sized kernels of a HOTRG step: operand re-layouts of T, the
+// max-abs normalisation with ln Z accumulation, the final trace, the
+// symmetrisation of E and the selection of the truncation isometry from the
+// eigensolver output.  None of them is on the D^7 path; they are written
+// for coalesced stores and deterministic (order-fixed) reductions.
+#include <math.h>
+#include "common.h"
+#include "../../include/hotrg.h"
+
+namespace hotrg {
+
+// ---------------------------------------------------------------- stores
+
+__device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
+    switch (o.fmt) {
+        case Fmt::F64: static_cast<double*>(o.ptr)[idx] = v; break;
+        case Fmt::F32: static_cast<float*>(o.ptr)[idx] = (float)v; break;
+        default: {
+            __bf16* p = static_cast<__bf16*>(o.ptr);
+            const float f = (float)v;
+            const __bf16 h = (__bf16)f;
+            p[idx] = h;
+            const float r = f - (float)h;
+            const __bf16 m = (__bf16)r;
+            p[idx + o.plane] = m;
+            if (o.fmt == Fmt::BF16x3) p[idx + 2 * o.plane] = (__bf16)(r - (float)m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- permute
+
+struct Perm4 {
+    int od[4];     // output dims
+    long is[4];    // input stride of the input axis feeding each output axis
+};
+
+__global__ void permute4_kernel(const double* __restrict__ in, Perm4 p, Buf out, size_t total) {
+    size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; o < total; o += stride) {
+        size_t t = o;
+        const int j3 = (int)(t % p.od[3]); t /= p.od[3];
+        const int j2 = (int)(t % p.od[2]); t /= p.od[2];
+        const int j1 = (int)(t % p.od[1]); t /= p.od[1];
+        const int j0 = (int)t;
+        const long src = j0 * p.is[0] + j1 * p.is[1] + j2 * p.is[2] + j3 * p.is[3];
+        put(out, o, in[src]);
+    }
+}
+
+hipError_t launch_permute4(const double* in, const int dims[4], const int perm[4],
+                           const Buf& out, hipStream_t stream) {
+    long st[4];
+    st[3] = 1;
+    st[2] = dims[3];
+    st[1] = (long)dims[2] * dims[3];
+    st[0] = (long)dims[1] * dims[2] * dims[3];
+    Perm4 p;
+    size_t total = 1;
+    for (int a = 0; a < 4; ++a) {
+        p.od[a] = dims[perm[a]];
+        p.is[a] = st[perm[a]];
+        total *= (size_t)p.od[a];
+    }
+    if (total == 0) return hipSuccess;
+    const int threads = 256;
+    size_t blocks = (total + threads - 1) / threads;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(permute4_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, in, p, out, total);
+    return hipGetLastError();
+}
+
+__global__ void convert2d_kernel(const double* __restrict__ in, long ld, int rows, int cols, Buf out) {
+    const size_t total = (size_t)rows * cols;
+    for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total; o += (size_t)gridDim.x * blockDim.x) {
+        const size_t r = o / cols, c = o - (o / cols) * cols;
+        put(out, o, in[r * ld + c]);
+    }
+}
+
+hipError_t launch_convert2d(const double* in, long ld, int rows, int cols, const Buf& out,
+                            hipStream_t stream) {
+    const size_t total = (size_t)rows * cols;
+    if (total == 0) return hipSuccess;
+    size_t blocks = (total + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(convert2d_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, in, ld, rows, cols, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+
+template <int NT>
+__device__ double block_max(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] = fmax(sh[tid], sh[tid + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] = sh[tid] + sh[tid + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+constexpr int RED_BLOCKS = 1024;  // == size of DevState::partial
+
+__global__ __launch_bounds__(256) void absmax_partial_kernel(const double* __restrict__ T, size_t count, DevState* st) {
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256)
+        m = fmax(m, fabs(T[i]));
+    m = block_max<256>(m, sh);
+    if (threadIdx.x == 0) st->partial[blockIdx.x] = m;
+}
+
+// One block: c_n = max of the partials; latch an error if c_n is not a
+// positive finite number; accumulate ln(c_n) / 2^n.  Single-thread stores.
+__global__ __launch_bounds__(256) void norm_finalize_kernel(DevState* st, int nblocks, int n) {
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += 256) m = fmax(m, st->partial[i]);
+    m = block_max<256>(m, sh);
+    if (threadIdx.x == 0) {
+        const bool ok = (m > 0.0) && isfinite(m);
+        if (!ok && st->status == 0) st->status = HOTRG_ENONFINITE;
+        st->c_cur = ok ? m : 1.0;
+        if (n < 64) st->c[n] = m;
+        if (ok) st->lnz_acc += log(m) * ldexp(1.0, -n);
+    }
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(double* __restrict__ T, size_t count, const DevState* st) {
+    const double c = st->c_cur;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256)
+        T[i] = T[i] / c;
+}
+
+hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStream_t stream) {
+    size_t nb = (count + 255) / 256;
+    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(absmax_partial_kernel, dim3((unsigned)nb), dim3(256), 0, stream, T, count, st);
+    hipLaunchKernelGGL(norm_finalize_kernel, dim3(1), dim3(256), 0, stream, st, (int)nb, n);
+    size_t sb = (count + 255) / 256;
+    if (sb > 8192) sb = 8192;
+    if (sb < 1) sb = 1;
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)sb), dim3(256), 0, stream, T, count, st);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void trace_kernel(const double* __restrict__ T, int Dx, int Dy, DevState* st) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    const int total = Dx * Dy;
+    for (int i = threadIdx.x; i < total; i += 256) {
+        const int x = i / Dy, y = i - (i / Dy) * Dy;
+        s += T[(((long)x * Dx + x) * Dy + y) * Dy + y];
+    }
+    s = block_sum<256>(s, sh);
+    if (threadIdx.x == 0) st->trace = s;
+}
+
+hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream) {
+    hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, stream, T, Dx, Dy, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- E symmetrisation
+
+__global__ void symmetrize_kernel(double* __restrict__ E, int n) {
+    // one thread per (i, j) with i < j, as 16x16 blocks of the upper triangle
+    const int i = blockIdx.y * 16 + threadIdx.y;
+    const int j = blockIdx.x * 16 + threadIdx.x;
+    if (i < n && j < n && i < j) {
+        const double v = 0.5 * (E[(long)i * n + j] + E[(long)j * n + i]);
+        E[(long)i * n + j] = v;
+        E[(long)j * n + i] = v;
+    }
+}
+
+hipError_t launch_symmetrize(double* E, int n, hipStream_t stream) {
+    const unsigned b = (unsigned)((n + 15) / 16);
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(b, b), dim3(16, 16), 0, stream, E, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- isometry
+
+// One block per kept column l.
+__global__ __launch_bounds__(256) void select_isometry_kernel(const double* __restrict__ V, int n, int dx, int kept,
+                                                              Buf Ut, Buf Ux) {
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    const int l = blockIdx.x;
+    const double* v = V + (long)(n - 1 - l) * n;  // descending order
+    // argmax |v[i]|, lowest index among equal magnitudes
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double a = fabs(v[i]);
+        if (a > best) { best = a; bi = i; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double a = sv[threadIdx.x + s];
+            const int ia = si[threadIdx.x + s];
+            if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ia < si[threadIdx.x])) {
+                sv[threadIdx.x] = a;
+                si[threadIdx.x] = ia;
+            }
+        }
+        __syncthreads();
+    }
+    const double sgn = v[si[0]] < 0.0 ? -1.0 : 1.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const double u = sgn * v[i];
+        put(Ut, (size_t)l * n + i, u);
+        const int a1 = i / dx, a2 = i - (i / dx) * dx;
+        put(Ux, ((size_t)l * dx + a2) * dx + a1, u);
+    }
+}
+
+// One block: truncation error and cut gap from the ascending eigenvalues,
+// eigensolver status.  Sums in a fixed order.
+__global__ __launch_bounds__(256) void eig_stats_kernel(const double* __restrict__ w, const int* info, int n, int kept,
+                                                        DevState* st, int step) {
+    __shared__ double sh[256];
+    double tot = 0.0, dis = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        tot += w[i];
+        if (i < n - kept) dis += w[i];   // ascending: the n - kept smallest are discarded
+    }
+    tot = block_sum<256>(tot, sh);
+    dis = block_sum<256>(dis, sh);
+    if (threadIdx.x == 0) {
+        const int inf = *info;
+        if (step < 64) {
+            st->info[step] = inf;
+            st->trunc_err[step] = tot != 0.0 ? dis / tot : 0.0;
+            st->cut_gap[step] = kept < n ? (w[n - kept] - w[n - kept - 1]) / w[n - 1] : INFINITY;
+        }
+        if (inf != 0 && st->status == 0) st->status = HOTRG_EEIG;
+    }
+}
+
+hipError_t launch_select_isometry(const double* V, const double* w, const int* info, int n, int dx,
+                                  int kept, const Buf& Ut, const Buf& Ux, DevState* st, int step,
+                                  hipStream_t stream) {
+    hipLaunchKernelGGL(select_isometry_kernel, dim3(kept), dim3(256), 0, stream, V, n, dx, kept, Ut, Ux);
+    hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(256), 0, stream, w, info, n, kept, st, step);
+    return hipGetLastError();
+}
+
+}  // namespace hotrg

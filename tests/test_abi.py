@@ -1,0 +1,96 @@
+"""CPU checks of the C ABI: the header is valid C, the library loads without a
+GPU and exports every function include/hotrg.h declares, and the host-only
+entry points (workspace sizing, parameter validation, strings) behave."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hotrg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hotrg_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2602_05900_amd import binding, build
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    return binding.load()
+
+
+def test_header_is_plain_c():
+    src = '#include "hotrg.h"\nint main(void) { hotrg_params p; (void)p; return HOTRG_OK; }\n'
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.dirname(HEADER),
+                            "-c", c, "-o", os.path.join(d, "t.o")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def test_every_declared_function_is_exported(lib):
+    names = declared_functions()
+    assert "hotrg_init_tensor" in names and "hotrg_coarse_grain" in names and "hotrg_log_z" in names
+    from paper_2602_05900_amd import binding
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.EXPORTS)
+
+
+def test_params_struct_matches_header(lib):
+    from paper_2602_05900_amd import binding
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "hotrg.h"\n'
+           'int main(void){printf("%zu %zu %zu\\n", sizeof(hotrg_params), '
+           'offsetof(hotrg_params, custom_tensor), offsetof(hotrg_params, max_steps));return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        size, off_t, off_m = (int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split())
+    assert ctypes.sizeof(binding.Params) == size
+    assert binding.Params.custom_tensor.offset == off_t
+    assert binding.Params.max_steps.offset == off_m
+
+
+def test_workspace_sizing_and_validation(lib):
+    from paper_2602_05900_amd import binding
+    ws48 = binding.workspace_bytes(model="ising", q=2, temperature=2.0, dmax=48, max_steps=30)
+    # two D^5 FP64 intermediates dominate: 2 * 48^5 * 8 bytes
+    assert 2 * 48 ** 5 * 8 < ws48 < 2.2 * 48 ** 5 * 8
+    assert binding.workspace_bytes(model="ising", q=2, temperature=2.0, dmax=48, precision="fp32") < ws48
+    # D^5 scaling of the footprint
+    ws24 = binding.workspace_bytes(model="ising", q=2, temperature=2.0, dmax=24)
+    assert 20 < ws48 / ws24 < 40
+    # invalid parameter sets give 0
+    assert binding.workspace_bytes(model="ising", q=3, temperature=2.0, dmax=8) == 0
+    assert binding.workspace_bytes(model="ising", q=2, temperature=-1.0, dmax=8) == 0
+    assert binding.workspace_bytes(model="potts", q=3, temperature=1.0, dmax=0) == 0
+    assert binding.workspace_bytes(model="potts", q=3, temperature=1.0, dmax=8, max_steps=61) == 0
+    # few steps at a large D need less than a long solve
+    assert (binding.workspace_bytes(model="potts", q=3, temperature=1.0, dmax=81, max_steps=4)
+            < binding.workspace_bytes(model="potts", q=3, temperature=1.0, dmax=81, max_steps=10))
+
+
+def test_host_error_paths_without_device(lib):
+    from paper_2602_05900_amd import binding
+    p, _ = binding.make_params(model="ising", q=2, temperature=2.0, dmax=8)
+    h = ctypes.c_void_p()
+    assert lib.hotrg_init_tensor(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == binding.EINVAL
+    assert lib.hotrg_init_tensor(None, None, 0, None, ctypes.byref(h)) == binding.EINVAL
+    assert lib.hotrg_coarse_grain(None, 1) == binding.EINVAL
+    v = ctypes.c_double()
+    assert lib.hotrg_log_z(None, ctypes.byref(v), None) == binding.EINVAL
+    lib.hotrg_destroy(None)
+    assert lib.hotrg_strerror(binding.ENOMEM) == b"workspace too small"
+    assert lib.hotrg_gemm_scratch_bytes(binding.FP64, 10, 10, 10) == 0
+    assert lib.hotrg_gemm_scratch_bytes(binding.BF16X6, 10, 10, 10) > 0
