@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--dmax", type=int, default=48)
     ap.add_argument("--nsteps", type=int, default=30, help="coarse-graining steps per solve")
-    ap.add_argument("--cpu-sample-steps", type=int, default=7)
+    ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -172,6 +172,7 @@ def main():
             "traffic": None,
             "algorithmic_flops_per_solve": y_flops,
             "launches": args.nsteps * args.steps,
+            "avg_launch_ms": y_ms / (args.nsteps * args.steps),
         },
         "lnz_per_site": {f"{T:.6f}": v for T, v in results},
     }

@@ -39,12 +39,15 @@ struct OutMap {
     long sn, cs_hi, cs_lo;
 };
 
+// Which contraction of a step a product is (selects tiles; distinct symbols).
+enum class GemmRole : int { Generic = 0, X = 1, Y = 2, TP = 3 };
+
 // C[map(m,n)] = alpha * sum_k A[m*lda + k] * B[n*ldb + k].
 // A, B: operand buffers (same format); C: output buffer (any format).
 // `products` selects the split-product count for the bf16 formats (3 or 6).
 hipError_t launch_gemm_nt(const Buf& A, long lda, const Buf& B, long ldb, const Buf& C,
                           int M, int N, int K, double alpha, const OutMap& map,
-                          int products, hipStream_t stream);
+                          int products, GemmRole role, hipStream_t stream);
 
 // out[j0,j1,j2,j3] = in[...] with out axis a taken from input axis perm[a];
 // in has dims (n0,n1,n2,n3) row-major, FP64.  Output in any format.

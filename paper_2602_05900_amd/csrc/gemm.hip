@@ -95,7 +95,9 @@ __device__ __forceinline__ long map_col(const OutMap& mp, unsigned n) {
 
 // ---------------------------------------------------------------- kernel
 
-template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N>
+// ROLE only gives each contraction of a step its own kernel symbol (so a
+// profiler separates them); the code is the same.
+template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int ROLE>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
 void gemm_nt_kernel(const T* __restrict__ A, long lda, const T* __restrict__ B, long ldb,
                     int M, int N, int K, Store store, OutMap mp,
@@ -223,7 +225,7 @@ void gemm_nt_kernel(const T* __restrict__ A, long lda, const T* __restrict__ B, 
 
 // ---------------------------------------------------------------- launcher
 
-template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N>
+template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int ROLE>
 static hipError_t run_gemm(const T* A, long lda, const T* B, long ldb, int M, int N, int K,
                            const Store& st, const OutMap& mp, hipStream_t stream)
 {
@@ -233,31 +235,43 @@ static hipError_t run_gemm(const T* A, long lda, const T* B, long ldb, int M, in
     const int per_xcd = (int)((tiles + 7) / 8);
     const long grid = 8L * per_xcd;
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, BK, WAVES_M, WAVES_N>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, BK, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream,
                        A, lda, B, ldb, M, N, K, st, mp, tiles_m, tiles_n, per_xcd);
     return hipGetLastError();
 }
 
+template <int ROLE>
+static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
+                           const Store& st, const OutMap& map, hipStream_t stream)
+{
+    switch (A.fmt) {
+        case Fmt::F64:
+            return run_gemm<double, 128, 128, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
+                                                              static_cast<const double*>(B.ptr), ldb,
+                                                              M, N, K, st, map, stream);
+        case Fmt::F32:
+            return run_gemm<float, 128, 128, 32, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
+                                                             static_cast<const float*>(B.ptr), ldb,
+                                                             M, N, K, st, map, stream);
+        default:
+            return hipErrorNotSupported;
+    }
+}
+
 hipError_t launch_gemm_nt(const Buf& A, long lda, const Buf& B, long ldb, const Buf& C,
                           int M, int N, int K, double alpha, const OutMap& map,
-                          int products, hipStream_t stream)
+                          int products, GemmRole role, hipStream_t stream)
 {
     (void)products;
     if (M <= 0 || N <= 0) return hipSuccess;
     if (A.fmt != B.fmt || map.sm < 1 || map.sn < 1) return hipErrorInvalidValue;
     Store st{C.ptr, C.plane, (int)C.fmt, alpha};
-    switch (A.fmt) {
-        case Fmt::F64:
-            return run_gemm<double, 128, 128, 16, 2, 2>(static_cast<const double*>(A.ptr), lda,
-                                                        static_cast<const double*>(B.ptr), ldb,
-                                                        M, N, K, st, map, stream);
-        case Fmt::F32:
-            return run_gemm<float, 128, 128, 32, 2, 2>(static_cast<const float*>(A.ptr), lda,
-                                                       static_cast<const float*>(B.ptr), ldb,
-                                                       M, N, K, st, map, stream);
-        default:
-            return hipErrorNotSupported;
+    switch (role) {
+        case GemmRole::X: return dispatch<1>(A, lda, B, ldb, M, N, K, st, map, stream);
+        case GemmRole::Y: return dispatch<2>(A, lda, B, ldb, M, N, K, st, map, stream);
+        case GemmRole::TP: return dispatch<3>(A, lda, B, ldb, M, N, K, st, map, stream);
+        default: return dispatch<0>(A, lda, B, ldb, M, N, K, st, map, stream);
     }
 }
 

@@ -232,8 +232,8 @@ void record(hotrg_solve* s, int step_index, int slot) {
 }
 
 int gemm(hotrg_solve* s, const Buf& A, long lda, const Buf& B, long ldb, const Buf& C, int M, int N, int K,
-         const OutMap& mp) {
-    HIP_TRY(s, launch_gemm_nt(A, lda, B, ldb, C, M, N, K, 1.0, mp, s->products, s->stream));
+         const OutMap& mp, GemmRole role = GemmRole::Generic) {
+    HIP_TRY(s, launch_gemm_nt(A, lda, B, ldb, C, M, N, K, 1.0, mp, s->products, role, s->stream));
     return HOTRG_OK;
 }
 
@@ -297,7 +297,7 @@ int enqueue_step(hotrg_solve* s) {
     record(s, step_index, 4);
     {
         const OutMap xm{Dx, (long)Dy * Dx * Dx * Dy, Dy, Dy, (long)Dx * Dy, 1};
-        if ((rc = gemm(s, Ux, Dx, Pa, Dx, X, Dp * Dx, Dy * Dx * Dy, Dx, xm))) return rc;
+        if ((rc = gemm(s, Ux, Dx, Pa, Dx, X, Dp * Dx, Dy * Dx * Dy, Dx, xm, GemmRole::X))) return rc;
     }
     record(s, step_index, 5);
     // -- Y = X . T  -> Y[l,d,u,r1,r2]
@@ -308,13 +308,15 @@ int enqueue_step(hotrg_solve* s) {
     record(s, step_index, 6);
     {
         const OutMap ym{Dx, (long)Dy * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};
-        if ((rc = gemm(s, X, (long)Dx * Dy, Pb, (long)Dx * Dy, Y, Dp * Dy * Dx, Dy * Dx, Dx * Dy, ym))) return rc;
+        if ((rc = gemm(s, X, (long)Dx * Dy, Pb, (long)Dx * Dy, Y, Dp * Dy * Dx, Dy * Dx, Dx * Dy, ym, GemmRole::Y)))
+            return rc;
     }
     record(s, step_index, 7);
     // -- T' = Y . U  -> next T[d,u,l,r] (x <-> y exchanged), FP64
     {
         const OutMap tm{(long)Dy * Dy, Dp, (long)Dp * Dp, Dp, 0, 1};
-        if ((rc = gemm(s, Y, (long)Dx * Dx, Ut, (long)Dx * Dx, Tbuf, Dp * Dy * Dy, Dp, Dx * Dx, tm))) return rc;
+        if ((rc = gemm(s, Y, (long)Dx * Dx, Ut, (long)Dx * Dx, Tbuf, Dp * Dy * Dy, Dp, Dx * Dx, tm, GemmRole::TP)))
+            return rc;
     }
     record(s, step_index, 8);
     HIP_TRY(s, launch_normalize(s->T(), (size_t)Dy * Dy * Dp * Dp, s->state(), n, s->stream));
@@ -613,7 +615,9 @@ int hotrg_gemm_nt(int precision, int M, int N, int K, const double* A, long lda,
     const Buf Cb{C, Fmt::F64, 0};
     if (precision == HOTRG_FP64) {
         const Buf Ab{const_cast<double*>(A), Fmt::F64, 0}, Bb{const_cast<double*>(B), Fmt::F64, 0};
-        return launch_gemm_nt(Ab, lda, Bb, ldb, Cb, M, N, K, alpha, mp, 1, st) == hipSuccess ? HOTRG_OK : HOTRG_EHIP;
+        return launch_gemm_nt(Ab, lda, Bb, ldb, Cb, M, N, K, alpha, mp, 1, GemmRole::Generic, st) == hipSuccess
+                   ? HOTRG_OK
+                   : HOTRG_EHIP;
     }
     if (!scratch || ((uintptr_t)scratch & 255u)) return HOTRG_EINVAL;
     const Fmt f = fmt_of(precision);
@@ -622,7 +626,8 @@ int hotrg_gemm_nt(int precision, int M, int N, int K, const double* A, long lda,
     const Buf Bb = make_buf(base, round_up(buf_bytes(f, (size_t)M * K), 256), f, (size_t)N * K);
     if (launch_convert2d(A, lda, M, K, Ab, st) != hipSuccess) return HOTRG_EHIP;
     if (launch_convert2d(B, ldb, N, K, Bb, st) != hipSuccess) return HOTRG_EHIP;
-    return launch_gemm_nt(Ab, K, Bb, K, Cb, M, N, K, alpha, mp, products_of(precision), st) == hipSuccess
+    return launch_gemm_nt(Ab, K, Bb, K, Cb, M, N, K, alpha, mp, products_of(precision), GemmRole::Generic, st) ==
+                   hipSuccess
                ? HOTRG_OK
                : HOTRG_EHIP;
 }
