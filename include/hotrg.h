@@ -24,8 +24,16 @@
  * Memory and streams: the caller owns the device workspace (one allocation
  * of hotrg_workspace_bytes(), e.g. a torch uint8 tensor) and the HIP stream;
  * every kernel of a solve is enqueued on that stream and nothing is
- * allocated on the device per step.  The library owns only the host handle,
- * its events and the eigensolver context, which it creates at init.
+ * allocated on the device per step.  The library owns only the host handle
+ * and its timing events.
+ *
+ * The truncation eigensolve (FP64) runs on the device: environments up to
+ * 96 x 96 are diagonalised completely by a parallel two-sided Jacobi method
+ * (the 2x2-block rotation scheme of Sec. II.B, Eqs. (5)-(6)); larger ones by
+ * a block subspace iteration with Rayleigh-Ritz projection (the small
+ * projected problem again by that Jacobi method), warm-started from the
+ * isometry of the step two earlier, until the kept Ritz pairs have relative
+ * residual <= 1e-12 (at most 30 passes).
  *
  * Errors: every int-returning call returns HOTRG_OK (0) or a negative
  * status.  Errors detected on the device (non-finite or non-positive c_n, a
@@ -49,7 +57,7 @@ extern "C" {
 #define HOTRG_EINVAL     -1  /* invalid argument or parameter set           */
 #define HOTRG_ENOMEM     -2  /* workspace smaller than hotrg_workspace_bytes */
 #define HOTRG_EHIP       -3  /* a HIP runtime call failed                    */
-#define HOTRG_EEIG       -4  /* the FP64 eigensolve reported failure         */
+#define HOTRG_EEIG       -4  /* eigensolve not possible for these parameters  */
 #define HOTRG_ENONFINITE -5  /* c_n or the final trace not finite or <= 0    */
 #define HOTRG_ESTATE     -6  /* call not valid in the handle's state         */
 #define HOTRG_ENODEV     -7  /* no HIP device                                */
@@ -112,25 +120,25 @@ size_t hotrg_workspace_bytes(const hotrg_params* p);
  * the symmetric square root of the bond Boltzmann weight matrix; T0 is
  * normalised by c_0 = max|T0| and ln c_0 starts the ln Z accumulator.  T0
  * and the device state are copied on the stream, which init synchronises.
- * Errors: EINVAL (parameters, NULL pointers, misaligned workspace),
- * ENOMEM (ws_bytes too small), ENODEV, EHIP. */
+ * Errors: EINVAL (parameters, NULL pointers, misaligned workspace, or a
+ * bond dimension too large for the eigensolver's Ritz block: every step
+ * with Dx^2 > 96 needs D' < 96), ENOMEM (ws_bytes too small), ENODEV, EHIP. */
 int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes,
                       void* stream, hotrg_solve** out);
 
 /* Restarts an existing handle on a new parameter set (a new temperature,
  * model or bond dimension) without creating a new one: the initial tensor is
  * rebuilt exactly as in hotrg_init_tensor, the step count and the device
- * status are cleared, and the handle's workspace, eigensolver context and
- * timing events are kept.  Synchronises the handle's stream first.
- * Errors: EINVAL (parameters), ENOMEM (the handle's workspace or eigensolver
- * context is too small for p: create a new handle instead), EHIP. */
+ * status are cleared, and the handle's workspace and timing events are kept.  Synchronises the handle's stream first.
+ * Errors: EINVAL (parameters), ENOMEM (the handle's workspace is too small
+ * for p: create a new handle instead), EHIP. */
 int hotrg_reset(hotrg_solve* s, const hotrg_params* p);
 
 /* Enqueues nsteps >= 0 coarse-graining steps (Sec. II.A: coarse-grain the
  * bonds of one direction and truncate them), continuing the x/y alternation
  * of earlier calls.  Asynchronous: returns once the work is enqueued.
  * Errors: EINVAL (nsteps < 0 or the total would exceed max_steps),
- * ESTATE (handle already failed), EHIP, EEIG (eigensolver launch failure). */
+ * ESTATE (handle already failed), EHIP. */
 int hotrg_coarse_grain(hotrg_solve* s, int nsteps);
 
 /* Synchronises the stream and returns ln Z / N of the torus reached so far:
@@ -148,6 +156,13 @@ int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites);
  * c_0 and zeros.  Any output pointer may be NULL.  Errors: EINVAL, latched. */
 int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err,
                     double* cut_gap);
+
+/* Synchronises and reports the eigensolve of step n (1..steps taken):
+ * iterations = subspace passes used (0 when E was diagonalised densely),
+ * sweeps = Jacobi sweeps of the last projected problem, residual =
+ * max_j |E u_j - theta_j u_j| / theta_0 over the kept pairs (0 when dense).
+ * Any output pointer may be NULL.  Errors: EINVAL, latched. */
+int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual);
 
 /* Synchronises and copies the current normalised tensor (FP64) to host
  * memory `host` of `capacity` doubles; dims receives {Dx, Dy} (the tensor

@@ -27,7 +27,7 @@ STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm"]
 
 EXPORTS = [
     "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain", "hotrg_log_z",
-    "hotrg_step_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
+    "hotrg_step_info", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
 ]
@@ -75,6 +75,7 @@ def load() -> ctypes.CDLL:
     lib.hotrg_coarse_grain.argtypes = [c_void_p, c_int]
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
+    lib.hotrg_eig_info.argtypes = [c_void_p, c_int, P(c_int), P(c_int), P(c_double)]
     lib.hotrg_copy_tensor.argtypes = [c_void_p, P(c_double), c_size_t, P(c_int)]
     lib.hotrg_set_timing.argtypes = [c_void_p, c_int]
     lib.hotrg_stage_times.argtypes = [c_void_p, P(c_double), P(c_int)]
@@ -200,6 +201,13 @@ class Solve:
         _check(self._lib.hotrg_step_info(self._h, int(n), ctypes.byref(c), ctypes.byref(e), ctypes.byref(g)),
                "hotrg_step_info")
         return c.value, e.value, g.value
+
+    def eig_info(self, n: int):
+        """(subspace passes, Jacobi sweeps, relative residual) of step n's eigensolve."""
+        it, sw, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self._lib.hotrg_eig_info(self._h, int(n), ctypes.byref(it), ctypes.byref(sw), ctypes.byref(r)),
+               "hotrg_eig_info")
+        return it.value, sw.value, r.value
 
     def tensor(self):
         import numpy as np

@@ -1,9 +1,9 @@
 """Build the HOTRG HIP library in-tree: paper_2602_05900_amd/libhotrg.so.
 
 Every source is compiled for gfx950 with hipcc and linked against the HIP
-runtime, rocBLAS and rocSOLVER that PyTorch ships, so a process that has
-imported torch holds exactly one HIP runtime (loading the system ROCm runtime
-beside torch's would put two in one process).
+runtime that PyTorch ships, so a process that has imported torch holds
+exactly one HIP runtime (loading the system ROCm runtime beside torch's would
+put two in one process).  No other ROCm library is linked.
 
     python -m paper_2602_05900_amd.build
 """
@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhotrg.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["gemm.hip", "tensor_ops.hip", "hotrg.cpp"]
+SOURCES = ["gemm.hip", "tensor_ops.hip", "eig.hip", "hotrg.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -68,7 +68,7 @@ def build(verbose: bool = False) -> str:
     clang = os.path.join(ROCM, "llvm", "bin", "clang++")
     tmp = LIB + ".tmp"
     _run([clang, "-shared", "-fPIC", "-o", tmp, *objs,
-          "-L", tlib, "-l:libamdhip64.so", "-l:librocsolver.so", "-l:librocblas.so",
+          "-L", tlib, "-l:libamdhip64.so",
           f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined", "-lstdc++", "-lm"], verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -64,9 +64,53 @@ struct DevState {
     double c[64];
     double trunc_err[64];
     double cut_gap[64];
-    int info[64];         // eigensolver info per step
+    int info[64];         // eigensolver iterations per step (0: dense Jacobi of E)
+    int eig_sweeps[64];   // Jacobi sweeps of the last Rayleigh-Ritz problem per step
+    double eig_resid[64]; // max residual / theta_0 of the kept Ritz pairs per step
     double partial[1024]; // partial maxima of the normalisation reduction
 };
+
+// Device control block of one eigensolve.
+struct EigCtl {
+    int done;        // set once the kept Ritz pairs have converged (or the last pass ran)
+    int iters;       // subspace passes used
+    int converged;   // 1 if the residual test passed
+    int sweeps;      // Jacobi sweeps of the last small eigenproblem
+    double resid;    // max_j |E u_j - theta_j u_j| / theta_0 over the kept pairs
+    double trace;    // Tr E
+};
+
+constexpr int kEigPMax = 96;   // largest Ritz block / largest fully diagonalised E
+
+// Device buffers of the eigensolver (FP64), carved from the workspace.
+struct EigWork {
+    double* V[2];    // Ritz blocks, n x p row-major, one per step parity (warm starts)
+    double* W;       // n x p
+    double* part;    // partial Gram blocks, ceil(n/32) x (kEigPMax^2 + kEigPMax)
+    double* G;       // reduced Gram (+ residuals), kEigPMax^2 + kEigPMax
+    double* S;       // Jacobi eigenvectors, kEigPMax^2
+    double* theta;   // Ritz values, kEigPMax
+    double* L;       // Cholesky factor, kEigPMax^2
+    double* dsc;     // column scales, kEigPMax
+    EigCtl* ctl;
+};
+
+// Ritz block width for an n x n environment keeping k vectors (n > kEigPMax).
+inline int eig_block(int n, int k) {
+    int p = 2 * k > k + 16 ? 2 * k : k + 16;
+    p = (p + 15) / 16 * 16;
+    if (p > kEigPMax) p = kEigPMax;
+    if (p > n) p = n;
+    return p;
+}
+
+// Leading k eigenpairs of the symmetric n x n matrix E (FP64), written as the
+// isometry Ut / Ux (see launch_select_isometry) with the sign gauge; step
+// diagnostics into st.  warm: V[parity] already holds the Ritz block of the
+// step two earlier with the same (n, p).
+hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
+                           unsigned long long seed, int maxit, double tol, const Buf& Ut, const Buf& Ux,
+                           DevState* st, int step, hipStream_t stream);
 
 // Normalisation of step n: c_n = max|T|, T /= c_n, lnz_acc += ln(c_n) / 2^n.
 hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStream_t stream);
@@ -74,16 +118,6 @@ hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStr
 hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream);
 // E <- (E + E^T) / 2 for an n x n matrix.
 hipError_t launch_symmetrize(double* E, int n, hipStream_t stream);
-// From the eigensolver output (eigenvalues ascending in w; eigenvector j in
-// column j of the column-major V, leading dimension n) take the leading kept
-// eigenvectors in descending order, fix each sign so its largest-magnitude
-// entry (lowest index on ties) is positive, and write
-//   Ut[l, i]             = u_l[i]                (kept x n, isometry rows)
-//   Ux[l, a2, a1]        = u_l[a1 * dx + a2]     (kept x dx x dx)
-// Records truncation error, cut gap and eigensolver status of step n.
-hipError_t launch_select_isometry(const double* V, const double* w, const int* info, int n, int dx,
-                                  int kept, const Buf& Ut, const Buf& Ux, DevState* st, int step,
-                                  hipStream_t stream);
 
 }  // namespace hotrg
 

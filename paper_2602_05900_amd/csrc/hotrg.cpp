@@ -10,7 +10,7 @@
 //   Ah[a1,b1,k,k'] = P1 P1^T          (half environment of the bottom copy)
 //   Bh[a2,b2,k,k'] = P2 P2^T          (half environment of the top copy)
 //   E[(a1a2),(b1b2)] = Ah Bh^T        (= M M^T, M never formed), symmetrised
-//   E = V diag(w) V^T  (FP64)         -> U = leading D' columns, sign-fixed
+//   E u_j = lambda_j u_j (FP64, eig.hip) -> U = leading D' eigenvectors, sign-fixed
 //   P3 = T as [(d,r,u), l]; X[l,d,r1,a2,k] = Ux P3^T            (K = Dx)
 //   P4 = T as [(u,r), (l,d)]; Y[l,d,u,r1,r2] = X P4^T            (K = Dx Dy, the D^7 term)
 //   T'[d,u,l,r] = Y Ut^T  (written already x<->y exchanged)      (K = Dx^2)
@@ -22,9 +22,6 @@
 #include <algorithm>
 #include <new>
 #include <vector>
-
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include "../../include/hotrg.h"
 #include "common.h"
@@ -72,9 +69,13 @@ size_t buf_bytes(Fmt f, size_t count) {
 }
 
 struct Layout {
-    size_t nT = 0, nP = 0, nAB = 0, nE = 0, nW = 0, nU = 0, nX = 0;
-    size_t oState, oT, oPa, oPb, oAh, oBh, oE, oW, oEoff, oInfo, oUt, oUx, oX, oY, total;
+    size_t nT = 0, nP = 0, nAB = 0, nE = 0, nU = 0, nX = 0, nEig = 0;
+    size_t oState, oT, oPa, oPb, oAh, oBh, oE, oEigV0, oEigV1, oEigW, oEigPart, oEigG, oEigS, oEigTheta, oEigL,
+        oEigD, oEigCtl, oUt, oUx, oX, oY, total;
 };
+
+constexpr double kEigTol = 1e-12;
+constexpr int kEigMaxIt = 30;
 
 int step_cap(const hotrg_params* p) { return p->max_steps > 0 ? p->max_steps : HOTRG_MAX_STEPS; }
 
@@ -100,6 +101,12 @@ bool valid_params(const hotrg_params* p) {
     return true;
 }
 
+void initial_dims(const hotrg_params* p, int* dx, int* dy);
+
+// Every step whose environment is too large to diagonalise densely needs a
+// Ritz block wider than the kept count.
+bool eig_feasible(const hotrg_params* p);
+
 void initial_dims(const hotrg_params* p, int* dx, int* dy) {
     if (p->model == HOTRG_CUSTOM) {
         *dx = p->custom_dx;
@@ -107,6 +114,16 @@ void initial_dims(const hotrg_params* p, int* dx, int* dy) {
     } else {
         *dx = *dy = p->q;
     }
+}
+
+bool eig_feasible(const hotrg_params* p) {
+    int dx, dy;
+    initial_dims(p, &dx, &dy);
+    for (const StepDims& s : trajectory(dx, dy, p->dmax, step_cap(p))) {
+        const int n = s.dx * s.dx;
+        if (n > kEigPMax && eig_block(n, s.dp) <= s.dp) return false;
+    }
+    return true;
 }
 
 Layout plan(const hotrg_params* p) {
@@ -120,7 +137,7 @@ Layout plan(const hotrg_params* p) {
         L.nP = std::max(L.nP, x * x * y * y);
         L.nAB = std::max(L.nAB, x * x * y * y);
         L.nE = std::max(L.nE, x * x * x * x);
-        L.nW = std::max(L.nW, x * x);
+        if (x * x > (size_t)kEigPMax) L.nEig = std::max(L.nEig, x * x);
         L.nU = std::max(L.nU, dp * x * x);
         L.nX = std::max(L.nX, dp * x * x * y * y);
     }
@@ -138,9 +155,17 @@ Layout plan(const hotrg_params* p) {
     L.oAh = take(buf_bytes(f, L.nAB));
     L.oBh = take(buf_bytes(f, L.nAB));
     L.oE = take(buf_bytes(Fmt::F64, L.nE));
-    L.oW = take(buf_bytes(Fmt::F64, L.nW));
-    L.oEoff = take(buf_bytes(Fmt::F64, L.nW));
-    L.oInfo = take(sizeof(int) * 64);
+    const size_t pb = (size_t)kEigPMax;
+    L.oEigV0 = take(8 * L.nEig * pb);
+    L.oEigV1 = take(8 * L.nEig * pb);
+    L.oEigW = take(8 * L.nEig * pb);
+    L.oEigPart = take(8 * ((L.nEig + 31) / 32) * (pb * pb + pb));
+    L.oEigG = take(8 * (pb * pb + pb));
+    L.oEigS = take(8 * pb * pb);
+    L.oEigTheta = take(8 * pb);
+    L.oEigL = take(8 * pb * pb);
+    L.oEigD = take(8 * pb);
+    L.oEigCtl = take(sizeof(EigCtl));
     L.oUt = take(buf_bytes(f, L.nU));
     L.oUx = take(buf_bytes(f, L.nU));
     L.oX = take(buf_bytes(f, L.nX));
@@ -197,14 +222,27 @@ struct hotrg_solve {
     int products = 1;
     int dx = 0, dy = 0, steps = 0;
     int host_status = HOTRG_OK;
-    rocblas_handle rb = nullptr;
-    void* eig_ws = nullptr;
-    size_t eig_ws_bytes = 0;
+    int warm_n[2] = {0, 0};   // (n, p) of the Ritz block kept per step parity
+    int warm_p[2] = {0, 0};
     bool timing = false;
     int timed_from = 0;  // first step recorded with events
     std::vector<hipEvent_t> ev;
 
     DevState* state() const { return reinterpret_cast<DevState*>(ws + L.oState); }
+    EigWork eig() const {
+        EigWork w;
+        w.V[0] = reinterpret_cast<double*>(ws + L.oEigV0);
+        w.V[1] = reinterpret_cast<double*>(ws + L.oEigV1);
+        w.W = reinterpret_cast<double*>(ws + L.oEigW);
+        w.part = reinterpret_cast<double*>(ws + L.oEigPart);
+        w.G = reinterpret_cast<double*>(ws + L.oEigG);
+        w.S = reinterpret_cast<double*>(ws + L.oEigS);
+        w.theta = reinterpret_cast<double*>(ws + L.oEigTheta);
+        w.L = reinterpret_cast<double*>(ws + L.oEigL);
+        w.dsc = reinterpret_cast<double*>(ws + L.oEigD);
+        w.ctl = reinterpret_cast<EigCtl*>(ws + L.oEigCtl);
+        return w;
+    }
     double* T() const { return reinterpret_cast<double*>(ws + L.oT); }
 };
 
@@ -250,9 +288,6 @@ int enqueue_step(hotrg_solve* s) {
     const Buf Ut = make_buf(w, L.oUt, f, L.nU), Ux = make_buf(w, L.oUx, f, L.nU);
     const Buf X = make_buf(w, L.oX, f, L.nX), Y = make_buf(w, L.oY, f, L.nX);
     double* E = reinterpret_cast<double*>(w + L.oE);
-    double* W = reinterpret_cast<double*>(w + L.oW);
-    double* Eoff = reinterpret_cast<double*>(w + L.oEoff);
-    int* info = reinterpret_cast<int*>(w + L.oInfo) + (n < 64 ? n : 63);
     const Buf Ebuf{E, Fmt::F64, 0};
     const Buf Tbuf{s->T(), Fmt::F64, 0};
     const int dims[4] = {Dx, Dx, Dy, Dy};
@@ -280,13 +315,16 @@ int enqueue_step(hotrg_solve* s) {
     record(s, step_index, 2);
     // -- FP64 eigensolve and isometry
     {
-        rocblas_status st = rocsolver_dsyevd(s->rb, rocblas_evect_original, rocblas_fill_upper, nE, E, nE, W,
-                                             Eoff, info);
-        if (st != rocblas_status_success) {
-            s->host_status = HOTRG_EEIG;
-            return HOTRG_EEIG;
+        const int par = step_index & 1;
+        const int pblk = nE > kEigPMax ? eig_block(nE, Dp) : nE;
+        const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;
+        const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)n;
+        HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, kEigMaxIt, kEigTol, Ut, Ux,
+                                   s->state(), n, s->stream));
+        if (nE > kEigPMax) {
+            s->warm_n[par] = nE;
+            s->warm_p[par] = pblk;
         }
-        HIP_TRY(s, launch_select_isometry(E, W, info, nE, Dx, Dp, Ut, Ux, s->state(), n, s->stream));
     }
     record(s, step_index, 3);
     // -- X = U . T  -> X[l,d,r1,a2,k]
@@ -333,6 +371,8 @@ int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     initial_dims(p, &s->dx, &s->dy);
     s->steps = 0;
     s->timed_from = 0;
+    s->warm_n[0] = s->warm_n[1] = 0;
+    s->warm_p[0] = s->warm_p[1] = 0;
     std::vector<double> T0;
     if (p->model == HOTRG_CUSTOM) {
         T0.assign(p->custom_tensor, p->custom_tensor + (size_t)s->dx * s->dx * s->dy * s->dy);
@@ -355,29 +395,6 @@ int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     return HOTRG_OK;
 }
 
-// Largest eigensolver workspace over the environments n = Dx^2 of the solve.
-size_t eig_workspace_need(hotrg_solve* s, const hotrg_params* p) {
-    int dx, dy;
-    initial_dims(p, &dx, &dy);
-    std::vector<int> ns;
-    for (const StepDims& d : trajectory(dx, dy, p->dmax, step_cap(p))) ns.push_back(d.dx * d.dx);
-    std::sort(ns.begin(), ns.end());
-    ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
-    size_t need = 0;
-    const Layout& L = s->L;
-    for (int n : ns) {
-        size_t sz = 0;
-        rocblas_start_device_memory_size_query(s->rb);
-        // the query validates its pointer arguments but does not touch them
-        rocsolver_dsyevd(s->rb, rocblas_evect_original, rocblas_fill_upper, n,
-                         reinterpret_cast<double*>(s->ws + L.oE), n, reinterpret_cast<double*>(s->ws + L.oW),
-                         reinterpret_cast<double*>(s->ws + L.oEoff), reinterpret_cast<int*>(s->ws + L.oInfo));
-        rocblas_stop_device_memory_size_query(s->rb, &sz);
-        need = std::max(need, sz);
-    }
-    return need;
-}
-
 int latched(const DevState& d) { return d.status; }
 
 }  // namespace
@@ -385,14 +402,14 @@ int latched(const DevState& d) { return d.status; }
 extern "C" {
 
 size_t hotrg_workspace_bytes(const hotrg_params* p) {
-    if (!valid_params(p)) return 0;
+    if (!valid_params(p) || !eig_feasible(p)) return 0;
     return plan(p).total;
 }
 
 int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes, void* stream, hotrg_solve** out) {
     if (!out) return HOTRG_EINVAL;
     *out = nullptr;
-    if (!valid_params(p) || !workspace || ((uintptr_t)workspace & 255u)) return HOTRG_EINVAL;
+    if (!valid_params(p) || !eig_feasible(p) || !workspace || ((uintptr_t)workspace & 255u)) return HOTRG_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HOTRG_ENODEV;
     const Layout L = plan(p);
@@ -416,38 +433,16 @@ int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes, v
         return rc;
     }
 
-    // Eigensolver context bound to the caller's stream, with its device
-    // workspace sized once, here, for the largest environment of the solve.
-    if (rocblas_create_handle(&s->rb) != rocblas_status_success) {
-        delete s;
-        return HOTRG_EEIG;
-    }
-    rocblas_set_stream(s->rb, s->stream);
-    const size_t need = eig_workspace_need(s, p);
-    if (need > 0) {
-        if (hipMalloc(&s->eig_ws, need) != hipSuccess) {
-            rocblas_destroy_handle(s->rb);
-            delete s;
-            return HOTRG_EHIP;
-        }
-        s->eig_ws_bytes = need;
-        rocblas_set_workspace(s->rb, s->eig_ws, need);
-    }
     *out = s;
     return HOTRG_OK;
 }
 
 int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
-    if (!s || !valid_params(p)) return HOTRG_EINVAL;
+    if (!s || !valid_params(p) || !eig_feasible(p)) return HOTRG_EINVAL;
     if (hipStreamSynchronize(s->stream) != hipSuccess) return HOTRG_EHIP;
     const Layout L = plan(p);
     if (L.total > s->ws_bytes) return HOTRG_ENOMEM;
-    const Layout old = s->L;
     s->L = L;
-    if (eig_workspace_need(s, p) > s->eig_ws_bytes) {
-        s->L = old;
-        return HOTRG_ENOMEM;
-    }
     s->p = *p;
     s->p.custom_tensor = nullptr;
     s->fmt = fmt_of(p->precision);
@@ -491,6 +486,19 @@ int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err, doubl
     if (c_n) *c_n = d.c[n];
     if (trunc_err) *trunc_err = n ? d.trunc_err[n] : 0.0;
     if (cut_gap) *cut_gap = n ? d.cut_gap[n] : 0.0;
+    return HOTRG_OK;
+}
+
+int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual) {
+    if (!s || n < 1 || n > s->steps) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    if (iterations) *iterations = d.info[n];
+    if (sweeps) *sweeps = d.eig_sweeps[n];
+    if (residual) *residual = d.eig_resid[n];
     return HOTRG_OK;
 }
 
@@ -565,8 +573,6 @@ void hotrg_destroy(hotrg_solve* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
-    if (s->rb) rocblas_destroy_handle(s->rb);
-    if (s->eig_ws) (void)hipFree(s->eig_ws);
     delete s;
 }
 

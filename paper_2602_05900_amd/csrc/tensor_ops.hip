@@ -1,7 +1,6 @@
 // Small D^4-sized kernels of a HOTRG step: operand re-layouts of T, the
-// max-abs normalisation with ln Z accumulation, the final trace, the
-// symmetrisation of E and the selection of the truncation isometry from the
-// eigensolver output.  None of them is on the D^7 path; they are written
+// max-abs normalisation with ln Z accumulation, the final trace and the
+// symmetrisation of E.  None of them is on the D^7 path; they are written
 // for coalesced stores and deterministic (order-fixed) reductions.
 #include <math.h>
 #include "common.h"
@@ -198,76 +197,6 @@ __global__ void symmetrize_kernel(double* __restrict__ E, int n) {
 hipError_t launch_symmetrize(double* E, int n, hipStream_t stream) {
     const unsigned b = (unsigned)((n + 15) / 16);
     hipLaunchKernelGGL(symmetrize_kernel, dim3(b, b), dim3(16, 16), 0, stream, E, n);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- isometry
-
-// One block per kept column l.
-__global__ __launch_bounds__(256) void select_isometry_kernel(const double* __restrict__ V, int n, int dx, int kept,
-                                                              Buf Ut, Buf Ux) {
-    __shared__ double sv[256];
-    __shared__ int si[256];
-    const int l = blockIdx.x;
-    const double* v = V + (long)(n - 1 - l) * n;  // descending order
-    // argmax |v[i]|, lowest index among equal magnitudes
-    double best = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const double a = fabs(v[i]);
-        if (a > best) { best = a; bi = i; }
-    }
-    sv[threadIdx.x] = best;
-    si[threadIdx.x] = bi;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            const double a = sv[threadIdx.x + s];
-            const int ia = si[threadIdx.x + s];
-            if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ia < si[threadIdx.x])) {
-                sv[threadIdx.x] = a;
-                si[threadIdx.x] = ia;
-            }
-        }
-        __syncthreads();
-    }
-    const double sgn = v[si[0]] < 0.0 ? -1.0 : 1.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const double u = sgn * v[i];
-        put(Ut, (size_t)l * n + i, u);
-        const int a1 = i / dx, a2 = i - (i / dx) * dx;
-        put(Ux, ((size_t)l * dx + a2) * dx + a1, u);
-    }
-}
-
-// One block: truncation error and cut gap from the ascending eigenvalues,
-// eigensolver status.  Sums in a fixed order.
-__global__ __launch_bounds__(256) void eig_stats_kernel(const double* __restrict__ w, const int* info, int n, int kept,
-                                                        DevState* st, int step) {
-    __shared__ double sh[256];
-    double tot = 0.0, dis = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        tot += w[i];
-        if (i < n - kept) dis += w[i];   // ascending: the n - kept smallest are discarded
-    }
-    tot = block_sum<256>(tot, sh);
-    dis = block_sum<256>(dis, sh);
-    if (threadIdx.x == 0) {
-        const int inf = *info;
-        if (step < 64) {
-            st->info[step] = inf;
-            st->trunc_err[step] = tot != 0.0 ? dis / tot : 0.0;
-            st->cut_gap[step] = kept < n ? (w[n - kept] - w[n - kept - 1]) / w[n - 1] : INFINITY;
-        }
-        if (inf != 0 && st->status == 0) st->status = HOTRG_EEIG;
-    }
-}
-
-hipError_t launch_select_isometry(const double* V, const double* w, const int* info, int n, int dx,
-                                  int kept, const Buf& Ut, const Buf& Ux, DevState* st, int step,
-                                  hipStream_t stream) {
-    hipLaunchKernelGGL(select_isometry_kernel, dim3(kept), dim3(256), 0, stream, V, n, dx, kept, Ut, Ux);
-    hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(256), 0, stream, w, info, n, kept, st, step);
     return hipGetLastError();
 }
 
