@@ -223,6 +223,187 @@ void gemm_nt_kernel(const T* __restrict__ A, long lda, const T* __restrict__ B, 
     }
 }
 
+
+// ---------------------------------------------------------------- BF16-split kernel
+
+// Split products: plane pairs (a, b) multiplied for each precision mode.
+//   2 terms, 3 products:  hi*hi + hi*lo + lo*hi
+//   3 terms, 6 products:  hi*hi + hi*mid + mid*hi + hi*lo + lo*hi + mid*mid
+template <int NPROD> struct SplitProducts;
+template <> struct SplitProducts<3> {
+    static constexpr int planes = 2;
+    __device__ static constexpr int a(int i) { return i == 2 ? 1 : 0; }
+    __device__ static constexpr int b(int i) { return i == 1 ? 1 : 0; }
+};
+template <> struct SplitProducts<6> {
+    static constexpr int planes = 3;
+    // order: hi*hi, hi*mid, mid*hi, hi*lo, lo*hi, mid*mid
+    __device__ static constexpr int a(int i) { return i == 2 ? 1 : (i == 4 ? 2 : (i == 5 ? 1 : 0)); }
+    __device__ static constexpr int b(int i) { return i == 1 ? 1 : (i == 3 ? 2 : (i == 5 ? 1 : 0)); }
+};
+
+// FP32 operands, split into bf16 planes while staged into LDS (each plane
+// rounded to nearest-even in fp32 arithmetic: hi = bf16(v), mid = bf16(v - hi),
+// lo = bf16(v - hi - mid)); v_mfma_f32_16x16x32_bf16 fragments (lane l holds
+// A[l%16][8(l/16)..8(l/16)+7] and B[8(l/16)..+7][l%16]; result row
+// 4(l/16)+r, column l%16 in component r), FP32 accumulation.
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
+void gemm_nt_bf16split_kernel(const float* __restrict__ A, long lda, const float* __restrict__ B, long ldb,
+                              int M, int N, int K, Store store, OutMap mp,
+                              int tiles_m, int tiles_n, int per_xcd)
+{
+    using SP = SplitProducts<NPROD>;
+    constexpr int NPL = SP::planes;
+    constexpr int BK = 32;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    constexpr int WM = BM / WAVES_M;
+    constexpr int WN = BN / WAVES_N;
+    constexpr int FM = WM / 16;
+    constexpr int FN = WN / 16;
+    constexpr int LDK = BK + 8;   // bf16 elements per LDS row (80 B: 16-byte aligned, conflict-free)
+    constexpr int A_PER_T = BM * BK / NT;
+    constexpr int B_PER_T = BN * BK / NT;
+    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile/threads mismatch");
+    static_assert(NT % BK == 0, "a K row must be loaded by whole thread groups");
+
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][NPL][BM * LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NPL][BN * LDK];
+
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * per_xcd + (bid >> 3);
+    if (tile >= tiles_m * tiles_n) return;
+    const int tm = tile / tiles_n;
+    const int tn = tile - tm * tiles_n;
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WAVES_N;
+    const int wn = wave - wm * WAVES_N;
+    const int lrow = tid / BK;
+    const int lcol = tid - lrow * BK;
+    constexpr int ROWS_PER_PASS = NT / BK;
+
+    float ra[A_PER_T], rb[B_PER_T];
+    auto load_tile = [&](int k0) {
+        const int k = k0 + lcol;
+        const bool kin = k < K;
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int r = m0 + lrow + i * ROWS_PER_PASS;
+            ra[i] = (kin && r < M) ? A[(long)r * lda + k] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) {
+            const int r = n0 + lrow + i * ROWS_PER_PASS;
+            rb[i] = (kin && r < N) ? B[(long)r * ldb + k] : 0.f;
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < A_PER_T; ++i) {
+            const int o = (lrow + i * ROWS_PER_PASS) * LDK + lcol;
+            const float v = ra[i];
+            const __bf16 h = (__bf16)v;
+            As[buf][0][o] = h;
+            const float r1 = v - (float)h;
+            const __bf16 m = (__bf16)r1;
+            As[buf][1][o] = m;
+            if constexpr (NPL == 3) As[buf][NPL - 1][o] = (__bf16)(r1 - (float)m);
+        }
+#pragma unroll
+        for (int i = 0; i < B_PER_T; ++i) {
+            const int o = (lrow + i * ROWS_PER_PASS) * LDK + lcol;
+            const float v = rb[i];
+            const __bf16 h = (__bf16)v;
+            Bs[buf][0][o] = h;
+            const float r1 = v - (float)h;
+            const __bf16 m = (__bf16)r1;
+            Bs[buf][1][o] = m;
+            if constexpr (NPL == 3) Bs[buf][NPL - 1][o] = (__bf16)(r1 - (float)m);
+        }
+    };
+
+    f4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+    const int nk = (K + BK - 1) / BK;
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+
+    const int frow = lane & 15;
+    const int fk = lane >> 4;   // 8-element k group of this lane
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_tile((kt + 1) * BK);
+        bf16x8 a[NPL][FM], b[NPL][FN];
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[pl][i] = *reinterpret_cast<const bf16x8*>(&As[buf][pl][(wm * WM + i * 16 + frow) * LDK + 8 * fk]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[pl][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][pl][(wn * WN + j * 16 + frow) * LDK + 8 * fk]);
+        }
+#pragma unroll
+        for (int pr = NPROD - 1; pr >= 0; --pr)   // smallest products first
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[SP::a(pr)][i], b[SP::b(pr)][j], acc[i][j],
+                                                                        0, 0, 0);
+        if (kt + 1 < nk) store_tile(buf ^ 1);
+        __syncthreads();
+    }
+
+    long coff[FN];
+    bool cin[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn * WN + j * 16 + frow;
+        cin[j] = n < N;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = m0 + wm * WM + i * 16 + 4 * fk + r;
+            if (m >= M) continue;
+            const long roff = map_row(mp, (unsigned)m);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+        }
+    }
+}
+
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
+static hipError_t run_gemm_split(const float* A, long lda, const float* B, long ldb, int M, int N, int K,
+                                 const Store& st, const OutMap& mp, hipStream_t stream)
+{
+    const int tiles_m = (M + BM - 1) / BM;
+    const int tiles_n = (N + BN - 1) / BN;
+    const long tiles = (long)tiles_m * tiles_n;
+    const int per_xcd = (int)((tiles + 7) / 8);
+    const long grid = 8L * per_xcd;
+    if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_nt_bf16split_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), 0, stream, A, lda, B, ldb, M, N, K, st, mp, tiles_m, tiles_n,
+                       per_xcd);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launcher
 
 template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int ROLE>
@@ -243,8 +424,16 @@ static hipError_t run_gemm(const T* A, long lda, const T* B, long ldb, int M, in
 
 template <int ROLE>
 static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
-                           const Store& st, const OutMap& map, hipStream_t stream)
+                           const Store& st, const OutMap& map, int products, hipStream_t stream)
 {
+    if (A.fmt == Fmt::F32 && products == 3)
+        return run_gemm_split<3, 128, 128, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
+                                                       static_cast<const float*>(B.ptr), ldb, M, N, K, st, map,
+                                                       stream);
+    if (A.fmt == Fmt::F32 && products == 6)
+        return run_gemm_split<6, 128, 128, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
+                                                       static_cast<const float*>(B.ptr), ldb, M, N, K, st, map,
+                                                       stream);
     switch (A.fmt) {
         case Fmt::F64:
             return run_gemm<double, 128, 128, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
@@ -263,15 +452,14 @@ hipError_t launch_gemm_nt(const Buf& A, long lda, const Buf& B, long ldb, const 
                           int M, int N, int K, double alpha, const OutMap& map,
                           int products, GemmRole role, hipStream_t stream)
 {
-    (void)products;
     if (M <= 0 || N <= 0) return hipSuccess;
     if (A.fmt != B.fmt || map.sm < 1 || map.sn < 1) return hipErrorInvalidValue;
     Store st{C.ptr, C.plane, (int)C.fmt, alpha};
     switch (role) {
-        case GemmRole::X: return dispatch<1>(A, lda, B, ldb, M, N, K, st, map, stream);
-        case GemmRole::Y: return dispatch<2>(A, lda, B, ldb, M, N, K, st, map, stream);
-        case GemmRole::TP: return dispatch<3>(A, lda, B, ldb, M, N, K, st, map, stream);
-        default: return dispatch<0>(A, lda, B, ldb, M, N, K, st, map, stream);
+        case GemmRole::X: return dispatch<1>(A, lda, B, ldb, M, N, K, st, map, products, stream);
+        case GemmRole::Y: return dispatch<2>(A, lda, B, ldb, M, N, K, st, map, products, stream);
+        case GemmRole::TP: return dispatch<3>(A, lda, B, ldb, M, N, K, st, map, products, stream);
+        default: return dispatch<0>(A, lda, B, ldb, M, N, K, st, map, products, stream);
     }
 }
 

@@ -48,7 +48,7 @@ GEMM_CASES = [
 
 
 @pytest.mark.parametrize("M,N,K", GEMM_CASES)
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6", "bf16x3"])
 def test_gemm_nt_row_major(gpu_lib, M, N, K, precision):
     """C = 0.75 A B^T against NumPy, within the standard error bound of a
     K-term dot product, |err| <= (2u + c sqrt(K) u) sum_k |a_k b_k| with u the
@@ -69,7 +69,10 @@ def test_gemm_nt_row_major(gpu_lib, M, N, K, precision):
     torch.cuda.synchronize()
     C = dC.cpu().numpy().reshape(M, N)
     assert np.all(np.isfinite(C))
-    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    # unit roundoff of each path: FP64; FP32 (and a 3-term BF16 split of an
+    # FP32 operand, 24 significant bits, with FP32 accumulation); a 2-term
+    # BF16 split keeps 16 significant bits
+    u = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x6": 2.0 ** -24, "bf16x3": 2.0 ** -16}[precision]
     bound = (2.0 + 8.0 * np.sqrt(max(K, 1))) * u * absdot + 1e-300
     assert np.all(np.abs(C - ref) <= bound), float(np.max(np.abs(C - ref) / bound))
 

@@ -1,0 +1,59 @@
+"""Reduced-precision contraction paths (FP32, BF16 split with 3 or 6
+products, FP32 accumulation) against the FP64 oracle.  The eigensolve, the
+normalisation and ln Z stay FP64 in every mode.  The bounds here are the
+claims each mode makes (|delta f| / |f|): FP32 and BF16x6 <= 1e-6, BF16x3
+<= 1e-5; the measured errors are reported by the benchmark."""
+import numpy as np
+import pytest
+
+from oracle import exact, hotrg as oracle
+
+pytestmark = pytest.mark.gpu
+
+CLAIM = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5}
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("T", [1.8, 2.269185314213022, 2.8])
+def test_d24_solve_error_within_claim(gpu_lib, precision, T):
+    from paper_2602_05900_amd import binding
+    ref = oracle.solve("ising", 2, T, 24, 30, keep_tensor=False).lnz_per_site
+    s = binding.Solve(model="ising", q=2, temperature=T, dmax=24, precision=precision, max_steps=30)
+    s.coarse_grain(30)
+    err = rel(-T * s.log_z(), -T * ref)
+    print(f"{precision} T={T:.4f} |df|/|f| = {err:.2e}")
+    assert err <= CLAIM[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "bf16x3"])
+def test_potts_solve_error_within_claim(gpu_lib, precision):
+    from paper_2602_05900_amd import binding
+    T = 0.9 * exact.POTTS3_TC
+    ref = oracle.solve("potts", 3, T, 15, 16, keep_tensor=False).lnz_per_site
+    s = binding.Solve(model="potts", q=3, temperature=T, dmax=15, precision=precision, max_steps=16)
+    s.coarse_grain(16)
+    assert rel(s.log_z(), ref) <= CLAIM[precision]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("bf16x6", 2e-5), ("bf16x3", 5e-4)])
+def test_d48_full_size_step_reduced_precision(gpu_lib, precision, tol):
+    """The D = 48 steady-state step in each precision from the same FP64 input
+    tensor as the oracle: the next tensor agrees elementwise to the precision's
+    level (relative to its largest entry, which is 1)."""
+    from paper_2602_05900_amd import binding
+    T = 2.25
+    f = binding.Solve(model="ising", q=2, temperature=T, dmax=48, max_steps=8)
+    f.coarse_grain(7)
+    Tin = f.tensor()
+    st = oracle.coarse_grain_step(Tin, 48)
+    s = binding.Solve(model="custom", tensor=Tin, dmax=48, temperature=1.0, precision=precision, max_steps=1)
+    s.coarse_grain(1)
+    c, _, _ = s.step_info(1)
+    assert rel(c, st.c) <= tol
+    if st.trunc.cut_gap > 1e-6:
+        G = s.tensor()
+        assert np.max(np.abs(G - st.T_next)) <= tol
