@@ -195,6 +195,10 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
     const int tid = threadIdx.x;
     const int pp = p + (p & 1);   // even number of players; index p (if any) is a zero dummy
     const int half = pp / 2;
+    const int bstride = 1024 / half;      // threads per block column
+    // threads 0 .. half*bstride-1 own block column bq and rows bp0, bp0+bstride, ...
+    const int bq = tid < half * bstride ? tid % half : half;
+    const int bp0 = tid / half;
     for (int e = tid; e < pp * pp; e += 1024) {
         const int i = e / pp, j = e - (e / pp) * pp;
         double h = 0.0;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
                 pj[tid] = j;
                 const double hii = H[i * EIG_LDP + i], hjj = H[j * EIG_LDP + j], hij = H[i * EIG_LDP + j];
                 double c = 1.0, s = 0.0, t = 0.0;
-                if (fabs(hij) > 1e-300 && fabs(hij) > 1e-16 * sqrt(fabs(hii * hjj))) {
+                if (fabs(hij) > 1e-300 && fabs(hij) > 1e-14 * sqrt(fabs(hii * hjj))) {
                     const double tau = (hjj - hii) / (2.0 * hij);
                     t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
@@ -230,21 +234,25 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
                 tt[tid] = t;
             }
             __syncthreads();
-            // two-sided update of every 2x2 block: B' = J_P^T B J_Q
-            for (int e = tid; e < half * half; e += 1024) {
-                const int P = e / half, Q = e - (e / half) * half;
-                const int i = pi[P], j = pj[P], k = pi[Q], l = pj[Q];
-                if (P == Q) {
-                    const double t = tt[P];
-                    if (t != 0.0) {
-                        const double hij = H[i * EIG_LDP + j];
-                        H[i * EIG_LDP + i] -= t * hij;
-                        H[j * EIG_LDP + j] += t * hij;
-                        H[i * EIG_LDP + j] = 0.0;
-                        H[j * EIG_LDP + i] = 0.0;
+            // two-sided update of every 2x2 block: B' = J_P^T B J_Q; thread
+            // (bq, bp0) handles blocks (P, Q = bq) for P = bp0, bp0 + bstride, ...
+            if (bq < half) {
+                const int k = pi[bq], l = pj[bq];
+                const double cq = cs[bq], sq = sn[bq];
+                for (int P = bp0; P < half; P += bstride) {
+                    const int i = pi[P], j = pj[P];
+                    if (P == bq) {
+                        const double t = tt[P];
+                        if (t != 0.0) {
+                            const double hij = H[i * EIG_LDP + j];
+                            H[i * EIG_LDP + i] -= t * hij;
+                            H[j * EIG_LDP + j] += t * hij;
+                            H[i * EIG_LDP + j] = 0.0;
+                            H[j * EIG_LDP + i] = 0.0;
+                        }
+                        continue;
                     }
-                } else {
-                    const double cp = cs[P], sp = sn[P], cq = cs[Q], sq = sn[Q];
+                    const double cp = cs[P], sp = sn[P];
                     if (sp == 0.0 && sq == 0.0) continue;   // both rotations are the identity
                     const double bik = H[i * EIG_LDP + k], bil = H[i * EIG_LDP + l];
                     const double bjk = H[j * EIG_LDP + k], bjl = H[j * EIG_LDP + l];
@@ -258,15 +266,16 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
                     H[j * EIG_LDP + l] = sq * rjk + cq * rjl;
                 }
             }
-            // accumulate: V <- V J (columns i, j of every row)
-            for (int e = tid; e < pp * half; e += 1024) {
-                const int row = e / half, Q = e - (e / half) * half;
-                const double c = cs[Q], s = sn[Q];
-                if (s != 0.0) {
-                    const int k = pi[Q], l = pj[Q];
-                    const double a = V[row * EIG_LDP + k], b = V[row * EIG_LDP + l];
-                    V[row * EIG_LDP + k] = c * a - s * b;
-                    V[row * EIG_LDP + l] = s * a + c * b;
+            // accumulate: V <- V J (columns k, l of rows bp0, bp0 + bstride, ...)
+            if (bq < half) {
+                const double c = cs[bq], sv = sn[bq];
+                if (sv != 0.0) {
+                    const int k = pi[bq], l = pj[bq];
+                    for (int row = bp0; row < pp; row += bstride) {
+                        const double a = V[row * EIG_LDP + k], b = V[row * EIG_LDP + l];
+                        V[row * EIG_LDP + k] = c * a - sv * b;
+                        V[row * EIG_LDP + l] = sv * a + c * b;
+                    }
                 }
             }
             __syncthreads();
@@ -419,26 +428,27 @@ __global__ __launch_bounds__(1024) void eig_chol_kernel(const double* __restrict
         A[i * EIG_LDP + j] = v;
     }
     __syncthreads();
-    // right-looking Cholesky on the lower triangle
+    // right-looking Cholesky of the lower triangle, two barriers per column:
+    // every thread takes the pivot sqrt(A_jj) itself (A_jj is final and is
+    // not overwritten until the end), scales its entries of column j, then
+    // the trailing update runs.
+    __shared__ double ldiag[EIG_PMAX];
+    const int ty = tid >> 5, tx = tid & 31;
     for (int j = 0; j < p; ++j) {
-        if (tid == 0) {
-            const double a = A[j * EIG_LDP + j];
-            A[j * EIG_LDP + j] = a > 1e-300 ? sqrt(a) : 1.0;
-        }
-        __syncthreads();
-        const double ljj = A[j * EIG_LDP + j];
+        const double a = A[j * EIG_LDP + j];
+        const double ljj = a > 1e-300 ? sqrt(a) : 1.0;
+        if (tid == 0) ldiag[j] = ljj;
         for (int i = j + 1 + tid; i < p; i += 1024) A[i * EIG_LDP + j] /= ljj;
         __syncthreads();
-        const int m = p - j - 1;
-        for (int e = tid; e < m * m; e += 1024) {
-            const int a = e / m, b = e - (e / m) * m;
-            if (b <= a) {
-                const int i = j + 1 + a, l = j + 1 + b;
-                A[i * EIG_LDP + l] -= A[i * EIG_LDP + j] * A[l * EIG_LDP + j];
-            }
+        // trailing update of the lower triangle, thread (ty, tx) of a 32 x 32 grid
+        for (int i = j + 1 + ty; i < p; i += 32) {
+            const double lij = A[i * EIG_LDP + j];
+            for (int l = j + 1 + tx; l <= i; l += 32) A[i * EIG_LDP + l] -= lij * A[l * EIG_LDP + j];
         }
         __syncthreads();
     }
+    for (int j = tid; j < p; j += 1024) A[j * EIG_LDP + j] = ldiag[j];
+    __syncthreads();
     // M = L^{-1} (lower), row by row: M[i][j] = -(sum_{m=j}^{i-1} L[i][m] M[m][j]) / L[i][i]
     // kept in the strict upper triangle of A transposed (A[j][i] for j < i) and
     // the diagonal in d2; L stays in the lower triangle.
