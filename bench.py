@@ -19,7 +19,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -31,15 +30,6 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc"}
-
-
-def percentile(xs, p):
-    xs = sorted(xs)
-    if not xs:
-        return float("nan")
-    k = (len(xs) - 1) * p / 100.0
-    lo, hi = math.floor(k), math.ceil(k)
-    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
 def cpu_baseline(dmax: int, nsteps_sample: int, temperature: float):
@@ -70,13 +60,15 @@ def cpu_baseline(dmax: int, nsteps_sample: int, temperature: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6, help="timed solves")
+    ap.add_argument("--steps", type=int, default=16, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--dmax", type=int, default=48)
     ap.add_argument("--nsteps", type=int, default=30, help="coarse-graining steps per solve")
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--concurrency", type=int, default=4, help="solves in flight (streams)")
+    ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -85,48 +77,42 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2602_05900_amd import accounting, binding, workloads
+    from paper_2602_05900_amd import accounting, binding, serve, workloads
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     temps = workloads.temperature_grid(2.0, 2.5, 16)
-    stream = torch.cuda.Stream(device=dev)
-    kw = dict(model="ising", q=2, dmax=args.dmax, precision=args.precision, max_steps=args.nsteps)
-    ws = torch.empty(binding.workspace_bytes(temperature=float(temps[0]), **kw), dtype=torch.uint8, device=dev)
-    solve = binding.Solve(temperature=float(temps[0]), stream=stream, workspace=ws, **kw)
-    solve.set_timing(True)
-
     flops_solve = accounting.solve_flops(2, args.dmax, args.nsteps)
     dims = accounting.step_dims(2, 2, args.dmax, args.nsteps)
     y_flops = sum(accounting.stage_flops(*d)["y"] for d in dims)
 
-    def run_one(i):
-        T = float(temps[i % len(temps)])
-        solve.reset(temperature=T, **kw)
-        solve.coarse_grain(args.nsteps)
-        lnz = solve.log_z()
-        st, nt = solve.stage_times()
-        return T, lnz, st
+    def batch(first, count):
+        return [workloads.Request(rid=first + i, arrival=0.0, model="ising", q=2,
+                                  temperature=float(temps[(first + i) % len(temps)]), dmax=args.dmax,
+                                  nsteps=args.nsteps) for i in range(count)]
 
-    for w in range(args.warmup):
-        run_one(w)
-        print(f"# warmup solve {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    server = serve.Server(slots=args.concurrency, budget=args.budget_gb << 30, precision=args.precision,
+                          device="cuda:0", timing=True)
+    if args.warmup:
+        server.run(batch(0, args.warmup), realtime=False)
+        print(f"# warmup: {args.warmup} solves done", file=sys.stderr, flush=True)
+
+    def progress(now, done, total, active, queued):
+        print(f"# {now:6.1f} s: {done}/{total} solves done, {active} active", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
-    lat, stage_sum, results = [], {k: 0.0 for k in binding.STAGES}, []
     t_start = time.perf_counter()
-    for i in range(args.steps):
-        t0 = time.perf_counter()
-        T, lnz, st = run_one(args.warmup + i)
-        lat.append(time.perf_counter() - t0)
-        for k, v in st.items():
-            stage_sum[k] += v
-        results.append((T, lnz))
-        print(f"# solve {i + 1}/{args.steps}: T={T:.4f} lnZ/N={lnz:.15f} {lat[-1] * 1e3:.1f} ms",
-              file=sys.stderr, flush=True)
+    done = server.run(batch(args.warmup, args.steps), realtime=False, progress=progress)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    for c in done:
+        print(f"# solve T={c.temperature:.4f} lnZ/N={c.lnz_per_site:.15f} service {1e3 * (c.finished - c.admitted):.1f} ms",
+              file=sys.stderr, flush=True)
 
+    stage_sum = {k: 0.0 for k in binding.STAGES}
+    for c in done:
+        for k, v in c.stage_ms.items():
+            stage_sum[k] += v
     total_flops = flops_solve * args.steps
     value = total_flops / wall / 1e12
     y_ms = stage_sum["y"]
@@ -134,6 +120,18 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     hw_achieved = achieved * PRODUCTS[args.precision] if achieved else None
     contraction_ms = stage_sum["env"] + stage_sum["x"] + stage_sum["y"] + stage_sum["tp"]
+    service = [c.finished - c.admitted for c in done]
+    latency = [c.latency for c in done]
+
+    ref = {}
+    ref_path = os.path.join(ROOT, "tests", "golden", "oracle_ising_d48.json")
+    if args.dmax == 48 and args.nsteps == 30 and os.path.exists(ref_path):
+        ref = {round(r["temperature"], 9): r["lnz_per_site"] for r in json.load(open(ref_path))["rows"]}
+    errs = {}
+    for c in done:
+        key = round(c.temperature, 9)
+        if key in ref:
+            errs[f"{c.temperature:.6f}"] = abs(c.lnz_per_site - ref[key]) / abs(ref[key])
 
     line = {
         "metric": "HOTRG contraction TFLOP/s at D=48 (FP64 vs mixed); p50/p99 solve latency",
@@ -150,15 +148,18 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"HOTRG 2D Ising J=1, D={args.dmax}, {args.nsteps} steps per solve, "
-                        f"T cycling over 16 values in [2.0, 2.5]; one step of this benchmark = one solve",
+                        f"T cycling over 16 values in [2.0, 2.5]; one step of this benchmark = one solve; "
+                        f"{args.concurrency} solves in flight on separate streams",
             "dmax": args.dmax,
             "coarse_grain_steps": args.nsteps,
             "contraction_precision": args.precision,
             "eigensolve": "FP64",
+            "concurrency": args.concurrency,
             "flops_per_solve": flops_solve,
         },
-        "p50_solve_ms": percentile(lat, 50) * 1e3,
-        "p99_solve_ms": percentile(lat, 99) * 1e3,
+        "p50_solve_ms": serve.percentile(service, 50) * 1e3,
+        "p99_solve_ms": serve.percentile(service, 99) * 1e3,
+        "p50_batch_latency_ms": serve.percentile(latency, 50) * 1e3,
         "solves_per_s": args.steps / wall,
         "stage_ms_per_solve": {k: v / args.steps for k, v in stage_sum.items()},
         "contraction_kernel_tflops": total_flops / (contraction_ms * 1e-3) / 1e12 if contraction_ms else None,
@@ -171,15 +172,16 @@ def main():
             "frac": hw_achieved / peak if hw_achieved else None,
             "traffic": None,
             "algorithmic_flops_per_solve": y_flops,
+            "hardware_flops_factor": PRODUCTS[args.precision],
             "launches": args.nsteps * args.steps,
             "avg_launch_ms": y_ms / (args.nsteps * args.steps),
         },
-        "lnz_per_site": {f"{T:.6f}": v for T, v in results},
+        "lnz_per_site": {f"{c.temperature:.6f}": c.lnz_per_site for c in done},
+        "rel_err_vs_fp64_oracle": errs or None,
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))
-    solve.close()
     print(json.dumps(line), flush=True)
 
 

@@ -1,0 +1,215 @@
+"""Continuous-batching HOTRG solve server on one GPU.
+
+Requests (model, q, T, D, steps) arrive over time.  The scheduler admits a
+request when a stream slot is free and its device footprint
+(hotrg_workspace_bytes: dominated by the two D^5 intermediates) fits the
+memory budget, keeps every admitted solve's tensors resident in its own
+workspace, and advances the active solves one coarse-graining step at a time,
+round-robin, each on its own HIP stream, so that the steps of different solves
+overlap on the device (iteration-level scheduling, not run-to-completion).  A
+solve completes when the event recorded after its last step has fired; its
+ln Z / N is read, its latency recorded, and its memory and slot are released
+for the next request.  All device work goes through the C ABI (binding.py);
+this module only schedules.
+
+Results do not depend on the mix: each solve's kernels use fixed-order
+reductions and no atomics, so a solve gives bitwise the same ln Z / N alone
+and among others.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from . import accounting, binding
+
+
+@dataclass
+class Completed:
+    rid: int
+    model: str
+    q: int
+    temperature: float
+    dmax: int
+    nsteps: int
+    precision: str
+    lnz_per_site: float
+    arrival: float        # seconds since the start of the run
+    admitted: float
+    finished: float
+    footprint: int
+    flops: float
+    stage_ms: dict | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+    @property
+    def free_energy(self) -> float:
+        return -self.temperature * self.lnz_per_site
+
+
+@dataclass
+class _Active:
+    req: object
+    solve: binding.Solve
+    stream: object
+    workspace: torch.Tensor
+    footprint: int
+    admitted: float
+    slot: int = -1
+    enqueued: int = 0
+    events: collections.deque = field(default_factory=collections.deque)
+
+
+class Server:
+    """Schedules HOTRG solves on one device.
+
+    slots       maximum number of solves in flight (one HIP stream each)
+    budget      bytes of device memory the solves' workspaces may hold
+    depth       coarse-graining steps a solve may have enqueued ahead of the
+                device (keeps every stream busy without flooding the host)
+    precision   contraction precision of every solve
+    timing      record per-stage HIP events of every solve (hotrg_stage_times)
+    """
+
+    def __init__(self, slots: int = 8, budget: int = 64 << 30, depth: int = 2,
+                 precision: str = "fp64", device: str = "cuda:0", timing: bool = False):
+        binding.load()
+        self.timing = timing
+        self.device = torch.device(device)
+        self.slots = slots
+        self.budget = budget
+        self.depth = depth
+        self.precision = precision
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.free_streams = list(range(slots))
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.queue: collections.deque = collections.deque()
+        self.active: list[_Active] = []
+        self.done: list[Completed] = []
+        self.admission_log: list = []   # (rid, footprint, bytes in use after admission)
+        self.t0 = None
+
+    # -- footprint -------------------------------------------------------
+    def footprint(self, req) -> int:
+        return binding.workspace_bytes(model=req.model, q=req.q, temperature=req.temperature,
+                                       dmax=req.dmax, precision=self.precision, max_steps=req.nsteps)
+
+    # -- scheduling ------------------------------------------------------
+    def _now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def _admit(self):
+        while self.queue and self.free_streams:
+            req = self.queue[0]
+            fp = self.footprint(req)
+            if fp == 0:
+                raise ValueError(f"request {req.rid} has an invalid parameter set")
+            if fp > self.budget:
+                raise ValueError(f"request {req.rid} needs {fp} bytes, more than the whole budget")
+            if self.in_use + fp > self.budget:
+                break   # wait for memory; requests are admitted in arrival order
+            self.queue.popleft()
+            si = self.free_streams.pop()
+            stream = self.streams[si]
+            ws = torch.empty(fp, dtype=torch.uint8, device=self.device)
+            solve = binding.Solve(model=req.model, q=req.q, temperature=req.temperature, dmax=req.dmax,
+                                  precision=self.precision, stream=stream, workspace=ws, max_steps=req.nsteps)
+            self.in_use += fp
+            self.peak_in_use = max(self.peak_in_use, self.in_use)
+            self.admission_log.append((req.rid, fp, self.in_use))
+            if self.timing:
+                solve.set_timing(True)
+            a = _Active(req=req, solve=solve, stream=stream, workspace=ws, footprint=fp, admitted=self._now(),
+                        slot=si)
+            self.active.append(a)
+
+    def _advance(self) -> bool:
+        """Enqueue at most one step per active solve; returns True if any was enqueued."""
+        progressed = False
+        for a in self.active:
+            while a.events and a.events[0].query():
+                a.events.popleft()
+            if a.enqueued < a.req.nsteps and len(a.events) < self.depth:
+                a.solve.coarse_grain(1)
+                a.enqueued += 1
+                ev = torch.cuda.Event()
+                ev.record(a.stream)
+                a.events.append(ev)
+                progressed = True
+        return progressed
+
+    def _complete(self):
+        still = []
+        for a in self.active:
+            if a.enqueued == a.req.nsteps and all(e.query() for e in a.events):
+                lnz = a.solve.log_z()          # its stream is idle: returns at once
+                st = a.solve.stage_times()[0] if self.timing else None
+                r = a.req
+                self.done.append(Completed(
+                    rid=r.rid, model=r.model, q=r.q, temperature=r.temperature, dmax=r.dmax, nsteps=r.nsteps,
+                    precision=self.precision, lnz_per_site=lnz, arrival=r.arrival, admitted=a.admitted,
+                    finished=self._now(), footprint=a.footprint,
+                    flops=accounting.solve_flops(r.q, r.dmax, r.nsteps), stage_ms=st))
+                a.solve.close()
+                self.in_use -= a.footprint
+                self.free_streams.append(a.slot)
+                del a.workspace
+            else:
+                still.append(a)
+        self.active = still
+
+    def run(self, requests, realtime: bool = True, progress=None) -> list[Completed]:
+        """Serve `requests` (objects with rid, arrival, model, q, temperature,
+        dmax, nsteps).  realtime: requests become visible at their arrival
+        time; otherwise all are queued at once (a closed batch)."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        self.t0 = time.perf_counter()
+        i = 0
+        n_total = len(reqs)
+        n_before = len(self.done)
+        last_report = 0.0
+        while len(self.done) - n_before < n_total:
+            now = self._now()
+            while i < n_total and (not realtime or reqs[i].arrival <= now):
+                self.queue.append(reqs[i])
+                i += 1
+            self._complete()
+            self._admit()
+            progressed = self._advance()
+            if progress and now - last_report >= 5.0:
+                progress(now, len(self.done), n_total, len(self.active), len(self.queue))
+                last_report = now
+            if not progressed:
+                time.sleep(0.0002)
+        torch.cuda.synchronize(self.device)
+        return sorted(self.done[n_before:], key=lambda c: c.rid)
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def summarize(done: list[Completed], wall: float) -> dict:
+    lat = [c.latency for c in done]
+    flops = sum(c.flops for c in done)
+    return {
+        "solves": len(done),
+        "wall_s": wall,
+        "solves_per_s": len(done) / wall if wall > 0 else None,
+        "served_tflops": flops / wall / 1e12 if wall > 0 else None,
+        "p50_latency_s": percentile(lat, 50),
+        "p99_latency_s": percentile(lat, 99),
+        "max_latency_s": max(lat) if lat else None,
+    }
