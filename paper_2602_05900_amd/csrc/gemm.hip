@@ -242,16 +242,19 @@ template <> struct SplitProducts<6> {
     __device__ static constexpr int b(int i) { return i == 1 ? 1 : (i == 3 ? 2 : (i == 5 ? 1 : 0)); }
 };
 
-// FP32 operands, split into bf16 planes while staged into LDS (each plane
-// rounded to nearest-even in fp32 arithmetic: hi = bf16(v), mid = bf16(v - hi),
-// lo = bf16(v - hi - mid)); v_mfma_f32_16x16x32_bf16 fragments (lane l holds
+// Operands stored as bf16 planes (plane p of A at A + p * a_plane, rows of
+// length lda), the planes of one value summing to it (hi + lo or
+// hi + mid + lo, written by the producing kernels).  Tiles move global -> LDS
+// as 16-byte chunks (8 bf16) when the leading dimensions allow, else element
+// by element.  v_mfma_f32_16x16x32_bf16 fragments: lane l holds
 // A[l%16][8(l/16)..8(l/16)+7] and B[8(l/16)..+7][l%16]; result row
-// 4(l/16)+r, column l%16 in component r), FP32 accumulation.
+// 4(l/16)+r, column l%16 in component r; FP32 accumulation.
 template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
-void gemm_nt_bf16split_kernel(const float* __restrict__ A, long lda, const float* __restrict__ B, long ldb,
-                              int M, int N, int K, Store store, OutMap mp,
-                              int tiles_m, int tiles_n, int per_xcd)
+void gemm_nt_bf16planes_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
+                               const __bf16* __restrict__ B, long ldb, long b_plane,
+                               int M, int N, int K, Store store, OutMap mp,
+                               int tiles_m, int tiles_n, int per_xcd, int vec)
 {
     using SP = SplitProducts<NPROD>;
     constexpr int NPL = SP::planes;
@@ -261,11 +264,12 @@ void gemm_nt_bf16split_kernel(const float* __restrict__ A, long lda, const float
     constexpr int WN = BN / WAVES_N;
     constexpr int FM = WM / 16;
     constexpr int FN = WN / 16;
-    constexpr int LDK = BK + 8;   // bf16 elements per LDS row (80 B: 16-byte aligned, conflict-free)
-    constexpr int A_PER_T = BM * BK / NT;
-    constexpr int B_PER_T = BN * BK / NT;
-    static_assert(BM * BK % NT == 0 && BN * BK % NT == 0, "tile/threads mismatch");
-    static_assert(NT % BK == 0, "a K row must be loaded by whole thread groups");
+    constexpr int LDK = BK + 8;           // 80-byte LDS rows: 16-byte aligned, conflict-free fragment reads
+    constexpr int CPR = BK / 8;           // 16-byte chunks per tile row
+    constexpr int A_CH = BM * CPR / NT;   // chunks per thread per plane
+    constexpr int B_CH = BN * CPR / NT;
+    static_assert(BM * CPR % NT == 0 && BN * CPR % NT == 0, "tile/threads mismatch");
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
     __shared__ __attribute__((aligned(16))) __bf16 As[2][NPL][BM * LDK];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NPL][BN * LDK];
@@ -283,47 +287,60 @@ void gemm_nt_bf16split_kernel(const float* __restrict__ A, long lda, const float
     const int wave = tid >> 6;
     const int wm = wave / WAVES_N;
     const int wn = wave - wm * WAVES_N;
-    const int lrow = tid / BK;
-    const int lcol = tid - lrow * BK;
-    constexpr int ROWS_PER_PASS = NT / BK;
 
-    float ra[A_PER_T], rb[B_PER_T];
-    auto load_tile = [&](int k0) {
-        const int k = k0 + lcol;
-        const bool kin = k < K;
+    u4 ra[NPL][A_CH], rb[NPL][B_CH];
+
+    auto fetch = [&](const __bf16* base, long ld, long pstride, int nrows, int row, int k, u4 (&dst)[NPL]) {
+        if (row < nrows && vec && k + 8 <= K) {
 #pragma unroll
-        for (int i = 0; i < A_PER_T; ++i) {
-            const int r = m0 + lrow + i * ROWS_PER_PASS;
-            ra[i] = (kin && r < M) ? A[(long)r * lda + k] : 0.f;
+            for (int pl = 0; pl < NPL; ++pl)
+                dst[pl] = *reinterpret_cast<const u4*>(base + pl * pstride + (long)row * ld + k);
+        } else {
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) {
+                unsigned short e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    __bf16 v = (__bf16)0.0f;
+                    if (row < nrows && k + q < K) v = base[pl * pstride + (long)row * ld + k + q];
+                    e[q] = __builtin_bit_cast(unsigned short, v);
+                }
+                dst[pl] = u4{e[0] | (unsigned)e[1] << 16, e[2] | (unsigned)e[3] << 16,
+                             e[4] | (unsigned)e[5] << 16, e[6] | (unsigned)e[7] << 16};
+            }
+        }
+    };
+
+    auto load_tile = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < A_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+            u4 t[NPL];
+            fetch(A, lda, a_plane, M, m0 + row, k0 + 8 * kc, t);
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) ra[pl][i] = t[pl];
         }
 #pragma unroll
-        for (int i = 0; i < B_PER_T; ++i) {
-            const int r = n0 + lrow + i * ROWS_PER_PASS;
-            rb[i] = (kin && r < N) ? B[(long)r * ldb + k] : 0.f;
+        for (int i = 0; i < B_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+            u4 t[NPL];
+            fetch(B, ldb, b_plane, N, n0 + row, k0 + 8 * kc, t);
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) rb[pl][i] = t[pl];
         }
     };
     auto store_tile = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < A_PER_T; ++i) {
-            const int o = (lrow + i * ROWS_PER_PASS) * LDK + lcol;
-            const float v = ra[i];
-            const __bf16 h = (__bf16)v;
-            As[buf][0][o] = h;
-            const float r1 = v - (float)h;
-            const __bf16 m = (__bf16)r1;
-            As[buf][1][o] = m;
-            if constexpr (NPL == 3) As[buf][NPL - 1][o] = (__bf16)(r1 - (float)m);
+        for (int i = 0; i < A_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&As[buf][pl][row * LDK + 8 * kc]) = ra[pl][i];
         }
 #pragma unroll
-        for (int i = 0; i < B_PER_T; ++i) {
-            const int o = (lrow + i * ROWS_PER_PASS) * LDK + lcol;
-            const float v = rb[i];
-            const __bf16 h = (__bf16)v;
-            Bs[buf][0][o] = h;
-            const float r1 = v - (float)h;
-            const __bf16 m = (__bf16)r1;
-            Bs[buf][1][o] = m;
-            if constexpr (NPL == 3) Bs[buf][NPL - 1][o] = (__bf16)(r1 - (float)m);
+        for (int i = 0; i < B_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&Bs[buf][pl][row * LDK + 8 * kc]) = rb[pl][i];
         }
     };
 
@@ -389,8 +406,8 @@ void gemm_nt_bf16split_kernel(const float* __restrict__ A, long lda, const float
 }
 
 template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
-static hipError_t run_gemm_split(const float* A, long lda, const float* B, long ldb, int M, int N, int K,
-                                 const Store& st, const OutMap& mp, hipStream_t stream)
+static hipError_t run_gemm_planes(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
+                                  const Store& st, const OutMap& mp, hipStream_t stream)
 {
     const int tiles_m = (M + BM - 1) / BM;
     const int tiles_n = (N + BN - 1) / BN;
@@ -398,9 +415,12 @@ static hipError_t run_gemm_split(const float* A, long lda, const float* B, long 
     const int per_xcd = (int)((tiles + 7) / 8);
     const long grid = 8L * per_xcd;
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_nt_bf16split_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
-                       dim3(64 * WAVES_M * WAVES_N), 0, stream, A, lda, B, ldb, M, N, K, st, mp, tiles_m, tiles_n,
-                       per_xcd);
+    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
+                     ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
+    hipLaunchKernelGGL((gemm_nt_bf16planes_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
+                       static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
+                       per_xcd, vec ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -426,14 +446,9 @@ template <int ROLE>
 static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
                            const Store& st, const OutMap& map, int products, hipStream_t stream)
 {
-    if (A.fmt == Fmt::F32 && products == 3)
-        return run_gemm_split<3, 128, 128, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
-                                                       static_cast<const float*>(B.ptr), ldb, M, N, K, st, map,
-                                                       stream);
-    if (A.fmt == Fmt::F32 && products == 6)
-        return run_gemm_split<6, 128, 128, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
-                                                       static_cast<const float*>(B.ptr), ldb, M, N, K, st, map,
-                                                       stream);
+    (void)products;
+    if (A.fmt == Fmt::BF16x2) return run_gemm_planes<3, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+    if (A.fmt == Fmt::BF16x3) return run_gemm_planes<6, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
     switch (A.fmt) {
         case Fmt::F64:
             return run_gemm<double, 128, 128, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,

@@ -50,9 +50,16 @@ std::vector<StepDims> trajectory(int dx, int dy, int dmax, int nsteps) {
     return t;
 }
 
-// Storage of contraction operands: FP64, or FP32 for every reduced mode (the
-// BF16-split products split FP32 operands into planes while staging them).
-Fmt fmt_of(int prec) { return prec == HOTRG_FP64 ? Fmt::F64 : Fmt::F32; }
+// Storage of contraction operands: FP64, FP32, or the BF16 planes of the
+// split modes (written once by each producer, read by the split products).
+Fmt fmt_of(int prec) {
+    switch (prec) {
+        case HOTRG_FP32: return Fmt::F32;
+        case HOTRG_BF16X3: return Fmt::BF16x2;
+        case HOTRG_BF16X6: return Fmt::BF16x3;
+        default: return Fmt::F64;
+    }
+}
 
 int products_of(int prec) { return prec == HOTRG_BF16X3 ? 3 : (prec == HOTRG_BF16X6 ? 6 : 1); }
 
