@@ -7,13 +7,20 @@ coarse-graining steps, temperatures cycling through 16 evenly spaced values
 in [2.0, 2.5].  The initial tensor is built from the temperature (128 bytes
 of input); all intermediates stay in HBM.
 
+The solves of the batch run concurrently (--concurrency of them in flight,
+one HIP stream and workspace each) through the continuous-batching server.
+
 value = algorithmic contraction FLOPs of the timed solves (O(D^7) order,
 eigensolve excluded from the count but not from the time) / wall time of
-the timed region.  Also reported: per-solve latency p50/p99, per-stage GPU
-times from HIP events on the solve's stream, the roofline of the dominant
-kernel (the Y product) and the FP64 CPU oracle on a bounded sample.
+the timed region, in the headline precision (default: BF16 split into 3
+terms, 6 products, FP32 accumulation; eigensolve, normalisation and ln Z in
+FP64).  Also reported: the same batch in FP64, per-solve service time
+p50/p99, per-stage GPU times from HIP events, |delta f| against the FP64
+oracle's stored values for these temperatures, the roofline of the dominant
+kernel (the Y product, measured on one solve running alone) and the FP64
+CPU oracle on a bounded sample.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6]
+    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6] [--concurrency C]
 """
 from __future__ import annotations
 
@@ -62,7 +69,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
-    ap.add_argument("--precision", default="fp64", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--precision", default="bf16x6", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
+                    help="skip the FP64 run of the same batch")
     ap.add_argument("--dmax", type=int, default=48)
     ap.add_argument("--nsteps", type=int, default=30, help="coarse-graining steps per solve")
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
@@ -91,34 +100,51 @@ def main():
                                   temperature=float(temps[(first + i) % len(temps)]), dmax=args.dmax,
                                   nsteps=args.nsteps) for i in range(count)]
 
-    server = serve.Server(slots=args.concurrency, budget=args.budget_gb << 30, precision=args.precision,
-                          device="cuda:0", timing=True)
-    if args.warmup:
-        server.run(batch(0, args.warmup), realtime=False)
-        print(f"# warmup: {args.warmup} solves done", file=sys.stderr, flush=True)
-
     def progress(now, done, total, active, queued):
         print(f"# {now:6.1f} s: {done}/{total} solves done, {active} active", file=sys.stderr, flush=True)
 
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    done = server.run(batch(args.warmup, args.steps), realtime=False, progress=progress)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
+    def run_batch(precision, concurrency, first, count, warmup):
+        server = serve.Server(slots=concurrency, budget=args.budget_gb << 30, precision=precision,
+                              device="cuda:0", timing=True)
+        if warmup:
+            server.run(batch(first, warmup), realtime=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = server.run(batch(first + warmup, count), realtime=False, progress=progress)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stage = {k: 0.0 for k in binding.STAGES}
+        for c in done:
+            for k, v in c.stage_ms.items():
+                stage[k] += v
+        print(f"# {precision}: {count} solves, {concurrency} in flight, {wall:.2f} s", file=sys.stderr, flush=True)
+        return done, wall, stage
+
+    done, wall, stage_sum = run_batch(args.precision, args.concurrency, 0, args.steps, args.warmup)
     for c in done:
         print(f"# solve T={c.temperature:.4f} lnZ/N={c.lnz_per_site:.15f} service {1e3 * (c.finished - c.admitted):.1f} ms",
               file=sys.stderr, flush=True)
 
-    stage_sum = {k: 0.0 for k in binding.STAGES}
-    for c in done:
-        for k, v in c.stage_ms.items():
-            stage_sum[k] += v
-    total_flops = flops_solve * args.steps
-    value = total_flops / wall / 1e12
-    y_ms = stage_sum["y"]
-    achieved = y_flops * args.steps / (y_ms * 1e-3) / 1e12 if y_ms > 0 else None
+    # the dominant kernel measured alone: one solve on one stream, events around each Y launch
+    iso, iso_wall, iso_stage = run_batch(args.precision, 1, 0, 1, 0)
+    y_ms = iso_stage["y"]
+    achieved = y_flops / (y_ms * 1e-3) / 1e12 if y_ms > 0 else None
     peak = PEAK_TFLOPS[args.precision]
     hw_achieved = achieved * PRODUCTS[args.precision] if achieved else None
+
+    cmp = None
+    if args.compare_fp64 and args.precision != "fp64":
+        fdone, fwall, _ = run_batch("fp64", args.concurrency, 0, args.steps, 1)
+        fl = {c.rid: c.lnz_per_site for c in fdone}
+        cmp = {
+            "fp64_value": flops_solve * args.steps / fwall / 1e12,
+            "fp64_ms_per_step": fwall / args.steps * 1e3,
+            "speedup_vs_fp64": fwall / wall,
+            "max_rel_df_vs_gpu_fp64": max(abs(c.lnz_per_site - fl[c.rid]) / abs(fl[c.rid]) for c in done),
+        }
+
+    total_flops = flops_solve * args.steps
+    value = total_flops / wall / 1e12
     contraction_ms = stage_sum["env"] + stage_sum["x"] + stage_sum["y"] + stage_sum["tp"]
     service = [c.finished - c.admitted for c in done]
     latency = [c.latency for c in done]
@@ -162,6 +188,8 @@ def main():
         "p50_batch_latency_ms": serve.percentile(latency, 50) * 1e3,
         "solves_per_s": args.steps / wall,
         "stage_ms_per_solve": {k: v / args.steps for k, v in stage_sum.items()},
+        "isolated_solve_stage_ms": iso_stage,
+        "isolated_solve_ms": iso_wall * 1e3,
         "contraction_kernel_tflops": total_flops / (contraction_ms * 1e-3) / 1e12 if contraction_ms else None,
         "roofline": {
             "kernel": "gemm_nt (Y = X . T, the D^7 product)",
@@ -173,11 +201,14 @@ def main():
             "traffic": None,
             "algorithmic_flops_per_solve": y_flops,
             "hardware_flops_factor": PRODUCTS[args.precision],
-            "launches": args.nsteps * args.steps,
-            "avg_launch_ms": y_ms / (args.nsteps * args.steps),
+            "measured": "HIP events around each Y launch of one solve run alone on its stream",
+            "launches": args.nsteps,
+            "avg_launch_ms": y_ms / args.nsteps,
+            "timed_region_avg_launch_ms": stage_sum["y"] / (args.nsteps * args.steps),
         },
         "lnz_per_site": {f"{c.temperature:.6f}": c.lnz_per_site for c in done},
         "rel_err_vs_fp64_oracle": errs or None,
+        "fp64_comparison": cmp,
     }
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -22,7 +22,22 @@
 // so that the workgroups one XCD runs together share the same A rows
 // (workgroup i runs on XCD i mod 8), keeping the big operand's re-reads in
 // that XCD's L2.
+#include <type_traits>
+
 #include "common.h"
+
+// Tile of the BF16-split product: workgroup BM x BN over WM x WN waves, PF
+// K stages of global loads in flight.  256 x 256 on 8 waves measured fastest
+// for the D = 48 Y product (6.9 ms vs 8.5 ms for 256 x 128, 11.5 ms for
+// 128 x 128): the split operands make the product L2-bandwidth-bound, and
+// the larger tile reads each operand byte fewer times.
+#ifndef HOTRG_BF16_BM
+#define HOTRG_BF16_BM 256
+#define HOTRG_BF16_BN 256
+#define HOTRG_BF16_WM 4
+#define HOTRG_BF16_WN 2
+#define HOTRG_BF16_PF 1
+#endif
 
 namespace hotrg {
 
@@ -424,6 +439,219 @@ static hipError_t run_gemm_planes(const Buf& A, long lda, const Buf& B, long ldb
     return hipGetLastError();
 }
 
+
+// Same operands and split products as above, on v_mfma_f32_32x32x16_bf16
+// (twice the work per issued instruction of the 16x16x32 form; measured on
+// gfx950: lane l supplies A[l%32][8(l/32)..8(l/32)+7] and
+// B[8(l/32)..+7][l%32]; component r of lane l is result row
+// 8(r/4) + 4(l/32) + r%4, column l%32).  K is staged 16 at a time (one MFMA
+// k-step per LDS stage), which lets a 256-row tile double-buffer three planes
+// of both operands in LDS.
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
+void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
+                            const __bf16* __restrict__ B, long ldb, long b_plane,
+                            int M, int N, int K, Store store, OutMap mp,
+                            int tiles_m, int tiles_n, int per_xcd, int vec)
+{
+    using SP = SplitProducts<NPROD>;
+    typedef float f16v __attribute__((ext_vector_type(16)));
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    constexpr int NPL = SP::planes;
+    constexpr int BK = 16;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    constexpr int WM = BM / WAVES_M;
+    constexpr int WN = BN / WAVES_N;
+    constexpr int FM = WM / 32;
+    constexpr int FN = WN / 32;
+    constexpr int LDK = BK + 8;           // 48-byte LDS rows: 16-byte aligned, conflict-free 16-byte reads
+    constexpr int CPR = BK / 8;           // 16-byte chunks per tile row
+    constexpr int A_CH = (BM * CPR + NT - 1) / NT;   // chunks per thread (the last pass may be partial)
+    constexpr int B_CH = (BN * CPR + NT - 1) / NT;
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be whole 32x32 fragments");
+
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][NPL][BM * LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NPL][BN * LDK];
+
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * per_xcd + (bid >> 3);
+    if (tile >= tiles_m * tiles_n) return;
+    const int tm = tile / tiles_n;
+    const int tn = tile - tm * tiles_n;
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WAVES_N;
+    const int wn = wave - wm * WAVES_N;
+
+    static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
+    u4 ra[PF][NPL][A_CH], rb[PF][NPL][B_CH];
+
+    auto fetch = [&](const __bf16* base, long ld, long pstride, int nrows, int row, int k, u4 (&dst)[NPL]) {
+        if (row < nrows && vec && k + 8 <= K) {
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+                dst[pl] = *reinterpret_cast<const u4*>(base + pl * pstride + (long)row * ld + k);
+        } else {
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) {
+                unsigned short e[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    __bf16 v = (__bf16)0.0f;
+                    if (row < nrows && k + q < K) v = base[pl * pstride + (long)row * ld + k + q];
+                    e[q] = __builtin_bit_cast(unsigned short, v);
+                }
+                dst[pl] = u4{e[0] | (unsigned)e[1] << 16, e[2] | (unsigned)e[3] << 16,
+                             e[4] | (unsigned)e[5] << 16, e[6] | (unsigned)e[7] << 16};
+            }
+        }
+    };
+    auto load_tile = [&](int k0, auto set) {
+        constexpr int S = decltype(set)::value;
+#pragma unroll
+        for (int i = 0; i < A_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+            u4 t[NPL];
+            fetch(A, lda, a_plane, c < BM * CPR ? M : 0, m0 + row, k0 + 8 * kc, t);
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) ra[S][pl][i] = t[pl];
+        }
+#pragma unroll
+        for (int i = 0; i < B_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+            u4 t[NPL];
+            fetch(B, ldb, b_plane, c < BN * CPR ? N : 0, n0 + row, k0 + 8 * kc, t);
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) rb[S][pl][i] = t[pl];
+        }
+    };
+    auto store_tile = [&](int buf, auto set) {
+        constexpr int S = decltype(set)::value;
+#pragma unroll
+        for (int i = 0; i < A_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+            if (c < BM * CPR)
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&As[buf][pl][row * LDK + 8 * kc]) = ra[S][pl][i];
+        }
+#pragma unroll
+        for (int i = 0; i < B_CH; ++i) {
+            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
+            if (c < BN * CPR)
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&Bs[buf][pl][row * LDK + 8 * kc]) = rb[S][pl][i];
+        }
+    };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, PF - 1>;
+
+    f16v acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int frow = lane & 31;
+    const int fk = lane >> 5;   // which 8-element half of the 16-wide k step
+
+    auto compute = [&](int buf) {
+        bf16x8 a[NPL][FM], b[NPL][FN];
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[pl][i] = *reinterpret_cast<const bf16x8*>(&As[buf][pl][(wm * WM + i * 32 + frow) * LDK + 8 * fk]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[pl][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][pl][(wn * WN + j * 32 + frow) * LDK + 8 * fk]);
+        }
+#pragma unroll
+        for (int pr = NPROD - 1; pr >= 0; --pr)   // smallest products first
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[SP::a(pr)][i], b[SP::b(pr)][j], acc[i][j],
+                                                                        0, 0, 0);
+    };
+
+    const int nk = (K + BK - 1) / BK;
+    load_tile(0, S0{});
+    store_tile(0, S0{});
+    if constexpr (PF == 1) {
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            if (kt + 1 < nk) load_tile((kt + 1) * BK, S0{});
+            compute(buf);
+            if (kt + 1 < nk) store_tile(buf ^ 1, S0{});
+            __syncthreads();
+        }
+    } else {
+        // two stages in flight: stage kt+1 waits in register set (kt+1)&1 while
+        // stage kt+2 is being fetched into the other set
+        if (nk > 1) load_tile(BK, S1{});
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            if (kt + 2 < nk) load_tile((kt + 2) * BK, S0{});
+            compute(0);
+            if (kt + 1 < nk) store_tile(1, S1{});
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            if (kt + 3 < nk) load_tile((kt + 3) * BK, S1{});
+            compute(1);
+            if (kt + 2 < nk) store_tile(0, S0{});
+            __syncthreads();
+        }
+    }
+
+    long coff[FN];
+    bool cin[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn * WN + j * 32 + frow;
+        cin[j] = n < N;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * fk + (r & 3);
+            if (m >= M) continue;
+            const long roff = map_row(mp, (unsigned)m);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+        }
+    }
+}
+
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE>
+static hipError_t run_gemm_p32(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
+                               const Store& st, const OutMap& mp, hipStream_t stream)
+{
+    const int tiles_m = (M + BM - 1) / BM;
+    const int tiles_n = (N + BN - 1) / BN;
+    const long tiles = (long)tiles_m * tiles_n;
+    const int per_xcd = (int)((tiles + 7) / 8);
+    const long grid = 8L * per_xcd;
+    if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
+                     ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
+    hipLaunchKernelGGL((gemm_nt_bf16p32_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, PF, ROLE>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
+                       static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
+                       per_xcd, vec ? 1 : 0);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launcher
 
 template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int ROLE>
@@ -447,8 +675,17 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                            const Store& st, const OutMap& map, int products, hipStream_t stream)
 {
     (void)products;
-    if (A.fmt == Fmt::BF16x2) return run_gemm_planes<3, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
-    if (A.fmt == Fmt::BF16x3) return run_gemm_planes<6, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+    if (A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3) {
+        // narrow outputs (T' has N = D') take a 64-wide tile
+        const bool narrow = N <= 64;
+        if (A.fmt == Fmt::BF16x2)
+            return narrow ? run_gemm_p32<3, 256, 64, 4, 1, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
+                          : run_gemm_p32<3, HOTRG_BF16_BM, HOTRG_BF16_BN, HOTRG_BF16_WM, HOTRG_BF16_WN, HOTRG_BF16_PF,
+                                         ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+        return narrow ? run_gemm_p32<6, 256, 64, 4, 1, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
+                      : run_gemm_p32<6, HOTRG_BF16_BM, HOTRG_BF16_BN, HOTRG_BF16_WM, HOTRG_BF16_WN, HOTRG_BF16_PF,
+                                     ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+    }
     switch (A.fmt) {
         case Fmt::F64:
             return run_gemm<double, 128, 128, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
