@@ -25,6 +25,7 @@ CPU oracle on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,8 +36,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+TRAFFIC_PROFILE = {"bf16x6": os.path.join(ROOT, "profiles", "gemm_y_bf16x6_ising_d48_traffic.md")}
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 6}
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc"}
+
+
+def measured_traffic(precision: str, dmax: int, nsteps: int):
+    """HBM bytes per Y launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary of this workload, or None when there is none or when the product
+    kernel's source has changed since the counters were taken."""
+    path = TRAFFIC_PROFILE.get(precision)
+    if path is None or dmax != 48 or nsteps != 30 or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        key, sep, val = line.strip().partition(":")
+        if sep and key in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            fields[key] = val.strip()
+    src = os.path.join(ROOT, "paper_2602_05900_amd", "csrc", "gemm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(dmax: int, nsteps_sample: int, temperature: float):
@@ -94,6 +116,7 @@ def main():
     flops_solve = accounting.solve_flops(2, args.dmax, args.nsteps)
     dims = accounting.step_dims(2, 2, args.dmax, args.nsteps)
     y_flops = sum(accounting.stage_flops(*d)["y"] for d in dims)
+    y_bytes = sum(accounting.y_bytes(*d, ELEM_BYTES[args.precision]) for d in dims)
 
     def batch(first, count):
         return [workloads.Request(rid=first + i, arrival=0.0, model="ising", q=2,
@@ -198,7 +221,9 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": hw_achieved / peak if hw_achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(args.precision, args.dmax, args.nsteps),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": y_bytes / args.nsteps,
             "algorithmic_flops_per_solve": y_flops,
             "hardware_flops_factor": PRODUCTS[args.precision],
             "measured": "HIP events around each Y launch of one solve run alone on its stream",
