@@ -141,6 +141,20 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p);
  * ESTATE (handle already failed), EHIP. */
 int hotrg_coarse_grain(hotrg_solve* s, int nsteps);
 
+/* Serving form of hotrg_coarse_grain for a group of independent solves:
+ * enqueues nsteps steps on each of the count handles in solves[], step by
+ * step across the group (step 1 of every handle, then step 2, ...), each on
+ * its own handle's stream, so that solves on different streams overlap on
+ * the device.  Each handle continues its own alternation; the result of
+ * every solve is the same as from hotrg_coarse_grain alone.  The array is
+ * read, not kept.  A handle listed twice advances twice.
+ * Errors: EINVAL (solves NULL with count > 0, a NULL entry, count < 0,
+ * nsteps < 0, or a handle whose total would exceed its max_steps; nothing
+ * is enqueued then), ESTATE (a listed handle has already failed; nothing is
+ * enqueued), EHIP (enqueueing failed part-way: the handles already advanced
+ * keep their steps, see hotrg_log_z of each). */
+int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps);
+
 /* Synchronises the stream and returns ln Z / N of the torus reached so far:
  *   ln Z/N = ln c_0 + sum_n ln(c_n) / 2^n + ln(sum_{x,y} T[x,x,y,y]) / 2^n_steps
  * lnz_per_site receives that value, log2_sites (may be NULL) the number of

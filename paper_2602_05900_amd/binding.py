@@ -26,7 +26,8 @@ MAX_STEPS = 60
 STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm"]
 
 EXPORTS = [
-    "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain", "hotrg_log_z",
+    "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain",
+    "hotrg_coarse_grain_batch", "hotrg_log_z",
     "hotrg_step_info", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
@@ -73,6 +74,7 @@ def load() -> ctypes.CDLL:
     lib.hotrg_init_tensor.argtypes = [P(Params), c_void_p, c_size_t, c_void_p, P(c_void_p)]
     lib.hotrg_reset.argtypes = [c_void_p, P(Params)]
     lib.hotrg_coarse_grain.argtypes = [c_void_p, c_int]
+    lib.hotrg_coarse_grain_batch.argtypes = [P(c_void_p), c_int, c_int]
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
     lib.hotrg_eig_info.argtypes = [c_void_p, c_int, P(c_int), P(c_int), P(c_double)]
@@ -238,6 +240,14 @@ class Solve:
             self.close()
         except Exception:
             pass
+
+
+def coarse_grain_batch(solves, nsteps: int) -> None:
+    """Advance every Solve in `solves` by nsteps, step by step across the
+    group, each on its own stream (hotrg_coarse_grain_batch)."""
+    lib = load()
+    handles = (ctypes.c_void_p * max(len(solves), 1))(*[s._h.value for s in solves])
+    _check(lib.hotrg_coarse_grain_batch(handles, len(solves), int(nsteps)), "hotrg_coarse_grain_batch")
 
 
 def gemm_nt(A, B, C, M, N, K, lda, ldb, out_map, precision: str = "fp64", alpha: float = 1.0, stream=None):

@@ -464,6 +464,27 @@ int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
     return HOTRG_OK;
 }
 
+int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps) {
+    if (count < 0 || nsteps < 0 || (count > 0 && !solves)) return HOTRG_EINVAL;
+    // validate the whole group before enqueueing anything; a handle listed
+    // k times needs room for k * nsteps more steps
+    for (int i = 0; i < count; ++i) {
+        hotrg_solve* s = solves[i];
+        if (!s) return HOTRG_EINVAL;
+        int times = 0;
+        for (int j = 0; j < count; ++j) times += solves[j] == s;
+        if (s->steps + (long)times * nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
+    }
+    for (int i = 0; i < count; ++i)
+        if (solves[i]->host_status) return HOTRG_ESTATE;
+    for (int n = 0; n < nsteps; ++n)
+        for (int i = 0; i < count; ++i) {
+            const int rc = enqueue_step(solves[i]);
+            if (rc) return rc;
+        }
+    return HOTRG_OK;
+}
+
 int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites) {
     if (!s || !lnz_per_site) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;

@@ -131,19 +131,23 @@ class Server:
             self.active.append(a)
 
     def _advance(self) -> bool:
-        """Enqueue at most one step per active solve; returns True if any was enqueued."""
-        progressed = False
+        """Enqueue at most one step per active solve, as one grouped call over
+        the solves that have room; returns True if any step was enqueued."""
+        ready = []
         for a in self.active:
             while a.events and a.events[0].query():
                 a.events.popleft()
             if a.enqueued < a.req.nsteps and len(a.events) < self.depth:
-                a.solve.coarse_grain(1)
-                a.enqueued += 1
-                ev = torch.cuda.Event()
-                ev.record(a.stream)
-                a.events.append(ev)
-                progressed = True
-        return progressed
+                ready.append(a)
+        if not ready:
+            return False
+        binding.coarse_grain_batch([a.solve for a in ready], 1)
+        for a in ready:
+            a.enqueued += 1
+            ev = torch.cuda.Event()
+            ev.record(a.stream)
+            a.events.append(ev)
+        return True
 
     def _complete(self):
         still = []

@@ -88,6 +88,11 @@ def test_host_error_paths_without_device(lib):
     assert lib.hotrg_init_tensor(ctypes.byref(p), None, 0, None, ctypes.byref(h)) == binding.EINVAL
     assert lib.hotrg_init_tensor(None, None, 0, None, ctypes.byref(h)) == binding.EINVAL
     assert lib.hotrg_coarse_grain(None, 1) == binding.EINVAL
+    assert lib.hotrg_coarse_grain_batch(None, 1, 1) == binding.EINVAL
+    assert lib.hotrg_coarse_grain_batch(None, -1, 1) == binding.EINVAL
+    assert lib.hotrg_coarse_grain_batch(None, 0, 1) == binding.OK       # empty group: nothing to do
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert lib.hotrg_coarse_grain_batch(nulls, 2, 1) == binding.EINVAL
     v = ctypes.c_double()
     assert lib.hotrg_log_z(None, ctypes.byref(v), None) == binding.EINVAL
     lib.hotrg_destroy(None)

@@ -47,6 +47,8 @@ def fake_device(monkeypatch):
     import torch
     monkeypatch.setattr(serve.binding, "load", lambda: None)
     monkeypatch.setattr(serve.binding, "Solve", FakeSolve)
+    monkeypatch.setattr(serve.binding, "coarse_grain_batch",
+                        lambda solves, n: [s.coarse_grain(n) for s in solves])
     # footprint grows like D^5 (bytes), as the real sizing does
     monkeypatch.setattr(serve.binding, "workspace_bytes",
                         lambda **kw: 16 * kw["dmax"] ** 5 + 1000 * kw["max_steps"])
