@@ -38,6 +38,9 @@
 #define HOTRG_BF16_WN 2
 #define HOTRG_BF16_PF 1
 #endif
+#ifndef HOTRG_BF16_DMA
+#define HOTRG_BF16_DMA 1
+#endif
 
 namespace hotrg {
 
@@ -652,6 +655,209 @@ static hipError_t run_gemm_p32(const Buf& A, long lda, const Buf& B, long ldb, i
     return hipGetLastError();
 }
 
+// Same product with the operand tiles moved by the load unit straight into
+// LDS (global_load_lds_dwordx4: no staging registers, no ds_write), three K
+// stages in flight.  Each 16-byte load instruction of a wave fills one
+// contiguous KiB of LDS, 32 tile rows of 32 bytes (two 8-element k chunks);
+// which global chunk a lane fetches is XOR-swizzled by the row so that the
+// 32x32x16 fragment reads (32 rows, one chunk each) hit distinct banks.
+// Stage s of K step kt is one of three separate LDS arrays (kt mod 3), so
+// that the compiler can tell a fragment read of one stage from the loads in
+// flight into another and need not wait for those.
+//
+// Per K step: wait until this wave's loads of step kt have landed (those of
+// kt + 1 stay in flight), barrier (every wave's part of stage kt is in LDS,
+// and every wave has finished reading stage kt - 1), issue the loads of
+// step kt + 2 into the stage of kt - 1, multiply stage kt.
+//
+// Needs K a multiple of 16 and 16-byte aligned rows and planes; rows past M
+// or N are clamped to the last row (their results are never stored).
+__device__ __forceinline__ int lds_swz(int r) { return ((r >> 2) ^ (r >> 3)) & 1; }
+
+// 16 zero bytes: the source of every lane's load in a padding K step
+__device__ __attribute__((aligned(16))) const unsigned int kZeroChunk[4] = {0u, 0u, 0u, 0u};
+
+template <int N>
+__device__ __forceinline__ void wait_vmem_le() {
+    static_assert(N >= 0 && N < 16, "vmcnt immediate");
+    // gfx9 s_waitcnt: vmcnt[3:0] = N, expcnt[6:4] = 7 (no wait), lgkmcnt[11:8] = 0
+    __builtin_amdgcn_s_waitcnt(N | (7 << 4));
+}
+
+__device__ __forceinline__ void stage_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
+void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
+                            const __bf16* __restrict__ B, long ldb, long b_plane,
+                            int M, int N, int K, Store store, OutMap mp,
+                            int tiles_m, int tiles_n, int per_xcd)
+{
+    using SP = SplitProducts<NPROD>;
+    typedef float f16v __attribute__((ext_vector_type(16)));
+    typedef __attribute__((address_space(3))) void lds_void;
+    constexpr int NPL = SP::planes;
+    constexpr int BK = 16;
+    constexpr int NW = WAVES_M * WAVES_N;
+    constexpr int WM = BM / WAVES_M;
+    constexpr int WN = BN / WAVES_N;
+    constexpr int FM = WM / 32;
+    constexpr int FN = WN / 32;
+    constexpr int A_BLK = BM / 32;                 // 32-row blocks: one wave load per plane
+    constexpr int B_BLK = BN / 32;
+    constexpr int NLOAD = NPL * (A_BLK + B_BLK);   // wave loads per K step
+    constexpr int LPW = NLOAD / NW;                // per wave
+    constexpr int A_EL = BM * BK;                  // elements of one plane of the A tile
+    constexpr int B_EL = BN * BK;
+    constexpr int STAGE = NPL * (A_EL + B_EL);
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be whole 32x32 fragments");
+    static_assert(NLOAD % NW == 0, "tile loads must divide evenly over the waves");
+
+    __shared__ __attribute__((aligned(1024))) __bf16 S0[STAGE];
+    __shared__ __attribute__((aligned(1024))) __bf16 S1[STAGE];
+    __shared__ __attribute__((aligned(1024))) __bf16 S2[STAGE];
+
+    const int bid = blockIdx.x;
+    const int tile = (bid & 7) * per_xcd + (bid >> 3);
+    if (tile >= tiles_m * tiles_n) return;
+    const int tm = tile / tiles_n;
+    const int tn = tile - tm * tiles_n;
+    const int m0 = tm * BM;
+    const int n0 = tn * BN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WAVES_N;
+    const int wn = wave - wm * WAVES_N;
+
+    // this wave's loads of one K step: per load j, this lane's source row
+    // start (with its swizzled k chunk) and the LDS offset of the KiB it fills
+    const int lrow = lane >> 1;
+    const __bf16* gsrc[LPW];
+    int dsto[LPW];
+#pragma unroll
+    for (int j = 0; j < LPW; ++j) {
+        const int idx = wave + j * NW;
+        const bool isA = idx < NPL * A_BLK;
+        const int li = isA ? idx : idx - NPL * A_BLK;
+        const int blocks = isA ? A_BLK : B_BLK;
+        const int pl = li / blocks;
+        const int rb = li - pl * blocks;
+        const int rloc = rb * 32 + lrow;
+        const int c = (lane & 1) ^ lds_swz(rloc);
+        const int row = isA ? min(m0 + rloc, M - 1) : min(n0 + rloc, N - 1);
+        gsrc[j] = (isA ? A + pl * a_plane + (long)row * lda : B + pl * b_plane + (long)row * ldb) + 8 * c;
+        dsto[j] = (isA ? pl * A_EL : NPL * A_EL + pl * B_EL) + rb * 32 * BK;
+    }
+    // padding K steps (past K) load zeros: every lane reads the same 16 bytes
+    const __bf16* zsrc = reinterpret_cast<const __bf16*>(kZeroChunk);
+    auto issue = [&](__bf16* S, int k0) {
+        const bool pad = k0 >= K;
+#pragma unroll
+        for (int j = 0; j < LPW; ++j) {
+            const __bf16* g = pad ? zsrc : gsrc[j] + k0;
+            __builtin_amdgcn_global_load_lds(g, (lds_void*)(S + dsto[j]), 16, 0, 0);
+        }
+    };
+
+    f16v acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int frow = lane & 31;
+    const int fk = lane >> 5;
+    auto compute = [&](const __bf16* S) {
+        bf16x8 a[NPL][FM], b[NPL][FN];
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int r = wm * WM + i * 32 + frow;
+                a[pl][i] = *reinterpret_cast<const bf16x8*>(S + pl * A_EL + (2 * r + (fk ^ lds_swz(r))) * 8);
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int r = wn * WN + j * 32 + frow;
+                b[pl][j] = *reinterpret_cast<const bf16x8*>(S + NPL * A_EL + pl * B_EL + (2 * r + (fk ^ lds_swz(r))) * 8);
+            }
+        }
+#pragma unroll
+        for (int pr = NPROD - 1; pr >= 0; --pr)   // smallest products first
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[SP::a(pr)][i], b[SP::b(pr)][j], acc[i][j],
+                                                                        0, 0, 0);
+    };
+
+    // K steps padded to a multiple of 3 (the padding steps load zeros), so
+    // the loop body is branch-free: every step waits for the same count and
+    // issues the loads two steps ahead
+    const int nk = (K / BK + 2) / 3 * 3;
+    auto step = [&](const __bf16* cur, __bf16* next2, int kt) {
+        wait_vmem_le<LPW>();
+        stage_barrier();
+        issue(next2, (kt + 2) * BK);
+        compute(cur);
+    };
+    issue(S0, 0);
+    issue(S1, BK);
+    for (int kt = 0; kt < nk; kt += 3) {
+        step(S0, S2, kt);
+        step(S1, S0, kt + 1);
+        step(S2, S1, kt + 2);
+    }
+    wait_vmem_le<0>();   // the last two stages' loads must land before the workgroup's LDS is released
+
+    long coff[FN];
+    bool cin[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn * WN + j * 32 + frow;
+        cin[j] = n < N;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * fk + (r & 3);
+            if (m >= M) continue;
+            const long roff = map_row(mp, (unsigned)m);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+        }
+    }
+}
+
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
+static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
+                               const Store& st, const OutMap& mp, hipStream_t stream)
+{
+    const int tiles_m = (M + BM - 1) / BM;
+    const int tiles_n = (N + BN - 1) / BN;
+    const long tiles = (long)tiles_m * tiles_n;
+    const int per_xcd = (int)((tiles + 7) / 8);
+    const long grid = 8L * per_xcd;
+    if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
+                       dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
+                       static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
+                       per_xcd);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launcher
 
 template <typename T, int BM, int BN, int BK, int WAVES_M, int WAVES_N, int ROLE>
@@ -678,6 +884,14 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
     if (A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3) {
         // narrow outputs (T' has N = D') take a 64-wide tile
         const bool narrow = N <= 64;
+#if HOTRG_BF16_DMA
+        const bool dma = !narrow && K >= 16 && K % 16 == 0 && lda % 8 == 0 && ldb % 8 == 0 &&
+                         (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 &&
+                         ((uintptr_t)B.ptr & 15) == 0;
+        if (dma)
+            return A.fmt == Fmt::BF16x2 ? run_gemm_dma<3, 256, 256, 4, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
+                                        : run_gemm_dma<6, 256, 256, 4, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+#endif
         if (A.fmt == Fmt::BF16x2)
             return narrow ? run_gemm_p32<3, 256, 64, 4, 1, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
                           : run_gemm_p32<3, HOTRG_BF16_BM, HOTRG_BF16_BN, HOTRG_BF16_WM, HOTRG_BF16_WN, HOTRG_BF16_PF,

@@ -44,6 +44,9 @@ GEMM_CASES = [
     # (M, N, K)
     (1, 1, 1), (16, 16, 4), (17, 33, 5), (128, 128, 16), (129, 130, 47),
     (300, 64, 576), (64, 300, 9), (4, 2304, 48), (2304, 48, 2304), (1000, 257, 0),
+    # K a multiple of 16 and N > 64: the BF16 products stream tiles into LDS
+    # directly; K steps 10 -> 12 and 2 -> 3 exercise the zero padding
+    (257, 300, 160), (70, 1000, 32), (600, 520, 2304),
 ]
 
 
