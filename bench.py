@@ -18,7 +18,10 @@ FP64).  Also reported: the same batch in FP64, per-solve service time
 p50/p99, per-stage GPU times from HIP events, |delta f| against the FP64
 oracle's stored values for these temperatures, the roofline of the dominant
 kernel (the Y product, measured on one solve running alone) and the FP64
-CPU oracle on a bounded sample.
+CPU oracle on a bounded sample.  Two further workloads are measured and
+reported beside the headline (not in `value`): a D = 24 FP64 scan of 64
+temperatures with the finite-difference internal energy against Onsager
+("c2"), and one D = 64, 40-step solve at Tc in BF16x6 and in FP64 ("c5").
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6] [--concurrency C]
 """
@@ -61,6 +64,89 @@ def measured_traffic(precision: str, dmax: int, nsteps: int):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def fd_energy(temps, lnz):
+    """u(T) = T^2 d(ln Z/N)/dT on a uniform grid: central differences inside,
+    second-order one-sided differences at the ends."""
+    h = temps[1] - temps[0]
+    d = [0.0] * len(lnz)
+    for i in range(1, len(lnz) - 1):
+        d[i] = (lnz[i + 1] - lnz[i - 1]) / (2 * h)
+    d[0] = (-3 * lnz[0] + 4 * lnz[1] - lnz[2]) / (2 * h)
+    d[-1] = (3 * lnz[-1] - 4 * lnz[-2] + lnz[-3]) / (2 * h)
+    return [t * t * g for t, g in zip(temps, d)]
+
+
+def onsager_reference():
+    path = os.path.join(ROOT, "tests", "golden", "onsager_ising.json")
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def run_c2(serve, accounting, workloads, budget):
+    """Ising, D = 24, 30 steps, FP64, 64 temperatures in [1.8, 2.8] one after
+    another: throughput, f against Onsager, and the finite-difference internal
+    energy against Onsager's u."""
+    import numpy as np
+    temps = [float(t) for t in np.linspace(1.8, 2.8, 64)]
+    reqs = [workloads.Request(rid=i, arrival=0.0, model="ising", q=2, temperature=t, dmax=24, nsteps=30)
+            for i, t in enumerate(temps)]
+    server = serve.Server(slots=1, budget=budget, precision="fp64", device="cuda:0")
+    server.run(reqs[:1], realtime=False)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = server.run(reqs, realtime=False)
+    wall = time.perf_counter() - t0
+    lnz = [c.lnz_per_site for c in sorted(done, key=lambda c: c.rid)]
+    u = fd_energy(temps, lnz)
+    out = {"workload": "Ising J=1, D=24, 30 steps, FP64, T = linspace(1.8, 2.8, 64), one solve at a time",
+           "solves": len(done), "seconds": wall,
+           "tflops": len(done) * accounting.solve_flops(2, 24, 30) / wall / 1e12}
+    ref = onsager_reference()
+    if ref:
+        g = ref["grid"]
+        tc = ref["critical"]["temperature"]
+        far = [abs(t - tc) > 0.1 for t in temps]
+        df = [abs(a - b) / abs(b) for a, b in zip(lnz, g["lnz_per_site"])]
+        du = [abs(a - b) for a, b in zip(u, g["energy"])]
+        du_grid = [abs(a - b) for a, b in zip(g["energy_fd_of_exact_lnz"], g["energy"])]
+        out.update({
+            "max_rel_df_vs_onsager": max(df),
+            "max_rel_df_vs_onsager_off_critical": max(d for d, f in zip(df, far) if f),
+            "max_abs_du_fd_vs_onsager_off_critical": max(d for d, f in zip(du, far) if f),
+            "max_abs_du_fd_vs_onsager": max(du),
+            "fd_discretisation_error_off_critical": max(d for d, f in zip(du_grid, far) if f),
+        })
+    return out
+
+
+def run_c5(binding, accounting):
+    """Ising at Tc, D = 64, 40 steps, one solve in BF16x6 and one in FP64 on
+    the same GPU: throughput and |delta f| between them and against Onsager."""
+    import torch
+    ref = onsager_reference()
+    tc = ref["critical"]["temperature"] if ref else 2.269185314213022
+    flops = accounting.solve_flops(2, 64, 40)
+    out = {"workload": "Ising J=1 at Tc, D=64, 40 steps, one solve per precision"}
+    lnz = {}
+    for prec in ("bf16x6", "fp64"):
+        s = binding.Solve(model="ising", q=2, temperature=tc, dmax=64, precision=prec, max_steps=40)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.coarse_grain(40)
+        lnz[prec] = s.log_z()
+        dt = time.perf_counter() - t0
+        s.close()
+        out[prec] = {"seconds": dt, "tflops": flops / dt / 1e12, "lnz_per_site": lnz[prec]}
+        if ref:
+            out[prec]["rel_df_vs_onsager"] = abs(lnz[prec] - ref["critical"]["lnz_per_site"]) / \
+                ref["critical"]["lnz_per_site"]
+        del s
+        torch.cuda.empty_cache()
+    out["rel_df_bf16x6_vs_fp64"] = abs(lnz["bf16x6"] - lnz["fp64"]) / abs(lnz["fp64"])
+    out["speedup_bf16x6_vs_fp64"] = out["fp64"]["seconds"] / out["bf16x6"]["seconds"]
+    return out
+
+
 def cpu_baseline(dmax: int, nsteps_sample: int, temperature: float):
     """The FP64 oracle, as it stands, on the first steps of one solve of the
     same workload (steps 1..nsteps_sample; the last is a full D^7 step)."""
@@ -100,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--concurrency", type=int, default=4, help="solves in flight (streams)")
     ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
+    ap.add_argument("--no-c2", dest="c2", action="store_false", help="skip the D=24 temperature scan")
+    ap.add_argument("--no-c5", dest="c5", action="store_false", help="skip the D=64 solve")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -235,6 +323,12 @@ def main():
         "rel_err_vs_fp64_oracle": errs or None,
         "fp64_comparison": cmp,
     }
+    if args.c2:
+        print("# C2: D=24 scan ...", file=sys.stderr, flush=True)
+        line["c2"] = run_c2(serve, accounting, workloads, args.budget_gb << 30)
+    if args.c5:
+        print("# C5: D=64 ...", file=sys.stderr, flush=True)
+        line["c5"] = run_c5(binding, accounting)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))

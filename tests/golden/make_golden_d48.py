@@ -2,7 +2,7 @@
 2D Ising model at D = 48 after 30 steps, at the 16 temperatures of the
 benchmark (numpy.linspace(2.0, 2.5, 16)).  Calls oracle/ only.
 
-    python tests/golden/make_golden_d48.py      (~1 min per temperature, 8 cores)
+    python tests/golden/make_golden_d48.py      (about 5 min per temperature on 8 cores)
 """
 import json
 import os

@@ -280,3 +280,26 @@ def test_errors_are_reported(gpu_lib):
         s.coarse_grain(binding.MAX_STEPS + 1)
     with pytest.raises(binding.HotrgError):
         s.step_info(1)   # no step taken yet
+
+
+def test_c2_internal_energy_by_finite_differences(gpu_lib):
+    """Ising, D = 24, 30 steps on the 64-point grid in [1.8, 2.8]: ln Z/N
+    against Onsager, and u = T^2 d(ln Z/N)/dT by finite differences against
+    Onsager's u.  Away from Tc the difference is the grid's discretisation
+    error (<= 3.4e-4 for the exact ln Z itself) plus HOTRG's small error."""
+    from paper_2602_05900_amd import binding
+    T = np.linspace(1.8, 2.8, 64)
+    lnz = []
+    for t in T:
+        s = gpu_solve(gpu_lib, 30, model="ising", q=2, temperature=float(t), dmax=24, max_steps=30)
+        lnz.append(s.log_z())
+        s.close()
+    lnz = np.array(lnz)
+    u = exact.finite_difference_energy(T, lnz)
+    u_exact = np.array([exact.onsager_energy(float(t)) for t in T])
+    lnz_exact = np.array([exact.onsager_lnz(float(t)) for t in T])
+    far = np.abs(T - exact.ISING_TC) > 0.1
+    assert np.max(np.abs(lnz - lnz_exact)[far] / lnz_exact[far]) < 1e-6
+    assert np.max(np.abs(u - u_exact)[far]) < 1e-3
+    # near Tc the finite differences of the exact ln Z are off by 3.2e-3 too
+    assert np.max(np.abs(u - u_exact)) < 1e-2

@@ -57,3 +57,27 @@ def test_d48_full_size_step_reduced_precision(gpu_lib, precision, tol):
     if st.trunc.cut_gap > 1e-6:
         G = s.tensor()
         assert np.max(np.abs(G - st.T_next)) <= tol
+
+
+def test_c5_d64_bf16x6_against_fp64_and_onsager(gpu_lib):
+    """Ising at Tc, D = 64, 40 steps (n = 4096 environments): BF16x6 within
+    its claim of the FP64 path on the same GPU; both near Onsager's exact
+    value (the HOTRG truncation error, largest at Tc); the eigensolver meets
+    its residual bound at every step."""
+    import torch
+    from paper_2602_05900_amd import binding
+    Tc = exact.ISING_TC
+    lnz = {}
+    for prec in ("fp64", "bf16x6"):
+        s = binding.Solve(model="ising", q=2, temperature=Tc, dmax=64, precision=prec, max_steps=40)
+        s.coarse_grain(40)
+        lnz[prec] = s.log_z()
+        for n in range(1, 41):
+            it, sweeps, res = s.eig_info(n)
+            assert res <= 1e-12 and it < 30, (prec, n, it, res)
+        s.close()
+        torch.cuda.empty_cache()
+    exact_tc = exact.onsager_lnz_tc()
+    print(f"D=64 Tc: fp64 {lnz['fp64']:.15f} bf16x6 {lnz['bf16x6']:.15f} onsager {exact_tc:.15f}")
+    assert rel(lnz["bf16x6"], lnz["fp64"]) <= CLAIM["bf16x6"]
+    assert rel(lnz["fp64"], exact_tc) < 1e-5

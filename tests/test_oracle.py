@@ -247,3 +247,18 @@ def test_step_dims_and_flops():
     dims = hotrg.step_dims(2, 2, 48, 8)
     assert [d[:2] for d in dims] == [(2, 2), (2, 4), (4, 4), (4, 16), (16, 16), (16, 48), (48, 48), (48, 48)]
     assert abs(hotrg.contraction_flops(48, 48, 48) - (2 * 48 ** 7 + 10 * 48 ** 6)) < 1
+
+
+def test_stored_onsager_grid_matches_the_oracle():
+    """tests/golden/onsager_ising.json (read by the benchmark) is what
+    oracle/exact.py gives now."""
+    import json
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "onsager_ising.json")
+    d = json.load(open(path))
+    g = d["grid"]
+    for i in (0, 17, 31, 63):
+        t = g["temperatures"][i]
+        assert abs(g["lnz_per_site"][i] - exact.onsager_lnz(t)) <= 1e-14
+        assert abs(g["energy"][i] - exact.onsager_energy(t)) <= 1e-12
+    assert abs(d["critical"]["lnz_per_site"] - exact.onsager_lnz_tc()) <= 1e-15
+    assert abs(d["critical"]["energy"] + math.sqrt(2.0)) <= 1e-15
