@@ -41,6 +41,10 @@
 #ifndef HOTRG_BF16_DMA
 #define HOTRG_BF16_DMA 1
 #endif
+#ifndef HOTRG_DMA_WM
+#define HOTRG_DMA_WM 4
+#define HOTRG_DMA_WN 2
+#endif
 
 namespace hotrg {
 
@@ -885,12 +889,27 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
         // narrow outputs (T' has N = D') take a 64-wide tile
         const bool narrow = N <= 64;
 #if HOTRG_BF16_DMA
-        const bool dma = !narrow && K >= 16 && K % 16 == 0 && lda % 8 == 0 && ldb % 8 == 0 &&
-                         (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 &&
-                         ((uintptr_t)B.ptr & 15) == 0;
-        if (dma)
-            return A.fmt == Fmt::BF16x2 ? run_gemm_dma<3, 256, 256, 4, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
-                                        : run_gemm_dma<6, 256, 256, 4, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+        const bool dma = K >= 16 && K % 16 == 0 && lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 &&
+                         (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
+        if (dma) {
+            // tile by the work available: 256 x 256 needs at least two rounds
+            // of workgroups over the 256 CUs to fill the chip; smaller
+            // products (half environments and E, N = K = D^2) take 128 x 128,
+            // narrow outputs (T', N = D') 128 x 64
+            const long big_tiles = (long)((M + 255) / 256) * ((N + 255) / 256);
+            if (A.fmt == Fmt::BF16x2) {
+                if (narrow) return run_gemm_dma<3, 128, 64, 2, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+                if (big_tiles < 512)
+                    return run_gemm_dma<3, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+                return run_gemm_dma<3, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
+                                                                                  stream);
+            }
+            if (narrow) return run_gemm_dma<6, 128, 64, 2, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+            if (big_tiles < 512)
+                return run_gemm_dma<6, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+            return run_gemm_dma<6, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
+                                                                              stream);
+        }
 #endif
         if (A.fmt == Fmt::BF16x2)
             return narrow ? run_gemm_p32<3, 256, 64, 4, 1, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)

@@ -44,9 +44,10 @@ GEMM_CASES = [
     # (M, N, K)
     (1, 1, 1), (16, 16, 4), (17, 33, 5), (128, 128, 16), (129, 130, 47),
     (300, 64, 576), (64, 300, 9), (4, 2304, 48), (2304, 48, 2304), (1000, 257, 0),
-    # K a multiple of 16 and N > 64: the BF16 products stream tiles into LDS
-    # directly; K steps 10 -> 12 and 2 -> 3 exercise the zero padding
-    (257, 300, 160), (70, 1000, 32), (600, 520, 2304),
+    # K a multiple of 16: the BF16 products stream tiles into LDS directly
+    # (128x64 for N <= 64, 128x128, and 256x256 from 512 such tiles up);
+    # K steps 10 -> 12 and 2 -> 3 exercise the zero padding
+    (257, 300, 160), (70, 1000, 32), (600, 520, 2304), (8192, 4096, 48),
 ]
 
 
