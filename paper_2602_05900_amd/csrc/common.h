@@ -26,17 +26,34 @@ inline size_t fmt_elem_bytes(Fmt f) { return fmt_plane_elem_bytes(f) * fmt_plane
 
 // A buffer of `count` logical elements in format `fmt`.  Planes of the
 // split formats are stored one after the other, `plane` elements apart.
+//
+// panel_k != 0 marks a matrix of rows x panel_k elements stored as 32 x 16
+// panels (BF16 formats only): element (r, c) at
+//   ((r / 32) * (panel_k / 16) + c / 16) * 512 + (r % 32) * 16 + c % 16,
+// so that the 32 rows x 16 columns a product kernel stages per K step are
+// one contiguous KiB.  Rows must be a multiple of 32, panel_k of 16.
 struct Buf {
     void* ptr;
     Fmt fmt;
-    size_t plane;  // elements between planes (>= count, rounded up)
+    size_t plane;      // elements between planes (>= count, rounded up)
+    long panel_k = 0;  // 0: row-major; else the row length of the panel layout
 };
 
+__host__ __device__ inline long panel_index(long r, long c, long panel_k) {
+    return ((r >> 5) * (panel_k >> 4) + (c >> 4)) * 512 + (r & 31) * 16 + (c & 15);
+}
+
 // Output map of the index-mapped product (see hotrg_gemm_nt in hotrg.h):
-//   off(m, n) = (m / sm) * rs_hi + (m % sm) * rs_lo + (n / sn) * cs_hi + (n % sn) * cs_lo
+//   R(m, n) = (m / sm) * rs_hi + (m % sm) * rs_lo + (n / sn) * cs_hi + (n % sn) * cs_lo
+// is the output offset when panel_k == 0.  With panel_k != 0 the output is
+// a panel-layout matrix (see Buf): R is its row and
+//   C(m, n) = (m / sm) * rc_hi + (m % sm) * rc_lo + (n / sn) * cc_hi + (n % sn) * cc_lo
+// its column, and the offset is panel_index(R, C, panel_k).
 struct OutMap {
     long sm, rs_hi, rs_lo;
     long sn, cs_hi, cs_lo;
+    long rc_hi = 0, rc_lo = 0, cc_hi = 0, cc_lo = 0;
+    long panel_k = 0;
 };
 
 // Which contraction of a step a product is (selects tiles; distinct symbols).

@@ -104,15 +104,25 @@ struct Store {
     }
 };
 
-__device__ __forceinline__ long map_row(const OutMap& mp, unsigned m) {
-    unsigned sm = (unsigned)mp.sm;
-    unsigned hi = m / sm;
-    return (long)hi * mp.rs_hi + (long)(m - hi * sm) * mp.rs_lo;
+// Row and column parts of the output map: r sums to the offset (or the
+// panel row), c to the panel column (zero for row-major maps).
+struct MapPart {
+    long r, c;
+};
+__device__ __forceinline__ MapPart map_row(const OutMap& mp, unsigned m) {
+    const unsigned sm = (unsigned)mp.sm;
+    const unsigned hi = m / sm;
+    const long lo = (long)(m - hi * sm);
+    return {(long)hi * mp.rs_hi + lo * mp.rs_lo, (long)hi * mp.rc_hi + lo * mp.rc_lo};
 }
-__device__ __forceinline__ long map_col(const OutMap& mp, unsigned n) {
-    unsigned sn = (unsigned)mp.sn;
-    unsigned hi = n / sn;
-    return (long)hi * mp.cs_hi + (long)(n - hi * sn) * mp.cs_lo;
+__device__ __forceinline__ MapPart map_col(const OutMap& mp, unsigned n) {
+    const unsigned sn = (unsigned)mp.sn;
+    const unsigned hi = n / sn;
+    const long lo = (long)(n - hi * sn);
+    return {(long)hi * mp.cs_hi + lo * mp.cs_lo, (long)hi * mp.cc_hi + lo * mp.cc_lo};
+}
+__device__ __forceinline__ long map_off(const OutMap& mp, const MapPart& row, const MapPart& col) {
+    return mp.panel_k ? panel_index(row.r + col.r, row.c + col.c, mp.panel_k) : row.r + col.r;
 }
 
 // ---------------------------------------------------------------- kernel
@@ -223,13 +233,13 @@ void gemm_nt_kernel(const T* __restrict__ A, long lda, const T* __restrict__ B, 
     }
 
     // epilogue: component r of each fragment holds row Op::row(lane/16, r), column lane%16
-    long coff[FN];
+    MapPart coff[FN];
     bool cin[FN];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int n = n0 + wn * WN + j * 16 + frow;
         cin[j] = n < N;
-        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
@@ -237,10 +247,10 @@ void gemm_nt_kernel(const T* __restrict__ A, long lda, const T* __restrict__ B, 
         for (int r = 0; r < 4; ++r) {
             const int m = m0 + wm * WM + i * 16 + Op::row(fk, r);
             if (m >= M) continue;
-            const long roff = map_row(mp, (unsigned)m);
+            const MapPart roff = map_row(mp, (unsigned)m);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+                if (cin[j]) store(map_off(mp, roff, coff[j]), acc[i][j][r]);
         }
     }
 }
@@ -266,190 +276,8 @@ template <> struct SplitProducts<6> {
 
 // Operands stored as bf16 planes (plane p of A at A + p * a_plane, rows of
 // length lda), the planes of one value summing to it (hi + lo or
-// hi + mid + lo, written by the producing kernels).  Tiles move global -> LDS
-// as 16-byte chunks (8 bf16) when the leading dimensions allow, else element
-// by element.  v_mfma_f32_16x16x32_bf16 fragments: lane l holds
-// A[l%16][8(l/16)..8(l/16)+7] and B[8(l/16)..+7][l%16]; result row
-// 4(l/16)+r, column l%16 in component r; FP32 accumulation.
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
-void gemm_nt_bf16planes_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
-                               const __bf16* __restrict__ B, long ldb, long b_plane,
-                               int M, int N, int K, Store store, OutMap mp,
-                               int tiles_m, int tiles_n, int per_xcd, int vec)
-{
-    using SP = SplitProducts<NPROD>;
-    constexpr int NPL = SP::planes;
-    constexpr int BK = 32;
-    constexpr int NT = 64 * WAVES_M * WAVES_N;
-    constexpr int WM = BM / WAVES_M;
-    constexpr int WN = BN / WAVES_N;
-    constexpr int FM = WM / 16;
-    constexpr int FN = WN / 16;
-    constexpr int LDK = BK + 8;           // 80-byte LDS rows: 16-byte aligned, conflict-free fragment reads
-    constexpr int CPR = BK / 8;           // 16-byte chunks per tile row
-    constexpr int A_CH = BM * CPR / NT;   // chunks per thread per plane
-    constexpr int B_CH = BN * CPR / NT;
-    static_assert(BM * CPR % NT == 0 && BN * CPR % NT == 0, "tile/threads mismatch");
-    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-
-    __shared__ __attribute__((aligned(16))) __bf16 As[2][NPL][BM * LDK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NPL][BN * LDK];
-
-    const int bid = blockIdx.x;
-    const int tile = (bid & 7) * per_xcd + (bid >> 3);
-    if (tile >= tiles_m * tiles_n) return;
-    const int tm = tile / tiles_n;
-    const int tn = tile - tm * tiles_n;
-    const int m0 = tm * BM;
-    const int n0 = tn * BN;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave / WAVES_N;
-    const int wn = wave - wm * WAVES_N;
-
-    u4 ra[NPL][A_CH], rb[NPL][B_CH];
-
-    auto fetch = [&](const __bf16* base, long ld, long pstride, int nrows, int row, int k, u4 (&dst)[NPL]) {
-        if (row < nrows && vec && k + 8 <= K) {
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl)
-                dst[pl] = *reinterpret_cast<const u4*>(base + pl * pstride + (long)row * ld + k);
-        } else {
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) {
-                unsigned short e[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    __bf16 v = (__bf16)0.0f;
-                    if (row < nrows && k + q < K) v = base[pl * pstride + (long)row * ld + k + q];
-                    e[q] = __builtin_bit_cast(unsigned short, v);
-                }
-                dst[pl] = u4{e[0] | (unsigned)e[1] << 16, e[2] | (unsigned)e[3] << 16,
-                             e[4] | (unsigned)e[5] << 16, e[6] | (unsigned)e[7] << 16};
-            }
-        }
-    };
-
-    auto load_tile = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < A_CH; ++i) {
-            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
-            u4 t[NPL];
-            fetch(A, lda, a_plane, M, m0 + row, k0 + 8 * kc, t);
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) ra[pl][i] = t[pl];
-        }
-#pragma unroll
-        for (int i = 0; i < B_CH; ++i) {
-            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
-            u4 t[NPL];
-            fetch(B, ldb, b_plane, N, n0 + row, k0 + 8 * kc, t);
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) rb[pl][i] = t[pl];
-        }
-    };
-    auto store_tile = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < A_CH; ++i) {
-            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&As[buf][pl][row * LDK + 8 * kc]) = ra[pl][i];
-        }
-#pragma unroll
-        for (int i = 0; i < B_CH; ++i) {
-            const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&Bs[buf][pl][row * LDK + 8 * kc]) = rb[pl][i];
-        }
-    };
-
-    f4 acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = f4{0, 0, 0, 0};
-
-    const int nk = (K + BK - 1) / BK;
-    load_tile(0);
-    store_tile(0);
-    __syncthreads();
-
-    const int frow = lane & 15;
-    const int fk = lane >> 4;   // 8-element k group of this lane
-
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) load_tile((kt + 1) * BK);
-        bf16x8 a[NPL][FM], b[NPL][FN];
-#pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-                a[pl][i] = *reinterpret_cast<const bf16x8*>(&As[buf][pl][(wm * WM + i * 16 + frow) * LDK + 8 * fk]);
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                b[pl][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][pl][(wn * WN + j * 16 + frow) * LDK + 8 * fk]);
-        }
-#pragma unroll
-        for (int pr = NPROD - 1; pr >= 0; --pr)   // smallest products first
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[SP::a(pr)][i], b[SP::b(pr)][j], acc[i][j],
-                                                                        0, 0, 0);
-        if (kt + 1 < nk) store_tile(buf ^ 1);
-        __syncthreads();
-    }
-
-    long coff[FN];
-    bool cin[FN];
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn * WN + j * 16 + frow;
-        cin[j] = n < N;
-        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
-    }
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = m0 + wm * WM + i * 16 + 4 * fk + r;
-            if (m >= M) continue;
-            const long roff = map_row(mp, (unsigned)m);
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
-        }
-    }
-}
-
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
-static hipError_t run_gemm_planes(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
-                                  const Store& st, const OutMap& mp, hipStream_t stream)
-{
-    const int tiles_m = (M + BM - 1) / BM;
-    const int tiles_n = (N + BN - 1) / BN;
-    const long tiles = (long)tiles_m * tiles_n;
-    const int per_xcd = (int)((tiles + 7) / 8);
-    const long grid = 8L * per_xcd;
-    if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
-                     ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
-    hipLaunchKernelGGL((gemm_nt_bf16planes_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
-                       dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
-                       static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
-                       per_xcd, vec ? 1 : 0);
-    return hipGetLastError();
-}
-
-
-// Same operands and split products as above, on v_mfma_f32_32x32x16_bf16
-// (twice the work per issued instruction of the 16x16x32 form; measured on
-// gfx950: lane l supplies A[l%32][8(l/32)..8(l/32)+7] and
+// hi + mid + lo, written by the producing kernels); products on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (measured on gfx950: lane l supplies A[l%32][8(l/32)..8(l/32)+7] and
 // B[8(l/32)..+7][l%32]; component r of lane l is result row
 // 8(r/4) + 4(l/32) + r%4, column l%32).  K is staged 16 at a time (one MFMA
 // k-step per LDS stage), which lets a 256-row tile double-buffer three planes
@@ -618,13 +446,13 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         }
     }
 
-    long coff[FN];
+    MapPart coff[FN];
     bool cin[FN];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int n = n0 + wn * WN + j * 32 + frow;
         cin[j] = n < N;
-        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
@@ -632,10 +460,10 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         for (int r = 0; r < 16; ++r) {
             const int m = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * fk + (r & 3);
             if (m >= M) continue;
-            const long roff = map_row(mp, (unsigned)m);
+            const MapPart roff = map_row(mp, (unsigned)m);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+                if (cin[j]) store(map_off(mp, roff, coff[j]), acc[i][j][r]);
         }
     }
 }
@@ -694,7 +522,7 @@ __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA, bool PB>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
 void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
                             const __bf16* __restrict__ B, long ldb, long b_plane,
@@ -742,8 +570,12 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     // this wave's loads of one K step: per load j, this lane's source row
     // start (with its swizzled k chunk) and the LDS offset of the KiB it fills
     const int lrow = lane >> 1;
+    // An operand in the panel layout (PA, PB: 32 x 16 panels, rows a
+    // multiple of 32, row length K) gives each wave load one contiguous KiB
+    // (32 cache lines per KiB become 8); the K step then advances by a panel.
     const __bf16* gsrc[LPW];
     int dsto[LPW];
+    int kmul[LPW];
 #pragma unroll
     for (int j = 0; j < LPW; ++j) {
         const int idx = wave + j * NW;
@@ -754,8 +586,17 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         const int rb = li - pl * blocks;
         const int rloc = rb * 32 + lrow;
         const int c = (lane & 1) ^ lds_swz(rloc);
-        const int row = isA ? min(m0 + rloc, M - 1) : min(n0 + rloc, N - 1);
-        gsrc[j] = (isA ? A + pl * a_plane + (long)row * lda : B + pl * b_plane + (long)row * ldb) + 8 * c;
+        const bool panel = isA ? PA : PB;
+        if (panel) {
+            const int last = ((isA ? M : N) + 31) / 32 - 1;
+            const int blk = min(((isA ? m0 : n0) >> 5) + rb, last);
+            gsrc[j] = (isA ? A + pl * a_plane : B + pl * b_plane) + (long)blk * (K >> 4) * 512 + lrow * 16 + 8 * c;
+            kmul[j] = 32;   // panel (k / 16) starts at 512 (k / 16) elements
+        } else {
+            const int row = isA ? min(m0 + rloc, M - 1) : min(n0 + rloc, N - 1);
+            gsrc[j] = (isA ? A + pl * a_plane + (long)row * lda : B + pl * b_plane + (long)row * ldb) + 8 * c;
+            kmul[j] = 1;
+        }
         dsto[j] = (isA ? pl * A_EL : NPL * A_EL + pl * B_EL) + rb * 32 * BK;
     }
     // padding K steps (past K) load zeros: every lane reads the same 16 bytes
@@ -764,7 +605,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         const bool pad = k0 >= K;
 #pragma unroll
         for (int j = 0; j < LPW; ++j) {
-            const __bf16* g = pad ? zsrc : gsrc[j] + k0;
+            const __bf16* g = pad ? zsrc : gsrc[j] + (long)kmul[j] * k0;
             __builtin_amdgcn_global_load_lds(g, (lds_void*)(S + dsto[j]), 16, 0, 0);
         }
     };
@@ -823,13 +664,13 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     }
     wait_vmem_le<0>();   // the last two stages' loads must land before the workgroup's LDS is released
 
-    long coff[FN];
+    MapPart coff[FN];
     bool cin[FN];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int n = n0 + wn * WN + j * 32 + frow;
         cin[j] = n < N;
-        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : 0;
+        coff[j] = cin[j] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
@@ -837,15 +678,15 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         for (int r = 0; r < 16; ++r) {
             const int m = m0 + wm * WM + i * 32 + 8 * (r >> 2) + 4 * fk + (r & 3);
             if (m >= M) continue;
-            const long roff = map_row(mp, (unsigned)m);
+            const MapPart roff = map_row(mp, (unsigned)m);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                if (cin[j]) store(roff + coff[j], acc[i][j][r]);
+                if (cin[j]) store(map_off(mp, roff, coff[j]), acc[i][j][r]);
         }
     }
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE>
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA = false, bool PB = false>
 static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
                                const Store& st, const OutMap& mp, hipStream_t stream)
 {
@@ -855,7 +696,7 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
     const int per_xcd = (int)((tiles + 7) / 8);
     const long grid = 8L * per_xcd;
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE, PA, PB>), dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
                        per_xcd);
@@ -885,7 +726,31 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                            const Store& st, const OutMap& map, int products, hipStream_t stream)
 {
     (void)products;
-    if (A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3) {
+    const bool split = A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3;
+    if (A.panel_k || B.panel_k) {
+        // panel-layout operands (the Y product at steady state): both
+        // operands, row length K, whole 32-row panels, direct-to-LDS kernel
+        const bool ok = split && A.panel_k == K && B.panel_k == K && K >= 16 && K % 16 == 0 && M % 32 == 0 &&
+                        N % 32 == 0 && N > 64 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
+                        ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
+        if constexpr (ROLE == 2) {
+            if (!ok) return hipErrorInvalidValue;
+            const long big_tiles = (long)((M + 255) / 256) * ((N + 255) / 256);
+            if (A.fmt == Fmt::BF16x2)
+                return big_tiles < 512
+                           ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
+                           : run_gemm_dma<3, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE, true, true>(
+                                 A, lda, B, ldb, M, N, K, st, map, stream);
+            return big_tiles < 512
+                       ? run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
+                       : run_gemm_dma<6, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE, true, true>(
+                             A, lda, B, ldb, M, N, K, st, map, stream);
+        } else {
+            (void)ok;
+            return hipErrorInvalidValue;   // only the Y product reads panel operands
+        }
+    }
+    if (split) {
         // narrow outputs (T' has N = D') take a 64-wide tile
         const bool narrow = N <= 64;
 #if HOTRG_BF16_DMA

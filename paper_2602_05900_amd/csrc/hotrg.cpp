@@ -329,6 +329,13 @@ int enqueue_step(hotrg_solve* s) {
         }
     }
     record(s, step_index, 3);
+    // The Y product's operands, X [(l,d,r1) x (a2,k)] and P4 [(u,r) x (l,d)],
+    // both with rows of Kp = Dx Dy elements, are written in the 32 x 16 panel
+    // layout when the split formats are used and the shapes allow it (Kp a
+    // multiple of 32, more than 64 columns of Y), so that every tile load of
+    // the D^7 product is one contiguous KiB.
+    const long Kp = (long)Dx * Dy;
+    const bool panel = (f == Fmt::BF16x2 || f == Fmt::BF16x3) && Kp % 32 == 0 && Kp > 64;
     // -- X = U . T  -> X[l,d,r1,a2,k]
     {
         const int p3[4] = {2, 1, 3, 0};  // P3[d,r,u,l]
@@ -336,20 +343,24 @@ int enqueue_step(hotrg_solve* s) {
     }
     record(s, step_index, 4);
     {
-        const OutMap xm{Dx, (long)Dy * Dx * Dx * Dy, Dy, Dy, (long)Dx * Dy, 1};
+        // rows (l, a2), columns (d r1, k): offset l Dy Dx Kp + a2 Dy + (d r1) Kp + k,
+        // i.e. row l Dy Dx + (d r1) and column a2 Dy + k of the [Dp Dy Dx x Kp] matrix
+        const OutMap xm = panel ? OutMap{Dx, (long)Dy * Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, Kp}
+                                : OutMap{Dx, (long)Dy * Dx * Kp, Dy, Dy, Kp, 1};
         if ((rc = gemm(s, Ux, Dx, Pa, Dx, X, Dp * Dx, Dy * Dx * Dy, Dx, xm, GemmRole::X))) return rc;
     }
     record(s, step_index, 5);
     // -- Y = X . T  -> Y[l,d,u,r1,r2]
+    Buf Xin = X, Pin = Pb;
+    if (panel) Xin.panel_k = Pin.panel_k = Kp;
     {
         const int p4[4] = {3, 1, 0, 2};  // P4[u,r,l,d]
-        HIP_TRY(s, launch_permute4(s->T(), dims, p4, Pb, s->stream));
+        HIP_TRY(s, launch_permute4(s->T(), dims, p4, Pin, s->stream));
     }
     record(s, step_index, 6);
     {
         const OutMap ym{Dx, (long)Dy * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};
-        if ((rc = gemm(s, X, (long)Dx * Dy, Pb, (long)Dx * Dy, Y, Dp * Dy * Dx, Dy * Dx, Dx * Dy, ym, GemmRole::Y)))
-            return rc;
+        if ((rc = gemm(s, Xin, Kp, Pin, Kp, Y, Dp * Dy * Dx, Dy * Dx, (int)Kp, ym, GemmRole::Y))) return rc;
     }
     record(s, step_index, 7);
     // -- T' = Y . U  -> next T[d,u,l,r] (x <-> y exchanged), FP64

@@ -11,6 +11,7 @@ namespace hotrg {
 // ---------------------------------------------------------------- stores
 
 __device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
+    if (o.panel_k) idx = (size_t)panel_index((long)(idx / o.panel_k), (long)(idx % o.panel_k), o.panel_k);
     switch (o.fmt) {
         case Fmt::F64: static_cast<double*>(o.ptr)[idx] = v; break;
         case Fmt::F32: static_cast<float*>(o.ptr)[idx] = (float)v; break;
