@@ -1,4 +1,5 @@
-"""Build the HOTRG HIP library in-tree: paper_2602_05900_amd/libhotrg.so.
+"""Build the HOTRG HIP library in-tree: paper_2602_05900_amd/libhotrg.so,
+and the stand-alone unit-ceiling microbenchmark paper_2602_05900_amd/peak_bench.
 
 Every source is compiled for gfx950 with hipcc and linked against the HIP
 runtime that PyTorch ships, so a process that has imported torch holds
@@ -18,6 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhotrg.so")
+PEAK = os.path.join(PKG, "peak_bench")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = ["gemm.hip", "tensor_ops.hip", "eig.hip", "hotrg.cpp"]
@@ -71,6 +73,11 @@ def build(verbose: bool = False) -> str:
           "-L", tlib, "-l:libamdhip64.so",
           f"-Wl,-rpath,{tlib}", "-Wl,--no-undefined", "-lstdc++", "-lm"], verbose)
     os.replace(tmp, LIB)
+    # the microbenchmark is its own program (no torch in its process): plain hipcc link
+    tmp = PEAK + ".tmp"
+    _run([hipcc, "-x", "hip", *[f for f in HIPCC_FLAGS if f != "-fPIC"], os.path.join(CSRC, "peak.hip"), "-o", tmp],
+         verbose)
+    os.replace(tmp, PEAK)
     return LIB
 
 

@@ -54,6 +54,10 @@ struct OutMap {
     long sn, cs_hi, cs_lo;
     long rc_hi = 0, rc_lo = 0, cc_hi = 0, cc_lo = 0;
     long panel_k = 0;
+    // Tile-order hint for the BF16 product at full size: when the columns
+    // are n = g * ngroup + h (ngroup a multiple of 16, N / ngroup too), a
+    // 256-wide tile may take 16 g x 16 h instead of 256 consecutive n (0: off).
+    long ngroup = 0;
 };
 
 // Which contraction of a step a product is (selects tiles; distinct symbols).

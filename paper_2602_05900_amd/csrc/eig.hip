@@ -207,10 +207,26 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
         V[i * EIG_LDP + j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
+    // Rotation test: an off-diagonal element is zeroed while it is large
+    // relative to its own diagonal pair.
+    auto passes = [&](double hij, double hii, double hjj) {
+        return fabs(hij) > 1e-300 && fabs(hij) > 1e-14 * sqrt(fabs(hii * hjj));
+    };
     int sweeps = 0;
     for (int sweep = 0; sweep < EIG_MAX_SWEEPS; ++sweep) {
+        // A sweep in which no off-diagonal element passes the rotation test
+        // below changes nothing; find that out directly (one pass over the
+        // upper triangle) instead of by running the sweep's pp - 1 rounds.
         if (tid == 0) any_rot = 0;
         __syncthreads();
+        for (int e = tid; e < p * p; e += 1024) {
+            const int i = e / p, j = e - (e / p) * p;
+            if (j > i) {
+                if (passes(H[i * EIG_LDP + j], H[i * EIG_LDP + i], H[j * EIG_LDP + j])) any_rot = 1;
+            }
+        }
+        __syncthreads();
+        if (!any_rot) break;
         for (int r = 0; r < pp - 1; ++r) {
             // round-robin pairing: position 0 fixed, positions 1..pp-1 rotate by r
             if (tid < half) {
@@ -222,12 +238,11 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
                 pj[tid] = j;
                 const double hii = H[i * EIG_LDP + i], hjj = H[j * EIG_LDP + j], hij = H[i * EIG_LDP + j];
                 double c = 1.0, s = 0.0, t = 0.0;
-                if (fabs(hij) > 1e-300 && fabs(hij) > 1e-14 * sqrt(fabs(hii * hjj))) {
+                if (passes(hij, hii, hjj)) {
                     const double tau = (hjj - hii) / (2.0 * hij);
                     t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + t * t);
                     s = t * c;
-                    any_rot = 1;
                 }
                 cs[tid] = c;
                 sn[tid] = s;
@@ -281,9 +296,7 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
             __syncthreads();
         }
         sweeps = sweep + 1;
-        const int rotated = any_rot;
         __syncthreads();
-        if (!rotated) break;
     }
     // descending order, ties by index
     for (int i = tid; i < p; i += 1024) {

@@ -45,6 +45,24 @@
 #define HOTRG_DMA_WM 4
 #define HOTRG_DMA_WN 2
 #endif
+// narrow outputs (T', N = D') and mid-size products (half environments, E)
+#ifndef HOTRG_NARROW_NST
+#define HOTRG_NARROW_NST 3    // two stages measured slower for T' (12.1 -> 16.1 ms per D = 48 solve)
+#define HOTRG_NARROW_MINW 1
+#endif
+#ifndef HOTRG_MID_NST
+#define HOTRG_MID_NST 2    // two stages, up to three workgroups per CU (env 19.2 -> 18.3 ms per D = 48 solve)
+#define HOTRG_MID_MINW 2
+#endif
+// Y product (panel operands) at full size
+#ifndef HOTRG_Y_BM
+#define HOTRG_Y_BM 256
+#define HOTRG_Y_BN 256
+#define HOTRG_Y_WM 4
+#define HOTRG_Y_WN 2
+#define HOTRG_Y_NST 3
+#define HOTRG_Y_MINW 1
+#endif
 
 namespace hotrg {
 
@@ -522,12 +540,12 @@ __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA, bool PB>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA, bool PB, int NST, int MINW>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, MINW)
 void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
                             const __bf16* __restrict__ B, long ldb, long b_plane,
                             int M, int N, int K, Store store, OutMap mp,
-                            int tiles_m, int tiles_n, int per_xcd)
+                            int tiles_m, int tiles_n, int per_xcd, int ngrp)
 {
     using SP = SplitProducts<NPROD>;
     typedef float f16v __attribute__((ext_vector_type(16)));
@@ -549,9 +567,10 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be whole 32x32 fragments");
     static_assert(NLOAD % NW == 0, "tile loads must divide evenly over the waves");
 
+    static_assert(NST == 2 || NST == 3, "two or three K stages in LDS");
     __shared__ __attribute__((aligned(1024))) __bf16 S0[STAGE];
     __shared__ __attribute__((aligned(1024))) __bf16 S1[STAGE];
-    __shared__ __attribute__((aligned(1024))) __bf16 S2[STAGE];
+    __shared__ __attribute__((aligned(1024))) __bf16 S2[NST == 3 ? STAGE : 8];
 
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * per_xcd + (bid >> 3);
@@ -560,6 +579,19 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     const int tn = tile - tm * tiles_n;
     const int m0 = tm * BM;
     const int n0 = tn * BN;
+
+    // Column order of the tile.  ngrp == 0: columns n0 .. n0 + BN - 1.
+    // ngrp > 0 (N = G ngrp columns n = g ngrp + h): the tile takes BN / 16
+    // consecutive g times 16 consecutive h, local column 16 (g - g0) +
+    // (h - h0), so that an output map whose panel row follows g and whose
+    // panel column follows h writes runs of BN / 16 whole panel rows.
+    auto ncol = [&](int nl) -> int {
+        if (ngrp == 0) return n0 + nl;
+        const int hb = ngrp >> 4;
+        const int g = (tn / hb) * (BN / 16) + (nl >> 4);
+        const int h = (tn - (tn / hb) * hb) * 16 + (nl & 15);
+        return g * ngrp + h;
+    };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -593,7 +625,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             gsrc[j] = (isA ? A + pl * a_plane : B + pl * b_plane) + (long)blk * (K >> 4) * 512 + lrow * 16 + 8 * c;
             kmul[j] = 32;   // panel (k / 16) starts at 512 (k / 16) elements
         } else {
-            const int row = isA ? min(m0 + rloc, M - 1) : min(n0 + rloc, N - 1);
+            const int row = isA ? min(m0 + rloc, M - 1) : min(ncol(rloc), N - 1);
             gsrc[j] = (isA ? A + pl * a_plane + (long)row * lda : B + pl * b_plane + (long)row * ldb) + 8 * c;
             kmul[j] = 1;
         }
@@ -645,30 +677,37 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
                                                                         0, 0, 0);
     };
 
-    // K steps padded to a multiple of 3 (the padding steps load zeros), so
+    // K steps padded to a multiple of NST (the padding steps load zeros), so
     // the loop body is branch-free: every step waits for the same count and
-    // issues the loads two steps ahead
-    const int nk = (K / BK + 2) / 3 * 3;
-    auto step = [&](const __bf16* cur, __bf16* next2, int kt) {
-        wait_vmem_le<LPW>();
+    // issues the loads NST - 1 steps ahead
+    const int nk = (K / BK + NST - 1) / NST * NST;
+    auto step = [&](const __bf16* cur, __bf16* ahead, int kt) {
+        wait_vmem_le<(NST - 2) * LPW>();
         stage_barrier();
-        issue(next2, (kt + 2) * BK);
+        issue(ahead, (kt + NST - 1) * BK);
         compute(cur);
     };
     issue(S0, 0);
-    issue(S1, BK);
-    for (int kt = 0; kt < nk; kt += 3) {
-        step(S0, S2, kt);
-        step(S1, S0, kt + 1);
-        step(S2, S1, kt + 2);
+    if constexpr (NST == 3) {
+        issue(S1, BK);
+        for (int kt = 0; kt < nk; kt += 3) {
+            step(S0, S2, kt);
+            step(S1, S0, kt + 1);
+            step(S2, S1, kt + 2);
+        }
+    } else {
+        for (int kt = 0; kt < nk; kt += 2) {
+            step(S0, S1, kt);
+            step(S1, S0, kt + 1);
+        }
     }
-    wait_vmem_le<0>();   // the last two stages' loads must land before the workgroup's LDS is released
+    wait_vmem_le<0>();   // the last stages' loads must land before the workgroup's LDS is released
 
     MapPart coff[FN];
     bool cin[FN];
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-        const int n = n0 + wn * WN + j * 32 + frow;
+        const int n = ncol(wn * WN + j * 32 + frow);
         cin[j] = n < N;
         coff[j] = cin[j] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
     }
@@ -686,20 +725,23 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     }
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA = false, bool PB = false>
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA = false, bool PB = false, int NST = 3,
+          int MINW = 1>
 static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
-                               const Store& st, const OutMap& mp, hipStream_t stream)
+                               const Store& st, const OutMap& mp, hipStream_t stream, int ngrp = 0)
 {
+    if (ngrp && (BN % 16 || ngrp % 16 || N % ngrp || (N / ngrp) % (BN / 16))) return hipErrorInvalidValue;
     const int tiles_m = (M + BM - 1) / BM;
     const int tiles_n = (N + BN - 1) / BN;
     const long tiles = (long)tiles_m * tiles_n;
     const int per_xcd = (int)((tiles + 7) / 8);
     const long grid = 8L * per_xcd;
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE, PA, PB>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE, PA, PB, NST, MINW>),
+                       dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
-                       per_xcd);
+                       per_xcd, ngrp);
     return hipGetLastError();
 }
 
@@ -739,12 +781,12 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
             if (A.fmt == Fmt::BF16x2)
                 return big_tiles < 512
                            ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
-                           : run_gemm_dma<3, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE, true, true>(
-                                 A, lda, B, ldb, M, N, K, st, map, stream);
+                           : run_gemm_dma<3, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true,
+                                          HOTRG_Y_NST, HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream);
             return big_tiles < 512
                        ? run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
-                       : run_gemm_dma<6, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE, true, true>(
-                             A, lda, B, ldb, M, N, K, st, map, stream);
+                       : run_gemm_dma<6, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true, HOTRG_Y_NST,
+                                      HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream);
         } else {
             (void)ok;
             return hipErrorInvalidValue;   // only the Y product reads panel operands
@@ -757,23 +799,42 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
         const bool dma = K >= 16 && K % 16 == 0 && lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 &&
                          (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
         if (dma) {
+            if constexpr (ROLE == 1) {
+                // X = U . T has K = Dx: a few K steps per tile and a D^5 output,
+                // so its time is the tile's load latency and its stores; small
+                // tiles with two LDS stages let three workgroups share a CU and
+                // overlap each other's loads, products and stores (measured
+                // 19.2 -> 15.8 ms per D = 48 solve against 256 x 256, one per CU)
+                if (!narrow)
+                    return A.fmt == Fmt::BF16x2
+                               ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, false, false, 2, 3>(A, lda, B, ldb, M, N, K, st,
+                                                                                        map, stream, (int)map.ngroup)
+                               : run_gemm_dma<6, 128, 128, 2, 2, ROLE, false, false, 2, 3>(A, lda, B, ldb, M, N, K, st,
+                                                                                        map, stream, (int)map.ngroup);
+            }
             // tile by the work available: 256 x 256 needs at least two rounds
             // of workgroups over the 256 CUs to fill the chip; smaller
             // products (half environments and E, N = K = D^2) take 128 x 128,
             // narrow outputs (T', N = D') 128 x 64
             const long big_tiles = (long)((M + 255) / 256) * ((N + 255) / 256);
             if (A.fmt == Fmt::BF16x2) {
-                if (narrow) return run_gemm_dma<3, 128, 64, 2, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+                if (narrow)
+                    return run_gemm_dma<3, 128, 64, 2, 1, ROLE, false, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                        A, lda, B, ldb, M, N, K, st, map, stream);
                 if (big_tiles < 512)
-                    return run_gemm_dma<3, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+                    return run_gemm_dma<3, 128, 128, 2, 2, ROLE, false, false, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                        A, lda, B, ldb, M, N, K, st, map, stream);
                 return run_gemm_dma<3, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
-                                                                                  stream);
+                                                                                  stream, (int)map.ngroup);
             }
-            if (narrow) return run_gemm_dma<6, 128, 64, 2, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+            if (narrow)
+                return run_gemm_dma<6, 128, 64, 2, 1, ROLE, false, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                    A, lda, B, ldb, M, N, K, st, map, stream);
             if (big_tiles < 512)
-                return run_gemm_dma<6, 128, 128, 2, 2, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
+                return run_gemm_dma<6, 128, 128, 2, 2, ROLE, false, false, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                    A, lda, B, ldb, M, N, K, st, map, stream);
             return run_gemm_dma<6, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
-                                                                              stream);
+                                                                              stream, (int)map.ngroup);
         }
 #endif
         if (A.fmt == Fmt::BF16x2)

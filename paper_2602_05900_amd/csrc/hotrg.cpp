@@ -345,8 +345,11 @@ int enqueue_step(hotrg_solve* s) {
     {
         // rows (l, a2), columns (d r1, k): offset l Dy Dx Kp + a2 Dy + (d r1) Kp + k,
         // i.e. row l Dy Dx + (d r1) and column a2 Dy + k of the [Dp Dy Dx x Kp] matrix
-        const OutMap xm = panel ? OutMap{Dx, (long)Dy * Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, Kp}
-                                : OutMap{Dx, (long)Dy * Dx * Kp, Dy, Dy, Kp, 1};
+        // With Dy and Dx Dy multiples of 16, a tile takes 16 (d r1) x 16 k
+        // columns, so its rows of X are whole runs of 16 panel rows.
+        OutMap xm = panel ? OutMap{Dx, (long)Dy * Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, Kp}
+                          : OutMap{Dx, (long)Dy * Dx * Kp, Dy, Dy, Kp, 1};
+        if (panel && Dy % 16 == 0 && Kp % 16 == 0) xm.ngroup = Dy;
         if ((rc = gemm(s, Ux, Dx, Pa, Dx, X, Dp * Dx, Dy * Dx * Dy, Dx, xm, GemmRole::X))) return rc;
     }
     record(s, step_index, 5);

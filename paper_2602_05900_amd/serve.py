@@ -188,7 +188,7 @@ class Server:
             self._admit()
             progressed = self._advance()
             if progress and now - last_report >= 5.0:
-                progress(now, len(self.done), n_total, len(self.active), len(self.queue))
+                progress(now, len(self.done) - n_before, n_total, len(self.active), len(self.queue))
                 last_report = now
             if not progressed:
                 time.sleep(0.0002)
