@@ -3,12 +3,15 @@
 // The truncation of a HOTRG step keeps the leading k eigenvectors of
 // E = M M^T, to which the higher-order SVD of the merged tensor reduces
 // (Sec. II.A).  Only k << n of them are needed, so for n > P_MAX the solver
-// is a block subspace iteration with a Rayleigh-Ritz projection each pass:
+// is a block subspace iteration with a Rayleigh-Ritz projection on every
+// second pass:
 //
 //   V (n x p, orthonormal)  ->  W = E V           (MFMA FP64, eig_ev_kernel)
 //   H = V^T W (p x p)       ->  H = S diag(theta) S^T   (Jacobi, one workgroup)
 //   V <- V S, W <- W S      (Ritz vectors; residual |W_j - theta_j V_j|)
 //   converged?  else  V <- orth(W diag(1/|W_j|))  (CholeskyQR)
+//
+// and on the passes between only W = E V and V <- orth(W diag(1/|W_j|)).
 //
 // warm-started from the Ritz block of the step two earlier (same fused leg
 // basis once the dims are steady), else from a counter-based random block.
@@ -35,6 +38,19 @@ constexpr int EIG_PMAX = kEigPMax; // largest Ritz block / fully diagonalised ma
 constexpr int EIG_LDP = EIG_PMAX + 1;
 constexpr int EIG_GRAM_ROWS = 32;  // rows per partial Gram block
 constexpr int EIG_MAX_SWEEPS = 40;
+// Rayleigh-Ritz (and the convergence test) on every second pass; the pass
+// between is a plain power step V <- orth(E V).  The span of the block, on
+// which convergence depends, is the same either way, and the Jacobi of the
+// Rayleigh quotient dominates a pass: measured at D = 48, 0.66-0.76x the
+// eigensolve time at the same residual bound (every third pass misses the
+// bound in 30 passes).
+#ifndef HOTRG_RR_EVERY
+#define HOTRG_RR_EVERY 2
+#endif
+#ifndef HOTRG_JAC_THREADS
+#define HOTRG_JAC_THREADS 1024
+#endif
+constexpr int EIG_JT = HOTRG_JAC_THREADS;   // threads of the one-workgroup Jacobi kernel
 
 // ---------------------------------------------------------------- helpers
 
@@ -182,7 +198,7 @@ __global__ __launch_bounds__(256) void eig_reduce_kernel(const double* __restric
 // Diagonalises the symmetric p x p matrix Hin (p <= EIG_PMAX; read with
 // leading dimension ldh): theta[j] descending, S column j the matching
 // eigenvector (S row-major p x p, S[i*p + j]).  sym: use (H + H^T)/2.
-__global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restrict__ Hin, int ldh, int p,
+__global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __restrict__ Hin, int ldh, int p,
                                                           double* __restrict__ theta, double* __restrict__ S,
                                                           EigCtl* ctl, int check_done) {
     if (check_done && eig_done(ctl)) return;
@@ -195,11 +211,11 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
     const int tid = threadIdx.x;
     const int pp = p + (p & 1);   // even number of players; index p (if any) is a zero dummy
     const int half = pp / 2;
-    const int bstride = 1024 / half;      // threads per block column
+    const int bstride = EIG_JT / half;      // threads per block column
     // threads 0 .. half*bstride-1 own block column bq and rows bp0, bp0+bstride, ...
     const int bq = tid < half * bstride ? tid % half : half;
     const int bp0 = tid / half;
-    for (int e = tid; e < pp * pp; e += 1024) {
+    for (int e = tid; e < pp * pp; e += EIG_JT) {
         const int i = e / pp, j = e - (e / pp) * pp;
         double h = 0.0;
         if (i < p && j < p) h = 0.5 * (Hin[(long)i * ldh + j] + Hin[(long)j * ldh + i]);
@@ -219,7 +235,7 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
         // upper triangle) instead of by running the sweep's pp - 1 rounds.
         if (tid == 0) any_rot = 0;
         __syncthreads();
-        for (int e = tid; e < p * p; e += 1024) {
+        for (int e = tid; e < p * p; e += EIG_JT) {
             const int i = e / p, j = e - (e / p) * p;
             if (j > i) {
                 if (passes(H[i * EIG_LDP + j], H[i * EIG_LDP + i], H[j * EIG_LDP + j])) any_rot = 1;
@@ -299,7 +315,7 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
         __syncthreads();
     }
     // descending order, ties by index
-    for (int i = tid; i < p; i += 1024) {
+    for (int i = tid; i < p; i += EIG_JT) {
         const double ti = H[i * EIG_LDP + i];
         int rk = 0;
         for (int j = 0; j < p; ++j) {
@@ -309,8 +325,8 @@ __global__ __launch_bounds__(1024) void eig_jacobi_kernel(const double* __restri
         rank[i] = rk;
     }
     __syncthreads();
-    for (int i = tid; i < p; i += 1024) theta[rank[i]] = H[i * EIG_LDP + i];
-    for (int e = tid; e < p * p; e += 1024) {
+    for (int i = tid; i < p; i += EIG_JT) theta[rank[i]] = H[i * EIG_LDP + i];
+    for (int e = tid; e < p * p; e += EIG_JT) {
         const int row = e / p, col = e - (e / p) * p;
         S[(long)row * p + rank[col]] = V[row * EIG_LDP + col];
     }
@@ -619,7 +635,7 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
     if (n < 1 || k < 1 || k > n) return hipErrorInvalidValue;
     if (n <= EIG_PMAX) {
         hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(256), 0, stream, E, n, (double*)nullptr, 0, 1, seed, w.ctl);
-        hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(1024), 0, stream, E, n, n, w.theta, w.S, w.ctl, 0);
+        hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(EIG_JT), 0, stream, E, n, n, w.theta, w.S, w.ctl, 0);
         hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, w.S, n, n, dx, k, Ut, Ux);
         hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, n, n, k, w.ctl, st, step);
         return hipGetLastError();
@@ -653,10 +669,24 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
     orth(V, shift, seed * 31 + 7);
     for (int it = 0; it < maxit; ++it) {
         hipLaunchKernelGGL(eig_ev_kernel, dim3(grid_for(n, 16)), dim3(256), 0, stream, E, n, V, w.W, p, w.ctl);
+#if HOTRG_RR_EVERY > 1
+        if (it % HOTRG_RR_EVERY != HOTRG_RR_EVERY - 1 && it != maxit - 1) {
+            // power step without Rayleigh-Ritz: V <- orth(E V)
+            hipLaunchKernelGGL(eig_gram_kernel, dim3(nb), dim3(256), 0, stream, w.W, w.W, n, p, w.part, pstride,
+                               w.ctl);
+            hipLaunchKernelGGL(eig_reduce_kernel, dim3(grid_for(p * p, 256)), dim3(256), 0, stream, w.part, nb,
+                               pstride, p * p, w.G, w.ctl);
+            hipLaunchKernelGGL(eig_chol_kernel, dim3(1), dim3(1024), 0, stream, w.G, n, p, k, w.theta, tol, -1,
+                               maxit - 1, shift, w.L, w.dsc, w.ctl);
+            hipLaunchKernelGGL(eig_orth_apply_kernel, dim3(nb), dim3(256), 0, stream, w.W, V, n, p, w.L, w.dsc,
+                               seed * 131 + it, w.ctl);
+            continue;
+        }
+#endif
         hipLaunchKernelGGL(eig_gram_kernel, dim3(nb), dim3(256), 0, stream, V, w.W, n, p, w.part, pstride, w.ctl);
         hipLaunchKernelGGL(eig_reduce_kernel, dim3(grid_for(p * p, 256)), dim3(256), 0, stream, w.part, nb, pstride,
                            p * p, w.G, w.ctl);
-        hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(1024), 0, stream, w.G, p, p, w.theta, w.S, w.ctl, 1);
+        hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(EIG_JT), 0, stream, w.G, p, p, w.theta, w.S, w.ctl, 1);
         hipLaunchKernelGGL(eig_rotate_kernel, dim3(nb), dim3(256), 0, stream, V, w.W, n, p, w.S, w.theta, w.part,
                            pstride, w.ctl);
         hipLaunchKernelGGL(eig_reduce_kernel, dim3(grid_for(p * p + p, 256)), dim3(256), 0, stream, w.part, nb,
