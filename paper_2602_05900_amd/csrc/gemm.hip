@@ -545,7 +545,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, MINW)
 void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
                             const __bf16* __restrict__ B, long ldb, long b_plane,
                             int M, int N, int K, Store store, OutMap mp,
-                            int tiles_m, int tiles_n, int per_xcd, int ngrp)
+                            int tiles_m, int tiles_n, int per_xcd, int ngrp, int vec_out)
 {
     using SP = SplitProducts<NPROD>;
     typedef float f16v __attribute__((ext_vector_type(16)));
@@ -703,6 +703,80 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     }
     wait_vmem_le<0>();   // the last stages' loads must land before the workgroup's LDS is released
 
+    // BF16-plane outputs whose map keeps runs of 8 columns contiguous and
+    // 16-byte aligned (checked on the host): stage 16-row slabs of all planes
+    // in LDS and write them back as 16-byte stores instead of one 2-byte
+    // store per element and plane.  The K stages serve as staging space, one
+    // private region per wave.
+    constexpr int RW = WN + 8;                     // staged row, bf16 (a 16-byte multiple)
+    constexpr int SLAB = 16 * RW;                  // one plane of a 16-row slab
+    constexpr int REG = NPL * SLAB;                // one wave's region
+    constexpr int PER_ARRAY = STAGE / REG;
+    if constexpr (PER_ARRAY > 0 && NW <= PER_ARRAY * NST) {
+        if (vec_out) {
+            typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+            constexpr int CPR = WN / 8;            // 16-byte chunks per staged row
+            constexpr int NCH = 16 * CPR;          // chunks per plane of a slab
+            static_assert(NCH % 64 == 0, "whole chunks per lane");
+            constexpr int CPL = NCH / 64;          // chunks per lane
+            __syncthreads();   // every wave is done reading the stages
+            const int ar = wave / PER_ARRAY;
+            __bf16* reg = (ar == 0 ? S0 : (ar == 1 ? S1 : S2)) + (wave - ar * PER_ARRAY) * REG;
+            __bf16* outp = static_cast<__bf16*>(store.ptr);
+            const long pstride = (long)store.plane;
+            // this lane's chunks: staged row and column, output column part
+            MapPart ccol[CPL];
+            bool cok[CPL];
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = lane + 64 * t;
+                const int n = ncol(wn * WN + (c % CPR) * 8);
+                cok[t] = n < N;
+                ccol[t] = cok[t] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // fragment rows 16h .. 16h + 15 are components 8h .. 8h + 7
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) {
+                            const int r = 8 * h + rr;
+                            const int row = 8 * (rr >> 2) + 4 * fk + (rr & 3);
+                            // the same split as split_store: hi, mid, lo by round-to-nearest-even
+                            const float f = (float)(store.alpha * (double)acc[i][j][r]);
+                            const __bf16 hi = (__bf16)f;
+                            const float rem = f - (float)hi;
+                            const __bf16 md = (__bf16)rem;
+                            __bf16* dst = reg + row * RW + j * 32 + frow;
+                            dst[0] = hi;
+                            dst[SLAB] = md;
+                            if constexpr (NPL == 3) dst[2 * SLAB] = (__bf16)(rem - (float)md);
+                        }
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's staging writes are done
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) {
+                        const int c = lane + 64 * t;
+                        const int row = c / CPR;
+                        const int m = m0 + wm * WM + i * 32 + 16 * h + row;
+                        if (cok[t] && m < M) {
+                            const long off = map_off(mp, map_row(mp, (unsigned)m), ccol[t]);
+                            const __bf16* src = reg + row * RW + (c % CPR) * 8;
+#pragma unroll
+                            for (int pl = 0; pl < NPL; ++pl)
+                                *reinterpret_cast<u4*>(outp + pl * pstride + off) =
+                                    *reinterpret_cast<const u4*>(src + pl * SLAB);
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // staging reads are done before the region is rewritten
+                }
+            }
+            return;
+        }
+    }
+
     MapPart coff[FN];
     bool cin[FN];
 #pragma unroll
@@ -731,6 +805,16 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
                                const Store& st, const OutMap& mp, hipStream_t stream, int ngrp = 0)
 {
     if (ngrp && (BN % 16 || ngrp % 16 || N % ngrp || (N / ngrp) % (BN / 16))) return hipErrorInvalidValue;
+    // 16-byte staged stores need the output in the planes of the operands'
+    // split format and runs of 8 output columns that stay contiguous and
+    // 16-byte aligned under the output map
+    const bool same_planes = st.fmt == (int)A.fmt;
+    const bool rm_ok = mp.panel_k == 0 && mp.cs_lo == 1 && mp.rs_hi % 8 == 0 && mp.rs_lo % 8 == 0 &&
+                       mp.cs_hi % 8 == 0;
+    const bool pn_ok = mp.panel_k != 0 && mp.panel_k % 16 == 0 && mp.cc_lo == 1 && mp.rc_hi % 8 == 0 &&
+                       mp.rc_lo % 8 == 0 && mp.cc_hi % 8 == 0;
+    const int vec_out = same_planes && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 && st.plane % 8 == 0 &&
+                        ((uintptr_t)st.ptr & 15) == 0;
     const int tiles_m = (M + BM - 1) / BM;
     const int tiles_n = (N + BN - 1) / BN;
     const long tiles = (long)tiles_m * tiles_n;
@@ -741,7 +825,7 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
                        dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
-                       per_xcd, ngrp);
+                       per_xcd, ngrp, vec_out ? 1 : 0);
     return hipGetLastError();
 }
 
