@@ -854,26 +854,46 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
     (void)products;
     const bool split = A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3;
     if (A.panel_k || B.panel_k) {
-        // panel-layout operands (the Y product at steady state): both
-        // operands, row length K, whole 32-row panels, direct-to-LDS kernel
-        const bool ok = split && A.panel_k == K && B.panel_k == K && K >= 16 && K % 16 == 0 && M % 32 == 0 &&
-                        N % 32 == 0 && N > 64 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
-                        ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
-        if constexpr (ROLE == 2) {
-            if (!ok) return hipErrorInvalidValue;
+        // panel-layout operands (row length K, whole 32-row panels) go to the
+        // direct-to-LDS kernel: both operands of the environment products and
+        // of Y, the A operand (Y itself) of T'
+        const bool base = split && K >= 16 && K % 16 == 0 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
+                          ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0 &&
+                          (!A.panel_k || (A.panel_k == K && M % 32 == 0)) &&
+                          (!B.panel_k || (B.panel_k == K && N % 32 == 0));
+        const bool both = base && A.panel_k && B.panel_k && N > 64;
+        if constexpr (ROLE == 0) {
+            // half environments and E (N = K = D^2): mid-size tiles
+            if (!both) return hipErrorInvalidValue;
+            return A.fmt == Fmt::BF16x2
+                       ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                             A, lda, B, ldb, M, N, K, st, map, stream)
+                       : run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                             A, lda, B, ldb, M, N, K, st, map, stream);
+        } else if constexpr (ROLE == 2) {
+            if (!both) return hipErrorInvalidValue;
             const long big_tiles = (long)((M + 255) / 256) * ((N + 255) / 256);
             if (A.fmt == Fmt::BF16x2)
                 return big_tiles < 512
                            ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
                            : run_gemm_dma<3, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true,
-                                          HOTRG_Y_NST, HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream);
+                                          HOTRG_Y_NST, HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream,
+                                                                     (int)map.ngroup);
             return big_tiles < 512
                        ? run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
                        : run_gemm_dma<6, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true, HOTRG_Y_NST,
-                                      HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream);
+                                      HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
+        } else if constexpr (ROLE == 3) {
+            // T' = Y . U: Y in panels, U row-major, narrow output
+            if (!(base && A.panel_k && !B.panel_k && N <= 64 && ldb % 8 == 0)) return hipErrorInvalidValue;
+            return A.fmt == Fmt::BF16x2
+                       ? run_gemm_dma<3, 128, 64, 2, 1, ROLE, true, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                             A, lda, B, ldb, M, N, K, st, map, stream)
+                       : run_gemm_dma<6, 128, 64, 2, 1, ROLE, true, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                             A, lda, B, ldb, M, N, K, st, map, stream);
         } else {
-            (void)ok;
-            return hipErrorInvalidValue;   // only the Y product reads panel operands
+            (void)both;
+            return hipErrorInvalidValue;
         }
     }
     if (split) {

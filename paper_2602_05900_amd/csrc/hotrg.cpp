@@ -297,21 +297,37 @@ int enqueue_step(hotrg_solve* s) {
     int rc;
 
     // -- half environments and E
+    // With the split formats and whole 32-row panels, the half-environment
+    // operands P1, P2 [(a,k) x (r,d)] and the half environments themselves,
+    // as E's operands [(a,b) x (k,k')], are stored in the 32 x 16 panel
+    // layout (as X and T are for Y), so the three products load contiguous
+    // KiBs.
+    const bool split = f == Fmt::BF16x2 || f == Fmt::BF16x3;
+    const long mxy = (long)Dx * Dy, mxx = (long)Dx * Dx, myy = (long)Dy * Dy;
+    const bool panel_env = split && mxy % 32 == 0 && mxy > 64 && mxx % 32 == 0 && mxx > 64 && myy % 16 == 0;
+    Buf P1b = Pa, P2b = Pb, Ahb = Ah, Bhb = Bh;
+    if (panel_env) {
+        P1b.panel_k = P2b.panel_k = mxy;
+        Ahb.panel_k = Bhb.panel_k = myy;
+    }
     record(s, step_index, 0);
     {
         const int p1[4] = {0, 3, 1, 2};  // P1[l,u,r,d]
         const int p2[4] = {0, 2, 1, 3};  // P2[l,d,r,u]
-        HIP_TRY(s, launch_permute4(s->T(), dims, p1, Pa, s->stream));
-        HIP_TRY(s, launch_permute4(s->T(), dims, p2, Pb, s->stream));
+        HIP_TRY(s, launch_permute4(s->T(), dims, p1, P1b, s->stream));
+        HIP_TRY(s, launch_permute4(s->T(), dims, p2, P2b, s->stream));
     }
     record(s, step_index, 1);
     {
         const int m = Dx * Dy;
-        const OutMap half{Dy, (long)Dx * Dy * Dy, Dy, Dy, (long)Dy * Dy, 1};  // -> [a,b,k,k']
-        if ((rc = gemm(s, Pa, m, Pa, m, Ah, m, m, m, half))) return rc;
-        if ((rc = gemm(s, Pb, m, Pb, m, Bh, m, m, m, half))) return rc;
+        // rows (a, k), columns (b, k') -> [a,b,k,k'], i.e. row a Dx + b and
+        // column k Dy + k' of E's [Dx^2 x Dy^2] operand
+        const OutMap half = panel_env ? OutMap{Dy, Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, myy}
+                                      : OutMap{Dy, (long)Dx * Dy * Dy, Dy, Dy, (long)Dy * Dy, 1};
+        if ((rc = gemm(s, P1b, m, P1b, m, Ah, m, m, m, half))) return rc;
+        if ((rc = gemm(s, P2b, m, P2b, m, Bh, m, m, m, half))) return rc;
         const OutMap env{Dx, (long)Dx * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};  // -> E[(a1a2),(b1b2)]
-        if ((rc = gemm(s, Ah, (long)Dy * Dy, Bh, (long)Dy * Dy, Ebuf, nE, nE, Dy * Dy, env))) return rc;
+        if ((rc = gemm(s, Ahb, (long)Dy * Dy, Bhb, (long)Dy * Dy, Ebuf, nE, nE, Dy * Dy, env))) return rc;
         HIP_TRY(s, launch_symmetrize(E, nE, s->stream));
     }
     record(s, step_index, 2);
