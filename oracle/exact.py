@@ -12,7 +12,16 @@ leg order, a dropped term, a transposed operand) shows up as a mismatch:
                            (Z = Tr T^N, Eq. (2)) through a tensor row transfer
                            matrix — no truncation, no isometries;
 * ``onsager_lnz``          Onsager's exact ln Z / N of the infinite square-
-                           lattice Ising model, and its internal energy.
+                           lattice Ising model, and its internal energy;
+* ``brute_force_observables``  the same enumeration with a magnetic field,
+                           returning the mean order parameter per site and the
+                           mean energy of a y bond and of an x bond;
+* ``network_impurity_ratio``  exact contraction of the periodic network with
+                           one copy replaced by another tensor, over the pure
+                           network (what an impurity-tensor estimator converges
+                           to when nothing is truncated);
+* ``yang_magnetisation``   the spontaneous magnetisation of the square-lattice
+                           Ising model below T_c (Onsager / Yang).
 """
 from __future__ import annotations
 
@@ -116,6 +125,82 @@ def network_lnz(T: np.ndarray, Lx: int, Ly: int) -> float:
     return Ly * math.log(c) + math.log(tr)
 
 
+def _row_transfer(tensors) -> np.ndarray:
+    """R[(d_0..d_{L-1}), (u_0..u_{L-1})] = sum_h prod_x A_x[h_x, h_{x+1}, d_x, u_x]
+    for a periodic row of the given tensors (all with the same dims)."""
+    W = np.asarray(tensors[0], dtype=np.float64).copy()
+    Dx, Dy = W.shape[0], W.shape[2]
+    for j in range(1, len(tensors)):
+        W = np.einsum("ahDU,hbdu->abDdUu", W, tensors[j])
+        W = W.reshape(Dx, Dx, Dy ** (j + 1), Dy ** (j + 1))
+    return np.einsum("hhDU->DU", W)
+
+
+def network_impurity_ratio(T: np.ndarray, I: np.ndarray, Lx: int, Ly: int) -> float:
+    """Z_I / Z for the periodic Lx x Ly network of copies of T[l, r, d, u] in
+    which the copy at site (0, 0) is replaced by I (same dims, same leg
+    joining as ``network_lnz``): Z_I = Tr(R_I R^(Ly-1)), Z = Tr R^Ly with R the
+    pure row transfer matrix and R_I the row holding I.  By translation
+    invariance of the rest of the network any site gives the same ratio."""
+    T = np.asarray(T, dtype=np.float64)
+    I = np.asarray(I, dtype=np.float64)
+    R = _row_transfer([T] * Lx)
+    RI = _row_transfer([I] + [T] * (Lx - 1))
+    c = float(np.max(np.abs(R)))
+    P = np.linalg.matrix_power(R / c, Ly - 1)
+    z = float(np.trace(P @ (R / c)))
+    zi = float(np.trace(P @ (RI / c)))
+    if z <= 0.0:
+        raise ValueError("network partition function is not positive")
+    return zi / z
+
+
+def brute_force_observables(model: str, q: int, temperature: float, Lx: int, Ly: int,
+                            J: float = 1.0, field: float = 0.0) -> dict:
+    """Exact thermal averages on the periodic Lx x Ly torus by enumeration.
+
+    H = sum over the 2 Lx Ly bonds of e(s, s') - field * sum_i f(s_i), with
+    e = -J s s' and f(s) = s for Ising (s = +-1), e = -J delta(s, s') and
+    f(s) = delta(s, 0) for Potts.  Returns ln Z, the order parameter per site
+    <m> (Ising s; Potts (q delta(s, 0) - 1) / (q - 1)), the mean energy of
+    one y bond (site to its upper neighbour) and of one x bond, and the
+    internal energy per site <H> / N.  Bonds are counted as in
+    ``brute_force_lnz`` (a width-2 direction has two parallel bonds).
+    """
+    nsites = Lx * Ly
+    if q ** nsites > 5_000_000:
+        raise ValueError("too many states for brute force")
+    beta = 1.0 / temperature
+    states = np.array(list(itertools.product(range(q), repeat=nsites)), dtype=np.int64)
+    s = states.reshape(-1, Ly, Lx)                       # s[config, y, x]
+    right = np.roll(s, -1, axis=2)
+    up = np.roll(s, -1, axis=1)
+    if model == "ising":
+        sig, sr, su = 1 - 2 * s, 1 - 2 * right, 1 - 2 * up
+        ex = -J * np.sum(sig * sr, axis=(1, 2)).astype(np.float64)
+        ey = -J * np.sum(sig * su, axis=(1, 2)).astype(np.float64)
+        fs = np.sum(sig, axis=(1, 2)).astype(np.float64)
+        mm = fs
+    elif model == "potts":
+        ex = -J * np.sum(s == right, axis=(1, 2)).astype(np.float64)
+        ey = -J * np.sum(s == up, axis=(1, 2)).astype(np.float64)
+        fs = np.sum(s == 0, axis=(1, 2)).astype(np.float64)
+        mm = (q * fs - nsites) / (q - 1.0)
+    else:
+        raise ValueError(model)
+    energy = ex + ey - field * fs
+    lw = -beta * energy
+    lz = _logsumexp(lw)
+    w = np.exp(lw - lz)
+    return {
+        "lnz": lz,
+        "m": float(np.sum(w * mm)) / nsites,
+        "e_y": float(np.sum(w * ey)) / nsites,
+        "e_x": float(np.sum(w * ex)) / nsites,
+        "u": float(np.sum(w * energy)) / nsites,
+    }
+
+
 def hotrg_torus(nsteps: int):
     """(Lx, Ly) of the torus that nsteps HOTRG steps (first merging along y)
     close into one tensor: Lx = 2^floor(n/2), Ly = 2^ceil(n/2)."""
@@ -157,6 +242,14 @@ def onsager_energy(temperature: float) -> float:
     if abs(k - 1.0) < 1e-15:
         return -1.0 / math.tanh(2.0 * b)
     return -(1.0 / math.tanh(2.0 * b)) * (1.0 + (2.0 / math.pi) * (2.0 * t2 - 1.0) * special.ellipk(k * k))
+
+
+def yang_magnetisation(temperature: float) -> float:
+    """Spontaneous magnetisation per site of the square-lattice Ising model
+    (J = 1): (1 - sinh(2b)^-4)^(1/8) below T_c, 0 above."""
+    b = 1.0 / temperature
+    x = 1.0 - math.sinh(2.0 * b) ** -4
+    return x ** 0.125 if x > 0.0 else 0.0
 
 
 def finite_difference_energy(temperatures: np.ndarray, lnz: np.ndarray) -> np.ndarray:

@@ -29,6 +29,18 @@ that published algorithm:
 * ln Z / N = ln c_0 + sum_n ln(c_n) / 2^n + ln(Tr T_final) / 2^nsteps, with a
   periodic torus of N = 2^nsteps sites.
 
+Two extensions of the same published algorithm (Xie et al. 2012) are also
+written out here:
+
+* two-sided truncation: the right environment (rows = the fused right leg) is
+  diagonalised as well, and each step keeps the isometry of the side whose
+  discarded eigenvalue weight is smaller, applying it to both fused legs;
+* impurity tensors: a local observable enters as one modified copy of the
+  local tensor; each step replaces an impurity tensor I by the average of the
+  two placements in the merged pair, U^T (I (x) T + T (x) I) U / 2, with the
+  same isometry and normalisation as T, so that after n steps
+  Tr I_n / Tr T_n is the observable averaged over the torus.
+
 Readings where the paper is silent are listed in the design doc; each appears
 below at the point it is used.
 """
@@ -73,12 +85,72 @@ def weight_root(W: np.ndarray) -> np.ndarray:
     return (V * np.sqrt(w)) @ V.T
 
 
-def initial_tensor(model: str, q: int, temperature: float, J: float = 1.0) -> np.ndarray:
-    """T0[x, x', y, y'] = sum_s Q[s,x] Q[s,x'] Q[s,y] Q[s,y'] (one spin per site,
-    each of its four bonds carrying a factor Q so that every bond sums to W)."""
+def field_weights(model: str, q: int, beta: float, field: float) -> np.ndarray:
+    """Site Boltzmann factor exp(beta * h * f(s)) of a field h coupled to
+    f(s) = sigma (Ising) or f(s) = delta(s, 0) (Potts)."""
+    if model == "ising":
+        return np.exp(beta * field * np.array([1.0, -1.0]))
+    f = np.zeros(q)
+    f[0] = 1.0
+    return np.exp(beta * field * f)
+
+
+def order_parameter(model: str, q: int) -> np.ndarray:
+    """Local order parameter m(s): sigma for Ising, (q delta(s,0) - 1)/(q - 1)
+    for Potts (1 in the ordered state s = 0, averaging to 0 when disordered)."""
+    if model == "ising":
+        return np.array([1.0, -1.0])
+    m = np.full(q, -1.0 / (q - 1.0))
+    m[0] = 1.0
+    return m
+
+
+def bond_energy(model: str, q: int, J: float = 1.0) -> np.ndarray:
+    """Bond energy e(s, s'): -J sigma sigma' (Ising), -J delta(s, s') (Potts)."""
+    if model == "ising":
+        sigma = np.array([1.0, -1.0])
+        return -J * np.outer(sigma, sigma)
+    return -J * np.eye(q)
+
+
+def site_tensor(Q: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """sum_s w(s) Q[s,x] Q[s,x'] Q[s,y] Q[s,y']."""
+    return np.einsum("s,sa,sb,sc,sd->abcd", weights, Q, Q, Q, Q)
+
+
+def initial_tensor(model: str, q: int, temperature: float, J: float = 1.0,
+                   field: float = 0.0) -> np.ndarray:
+    """T0[x, x', y, y'] = sum_s g(s) Q[s,x] Q[s,x'] Q[s,y] Q[s,y'] (one spin per
+    site, each of its four bonds carrying a factor Q so that every bond sums
+    to W; g the site factor of the field, 1 without one)."""
     beta = 1.0 / temperature
     Q = weight_root(boltzmann_weights(model, q, beta, J))
-    return np.einsum("sa,sb,sc,sd->abcd", Q, Q, Q, Q)
+    return site_tensor(Q, field_weights(model, q, beta, field))
+
+
+def impurity_tensors(model: str, q: int, temperature: float, J: float = 1.0,
+                     field: float = 0.0) -> dict:
+    """The two impurity tensors of the observables.
+
+    "m": the site's spin sum weighted by the order parameter,
+         S = sum_s m(s) g(s) Q[s,.]^4, so that one copy of S in the network
+         gives Z <m_i>.
+    "e": the local tensor with the bond below the site (its d leg) carrying
+         e(s, s') W(s, s') instead of W(s, s'): the leg is contracted with
+         G = Q^-1 W_e Q^-1 (W_e = e o W elementwise), since Q G Q = W_e.  One
+         copy gives Z <e_b> for that y bond.
+    Both are normalised like T0 by the caller (the same c_0).
+    """
+    beta = 1.0 / temperature
+    W = boltzmann_weights(model, q, beta, J)
+    Q = weight_root(W)
+    g = field_weights(model, q, beta, field)
+    S = site_tensor(Q, order_parameter(model, q) * g)
+    We = bond_energy(model, q, J) * W
+    G = np.linalg.solve(Q, np.linalg.solve(Q, We).T).T      # Q^-1 We Q^-1 (Q symmetric)
+    T0 = site_tensor(Q, g)
+    TG = np.einsum("yb,xzbw->xzyw", G, T0)
+    return {"m": S, "e": TG}
 
 
 # --------------------------------------------------------------------------
@@ -106,6 +178,24 @@ def environment(T: np.ndarray) -> np.ndarray:
     Dx = T.shape[0]
     A, B = half_environments(T)
     E4 = np.einsum("ikjl,mknl->imjn", A, B, optimize=True)   # [a1, a2, b1, b2]
+    E = E4.reshape(Dx * Dx, Dx * Dx)
+    return 0.5 * (E + E.T)
+
+
+def right_environment(T: np.ndarray) -> np.ndarray:
+    """E_R[(r1 r2), (s1 s2)] = sum M[(a1 a2), (r1 r2), d, u] M[(a1 a2), (s1 s2), d, u]:
+    the environment of the fused right leg of the same stacked pair, built
+    from its own two halves,
+
+    A_R[r1,k,s1,k'] = sum_{a1,d} T[a1,r1,d,k] T[a1,s1,d,k']   (bottom copy)
+    B_R[r2,k,s2,k'] = sum_{a2,u} T[a2,r2,k,u] T[a2,s2,k',u]   (top copy)
+
+    and symmetrised like the left one.
+    """
+    Dx = T.shape[0]
+    A = np.einsum("ardk,asdl->rksl", T, T, optimize=True)
+    B = np.einsum("arku,aslu->rksl", T, T, optimize=True)
+    E4 = np.einsum("ikjl,mknl->imjn", A, B, optimize=True)
     E = E4.reshape(Dx * Dx, Dx * Dx)
     return 0.5 * (E + E.T)
 
@@ -151,10 +241,15 @@ def truncation(E: np.ndarray, dmax: int) -> Truncation:
 class StepResult:
     T_next: np.ndarray     # normalised, x/y exchanged: dims [Dy, Dy, D', D']
     c: float               # normalisation c_n = max |T'|
-    trunc: Truncation
+    trunc: Truncation      # the truncation applied (the chosen side's)
+    eps_left: float = 0.0  # discarded weight of the left environment
+    eps_right: float = math.nan  # ... of the right one (two-sided only)
+    side: int = 0          # 0: left isometry applied, 1: right
+    impurities_next: list = field(default_factory=list)
 
 
-def coarse_grain_step(T: np.ndarray, dmax: int) -> StepResult:
+def coarse_grain_step(T: np.ndarray, dmax: int, two_sided: bool = False,
+                      impurities=()) -> StepResult:
     """One HOTRG step on T[l, r, d, u] with dims [Dx, Dx, Dy, Dy].
 
     X[l,a2,r1,d,k] = sum_{a1}     U[a1,a2,l] T[a1,r1,d,k]
@@ -164,18 +259,39 @@ def coarse_grain_step(T: np.ndarray, dmax: int) -> StepResult:
     i.e. T' = U^T M U applied to the fused left and right legs, contracted in
     the O(D^7) order.  Then c_n = max|T'|, T' <- T'/c_n, and the legs are
     exchanged (x <-> y) for the next step.
+
+    two_sided: U is taken from the right environment instead when its
+    discarded weight is strictly smaller (ties keep the left one).
+
+    impurities: tensors I of T's dims; each becomes
+    I' = U^T (I (x) T + T (x) I) U / (2 c_n), the bottom copy written first,
+    exchanged like T.
     """
     Dx = T.shape[0]
     if T.shape[1] != Dx or T.shape[3] != T.shape[2]:
         raise ValueError("T must have dims [Dx, Dx, Dy, Dy]")
     tr = truncation(environment(T), dmax)
+    eps_left, eps_right, side = tr.trunc_err, math.nan, 0
+    if two_sided:
+        trr = truncation(right_environment(T), dmax)
+        eps_right = trr.trunc_err
+        if trr.trunc_err < tr.trunc_err:
+            tr, side = trr, 1
     U3 = tr.U.reshape(Dx, Dx, tr.kept)                           # U[a1, a2, l]
     X = np.einsum("abl,ardk->lbrdk", U3, T, optimize=True)       # X[l,a2,r1,d,k]
     Y = np.einsum("lbrdk,bsku->lrdsu", X, T, optimize=True)      # Y[l,r1,d,r2,u]
     Tp = np.einsum("lrdsu,rsm->lmdu", Y, U3, optimize=True)      # T'[l,r,d,u]
     c = float(np.max(np.abs(Tp)))
     Tp = Tp / c
-    return StepResult(T_next=np.ascontiguousarray(Tp.transpose(2, 3, 0, 1)), c=c, trunc=tr)
+    nxt = []
+    for I in impurities:
+        XI = np.einsum("abl,ardk->lbrdk", U3, I, optimize=True)
+        YI = (np.einsum("lbrdk,bsku->lrdsu", XI, T, optimize=True)      # impurity in the bottom copy
+              + np.einsum("lbrdk,bsku->lrdsu", X, I, optimize=True))    # impurity in the top copy
+        Ip = 0.5 * np.einsum("lrdsu,rsm->lmdu", YI, U3, optimize=True) / c
+        nxt.append(np.ascontiguousarray(Ip.transpose(2, 3, 0, 1)))
+    return StepResult(T_next=np.ascontiguousarray(Tp.transpose(2, 3, 0, 1)), c=c, trunc=tr,
+                      eps_left=eps_left, eps_right=eps_right, side=side, impurities_next=nxt)
 
 
 # --------------------------------------------------------------------------
@@ -191,9 +307,14 @@ class Solve:
     cut_gap: list = field(default_factory=list)    # per step
     dims: list = field(default_factory=list)       # (Dx, Dy) entering each step
     T_final: np.ndarray | None = None              # normalised tensor after the last step
+    eps_left: list = field(default_factory=list)   # per step (two-sided runs)
+    eps_right: list = field(default_factory=list)
+    sides: list = field(default_factory=list)      # 0 left / 1 right isometry per step
+    observables: list = field(default_factory=list)  # Tr I_n / Tr T_n per impurity
 
 
-def solve_tensor(T0: np.ndarray, dmax: int, nsteps: int, keep_tensor: bool = True) -> Solve:
+def solve_tensor(T0: np.ndarray, dmax: int, nsteps: int, keep_tensor: bool = True,
+                 two_sided: bool = False, impurities=()) -> Solve:
     """Run nsteps HOTRG steps from the local tensor T0 and return ln Z / N.
 
     ln Z/N = ln c_0 + sum_{n=1..nsteps} ln(c_n)/2^n + ln(sum_{x,y} T[x,x,y,y]) / 2^nsteps,
@@ -204,27 +325,51 @@ def solve_tensor(T0: np.ndarray, dmax: int, nsteps: int, keep_tensor: bool = Tru
     T0 = np.asarray(T0, dtype=np.float64)
     c0 = float(np.max(np.abs(T0)))
     T = T0 / c0
+    imps = [np.asarray(I, dtype=np.float64) / c0 for I in impurities]
     out = Solve(lnz_per_site=0.0, log2_sites=nsteps, c=[c0])
     lnz = math.log(c0)
     for n in range(1, nsteps + 1):
         out.dims.append((T.shape[0], T.shape[2]))
-        step = coarse_grain_step(T, dmax)
+        step = coarse_grain_step(T, dmax, two_sided, imps)
         T = step.T_next
+        imps = step.impurities_next
         out.c.append(step.c)
         out.trunc_err.append(step.trunc.trunc_err)
         out.cut_gap.append(step.trunc.cut_gap)
+        out.eps_left.append(step.eps_left)
+        out.eps_right.append(step.eps_right)
+        out.sides.append(step.side)
         lnz += math.log(step.c) / 2.0 ** n
     trace = float(np.einsum("xxyy->", T))
     out.lnz_per_site = lnz + math.log(trace) / 2.0 ** nsteps
+    out.observables = [float(np.einsum("xxyy->", I)) / trace for I in imps]
     if keep_tensor:
         out.T_final = T
     return out
 
 
 def solve(model: str, q: int, temperature: float, dmax: int, nsteps: int,
-          J: float = 1.0, keep_tensor: bool = True) -> Solve:
-    """HOTRG for the Ising (q = 2) or q-state Potts model at a temperature."""
-    return solve_tensor(initial_tensor(model, q, temperature, J), dmax, nsteps, keep_tensor)
+          J: float = 1.0, keep_tensor: bool = True, field: float = 0.0,
+          two_sided: bool = False, observables=()) -> Solve:
+    """HOTRG for the Ising (q = 2) or q-state Potts model at a temperature.
+
+    observables: any of "m" (order parameter per site) and "e" (energy of one
+    y bond), carried as impurity tensors; their estimates land in
+    ``Solve.observables`` in the order given."""
+    imp = impurity_tensors(model, q, temperature, J, field) if observables else {}
+    return solve_tensor(initial_tensor(model, q, temperature, J, field), dmax, nsteps, keep_tensor,
+                        two_sided, [imp[o] for o in observables])
+
+
+def internal_energy(model: str, q: int, e_bond: float, m: float, field: float) -> float:
+    """Internal energy per site from the y-bond energy and the order
+    parameter: two bonds per site (x and y bonds equal for these isotropic
+    models) plus the field term -h <f(s)>."""
+    if model == "ising":
+        f = m
+    else:
+        f = ((q - 1.0) * m + 1.0) / q
+    return 2.0 * e_bond - field * f
 
 
 def free_energy(lnz_per_site: float, temperature: float) -> float:
