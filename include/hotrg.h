@@ -83,7 +83,13 @@ extern "C" {
 #define HOTRG_STAGE_Y       4  /* Y = X . T (GEMM, the D^7 term)              */
 #define HOTRG_STAGE_TP      5  /* T' = Y . U (GEMM)                           */
 #define HOTRG_STAGE_NORM    6  /* max|T'|, scaling, ln Z accumulation         */
-#define HOTRG_NUM_STAGES    7
+#define HOTRG_STAGE_OBS     7  /* impurity-tensor contractions (observables)  */
+#define HOTRG_NUM_STAGES    8
+
+/* Observables carried as impurity tensors (bits of hotrg_params.observables;
+ * slot 0 and slot 1 of hotrg_observables()). */
+#define HOTRG_OBS_MAGNETIZATION 1  /* slot 0: order parameter per site        */
+#define HOTRG_OBS_BOND_ENERGY   2  /* slot 1: energy of one y bond            */
 
 typedef struct hotrg_solve hotrg_solve;  /* opaque host handle */
 
@@ -100,6 +106,14 @@ typedef struct hotrg_params {
     int custom_dy;       /* HOTRG_CUSTOM: Dy (1..HOTRG_MAX_DIM)               */
     int max_steps;       /* steps the handle may take in total; sizes the
                             workspace (0 = HOTRG_MAX_STEPS)                   */
+    double field;        /* h: H gains -h sum_i f(s_i), f(s) = s (Ising, s = +-1)
+                            or delta(s, 0) (Potts); must be 0 for HOTRG_CUSTOM */
+    int two_sided;       /* 0: isometry from the left environment; 1: both
+                            environments, the smaller truncation error wins  */
+    int observables;     /* bitmask of HOTRG_OBS_*: impurity tensors carried  */
+    const double* custom_impurity[2]; /* HOTRG_CUSTOM: the impurity tensors of
+                            slots 0 and 1 (host, dims of custom_tensor), read
+                            during init only, for the bits set in observables */
 } hotrg_params;
 
 /* Bytes of device workspace one solve with these parameters needs, for any
@@ -116,13 +130,16 @@ size_t hotrg_workspace_bytes(const hotrg_params* p);
  *   stream     hipStream_t on which all work of this solve is enqueued
  *              (NULL = the legacy default stream)
  *   out        receives the new handle
- * For Ising/Potts, T0[x,x',y,y'] = sum_s Q[s,x]Q[s,x']Q[s,y]Q[s,y'] with Q
- * the symmetric square root of the bond Boltzmann weight matrix; T0 is
- * normalised by c_0 = max|T0| and ln c_0 starts the ln Z accumulator.  T0
- * and the device state are copied on the stream, which init synchronises.
- * Errors: EINVAL (parameters, NULL pointers, misaligned workspace, or a
- * bond dimension too large for the eigensolver's Ritz block: every step
- * with Dx^2 > 96 needs D' < 96), ENOMEM (ws_bytes too small), ENODEV, EHIP. */
+ * For Ising/Potts, T0[x,x',y,y'] = sum_s g(s) Q[s,x]Q[s,x']Q[s,y]Q[s,y'] with
+ * Q the symmetric square root of the bond Boltzmann weight matrix and g(s) =
+ * exp(h f(s) / temperature) the field's site factor; T0 (and any impurity
+ * tensor, see hotrg_observables) is normalised by c_0 = max|T0| and ln c_0
+ * starts the ln Z accumulator.  The tensors and the device state are copied
+ * on the stream, which init synchronises.
+ * Errors: EINVAL (parameters, NULL pointers, misaligned workspace, a
+ * non-zero field or a missing impurity tensor with HOTRG_CUSTOM, or a bond
+ * dimension too large for the eigensolver's Ritz block: every step with
+ * Dx^2 > 96 needs D' < 96), ENOMEM (ws_bytes too small), ENODEV, EHIP. */
 int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes,
                       void* stream, hotrg_solve** out);
 
@@ -170,6 +187,36 @@ int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites);
  * c_0 and zeros.  Any output pointer may be NULL.  Errors: EINVAL, latched. */
 int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err,
                     double* cut_gap);
+
+/* Two-sided truncation (Xie et al., PRB 86, 045139 (2012), the HOTRG the
+ * paper's Sec. II.A builds on): with p->two_sided the right environment of
+ * the merged pair (rows = the fused right leg) is diagonalised as well, and
+ * the step applies, to both fused legs, the isometry of the side with the
+ * smaller discarded weight (ties keep the left).  Synchronises and reports
+ * step n (1..steps taken): both sides' discarded weight over total weight
+ * (eps_right = NaN for one-sided handles) and the side applied (0 left,
+ * 1 right).  hotrg_step_info and hotrg_eig_info report the applied side.
+ * Any output pointer may be NULL.  Errors: EINVAL, latched. */
+int hotrg_step_sides(hotrg_solve* s, int n, double* eps_left, double* eps_right, int* side);
+
+/* Impurity-tensor observables.  An observable enters as one modified copy I
+ * of the local tensor; every step replaces I by U^T (I (x) T + T (x) I) U,
+ * the average of its two placements in the merged pair, divided by the same
+ * c_n as T, so that after n steps Tr I / Tr T is the observable averaged
+ * over the 2^n-site torus (exact when nothing is truncated).  For Ising /
+ * Potts the library builds
+ *   slot 0: sum_s m(s) g(s) Q[s,.]^4 with m = s (Ising), (q delta(s,0) - 1) /
+ *           (q - 1) (Potts): the order parameter per site <m>;
+ *   slot 1: T0 with its d leg carrying e(s,s') W(s,s') instead of W(s,s')
+ *           (e = -J s s' or -J delta(s,s')): the mean energy <e_b> of one y
+ *           bond.  The internal energy per site of these isotropic models is
+ *           2 <e_b> - h <f>.
+ * For HOTRG_CUSTOM the slots hold Tr I / Tr T of the caller's tensors.
+ * Each carried tensor costs one more D^6 product and one D^7 product over
+ * twice the contraction length per step.  Synchronises; values[slot] gets
+ * the estimate, NaN for a slot not carried.  Errors: EINVAL, latched,
+ * ENONFINITE (Tr T = 0). */
+int hotrg_observables(hotrg_solve* s, double values[2]);
 
 /* Synchronises and reports the eigensolve of step n (1..steps taken):
  * iterations = subspace passes used (0 when E was diagonalised densely),

@@ -26,12 +26,19 @@ def stage_flops(dx: int, dy: int, dp: int) -> dict:
     }
 
 
-def step_flops(dx: int, dy: int, dp: int) -> float:
-    return sum(stage_flops(dx, dy, dp).values())
+def step_flops(dx: int, dy: int, dp: int, two_sided: bool = False, nimp: int = 0) -> float:
+    """Contraction FLOPs of one step.  Two-sided truncation builds a second
+    environment; each impurity tensor adds its X, a Y over twice the
+    contraction length and its T'."""
+    f = stage_flops(dx, dy, dp)
+    total = sum(f.values())
+    if two_sided:
+        total += f["env"]
+    return total + nimp * (f["x"] + 2.0 * f["y"] + f["tp"])
 
 
-def solve_flops(q: int, dmax: int, nsteps: int) -> float:
-    return sum(step_flops(*d) for d in step_dims(q, q, dmax, nsteps))
+def solve_flops(q: int, dmax: int, nsteps: int, two_sided: bool = False, nimp: int = 0) -> float:
+    return sum(step_flops(*d, two_sided=two_sided, nimp=nimp) for d in step_dims(q, q, dmax, nsteps))
 
 
 def y_flops(q: int, dmax: int, nsteps: int) -> float:

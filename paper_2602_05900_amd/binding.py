@@ -23,12 +23,15 @@ FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 MODELS = {"ising": ISING, "potts": POTTS, "custom": CUSTOM}
 MAX_STEPS = 60
-STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm"]
+STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm", "obs"]
+# observable slots (hotrg_observables): order parameter per site, energy of one y bond
+OBS_MAGNETIZATION, OBS_BOND_ENERGY = 1, 2
+OBSERVABLES = {"m": OBS_MAGNETIZATION, "e": OBS_BOND_ENERGY}
 
 EXPORTS = [
     "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain",
     "hotrg_coarse_grain_batch", "hotrg_log_z",
-    "hotrg_step_info", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
+    "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
 ]
@@ -52,6 +55,10 @@ class Params(ctypes.Structure):
         ("custom_dx", ctypes.c_int),
         ("custom_dy", ctypes.c_int),
         ("max_steps", ctypes.c_int),
+        ("field", ctypes.c_double),
+        ("two_sided", ctypes.c_int),
+        ("observables", ctypes.c_int),
+        ("custom_impurity", ctypes.POINTER(ctypes.c_double) * 2),
     ]
 
 
@@ -78,6 +85,8 @@ def load() -> ctypes.CDLL:
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
     lib.hotrg_eig_info.argtypes = [c_void_p, c_int, P(c_int), P(c_int), P(c_double)]
+    lib.hotrg_step_sides.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_int)]
+    lib.hotrg_observables.argtypes = [c_void_p, P(c_double)]
     lib.hotrg_copy_tensor.argtypes = [c_void_p, P(c_double), c_size_t, P(c_int)]
     lib.hotrg_set_timing.argtypes = [c_void_p, c_int]
     lib.hotrg_stage_times.argtypes = [c_void_p, P(c_double), P(c_int)]
@@ -124,8 +133,12 @@ def runtime_version() -> int:
 
 
 def make_params(model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
-                precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0) -> tuple:
-    """hotrg_params plus the host array it points to (kept alive by the caller)."""
+                precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0,
+                field: float = 0.0, two_sided: bool = False, observables=(), impurities=None) -> tuple:
+    """hotrg_params plus the host arrays it points to (kept alive by the caller).
+
+    observables: names from OBSERVABLES ("m", "e"); for the custom model,
+    impurities maps each of them to a tensor of the custom tensor's dims."""
     p = Params()
     p.model = MODELS[model]
     p.q = q
@@ -134,14 +147,27 @@ def make_params(model: str = "ising", q: int = 2, temperature: float = 2.0, dmax
     p.dmax = dmax
     p.precision = PRECISIONS[precision]
     p.max_steps = max_steps
-    keep = None
+    p.field = field
+    p.two_sided = 1 if two_sided else 0
+    mask = 0
+    for o in observables:
+        mask |= OBSERVABLES[o]
+    p.observables = mask
+    keep = []
     if model == "custom":
         import numpy as np
-        keep = np.ascontiguousarray(tensor, dtype=np.float64)
-        if keep.ndim != 4 or keep.shape[0] != keep.shape[1] or keep.shape[2] != keep.shape[3]:
+        t = np.ascontiguousarray(tensor, dtype=np.float64)
+        if t.ndim != 4 or t.shape[0] != t.shape[1] or t.shape[2] != t.shape[3]:
             raise ValueError("custom tensor must have dims [Dx, Dx, Dy, Dy]")
-        p.custom_tensor = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.custom_dx, p.custom_dy = keep.shape[0], keep.shape[2]
+        keep.append(t)
+        p.custom_tensor = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.custom_dx, p.custom_dy = t.shape[0], t.shape[2]
+        for o in observables:
+            imp = np.ascontiguousarray((impurities or {})[o], dtype=np.float64)
+            if imp.shape != t.shape:
+                raise ValueError("impurity tensors must have the custom tensor's dims")
+            keep.append(imp)
+            p.custom_impurity[OBSERVABLES[o] - 1] = imp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return p, keep
 
 
@@ -156,10 +182,12 @@ class Solve:
 
     def __init__(self, model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
                  precision: str = "fp64", coupling: float = 1.0, tensor=None, stream=None,
-                 workspace=None, device="cuda", max_steps: int = 0):
+                 workspace=None, device="cuda", max_steps: int = 0, field: float = 0.0,
+                 two_sided: bool = False, observables=(), impurities=None):
         lib = load()
         self._lib = lib
-        p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps)
+        p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps,
+                              field, two_sided, observables, impurities)
         nbytes = lib.hotrg_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise HotrgError(EINVAL, "hotrg_workspace_bytes")
@@ -177,9 +205,11 @@ class Solve:
         self._h = h
 
     def reset(self, model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
-              precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0) -> "Solve":
+              precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0,
+              field: float = 0.0, two_sided: bool = False, observables=(), impurities=None) -> "Solve":
         """Restart this handle (same workspace, stream and eigensolver context)."""
-        p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps)
+        p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps,
+                              field, two_sided, observables, impurities)
         _check(self._lib.hotrg_reset(self._h, ctypes.byref(p)), "hotrg_reset")
         del keep
         self.temperature = temperature
@@ -203,6 +233,19 @@ class Solve:
         _check(self._lib.hotrg_step_info(self._h, int(n), ctypes.byref(c), ctypes.byref(e), ctypes.byref(g)),
                "hotrg_step_info")
         return c.value, e.value, g.value
+
+    def step_sides(self, n: int):
+        """(eps_left, eps_right, side) of step n (two-sided truncation)."""
+        el, er, sd = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _check(self._lib.hotrg_step_sides(self._h, int(n), ctypes.byref(el), ctypes.byref(er), ctypes.byref(sd)),
+               "hotrg_step_sides")
+        return el.value, er.value, sd.value
+
+    def observables(self):
+        """{"m": <m>, "e": <e_b>} of the carried impurity tensors (NaN when not carried)."""
+        v = (ctypes.c_double * 2)()
+        _check(self._lib.hotrg_observables(self._h, v), "hotrg_observables")
+        return {"m": v[0], "e": v[1]}
 
     def eig_info(self, n: int):
         """(subspace passes, Jacobi sweeps, relative residual) of step n's eigensolve."""

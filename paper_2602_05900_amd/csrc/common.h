@@ -31,12 +31,21 @@ inline size_t fmt_elem_bytes(Fmt f) { return fmt_plane_elem_bytes(f) * fmt_plane
 // panels (BF16 formats only): element (r, c) at
 //   ((r / 32) * (panel_k / 16) + c / 16) * 512 + (r % 32) * 16 + c % 16,
 // so that the 32 rows x 16 columns a product kernel stages per K step are
-// one contiguous KiB.  Rows must be a multiple of 32, panel_k of 16.
+// one contiguous KiB.  Rows must be a multiple of 32, panel_k of 16.  As a
+// product operand, ptr may point at column c0 (a multiple of 16) of a wider
+// panel matrix: the operand is then columns c0 .. c0 + K - 1 and lda equals
+// panel_k.
+//
+// cols != 0 makes ptr a block of `cols` columns inside a wider matrix for the
+// element-wise writers: logical element i is (i / cols, i % cols), stored at
+// row stride ld (row-major) or at panel_index() of the panel_k-wide layout.
 struct Buf {
     void* ptr;
     Fmt fmt;
     size_t plane;      // elements between planes (>= count, rounded up)
     long panel_k = 0;  // 0: row-major; else the row length of the panel layout
+    long cols = 0;     // 0: dense; else the column count of a sub-block
+    long ld = 0;       // row stride of a row-major sub-block (cols != 0, panel_k == 0)
 };
 
 __host__ __device__ inline long panel_index(long r, long c, long panel_k) {
@@ -88,6 +97,16 @@ struct DevState {
     int info[64];         // eigensolver iterations per step (0: dense Jacobi of E)
     int eig_sweeps[64];   // Jacobi sweeps of the last Rayleigh-Ritz problem per step
     double eig_resid[64]; // max residual / theta_0 of the kept Ritz pairs per step
+    // two-sided truncation: both sides' discarded weights, the side applied
+    // (0 left, 1 right) and the right eigensolve's diagnostics per step
+    double eps_left[64];
+    double eps_right[64];
+    int side[64];
+    double r_cut_gap[64];
+    int r_info[64];
+    int r_sweeps[64];
+    double r_resid[64];
+    double imp_trace[2];  // sum_{x,y} I[x,x,y,y] of the impurity tensors
     double partial[1024]; // partial maxima of the normalisation reduction
 };
 
@@ -135,14 +154,26 @@ inline int eig_block(int n, int k) {
 // isometry Ut / Ux (see launch_select_isometry) with the sign gauge; step
 // diagnostics into st.  warm: V[parity] already holds the Ritz block of the
 // step two earlier with the same (n, p).
+// slot 0 records the diagnostics as the step's own (and eps_left), slot 1 as
+// the right environment's (eps_right, r_*).
 hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
                            unsigned long long seed, int maxit, double tol, const Buf& Ut, const Buf& Ux,
-                           DevState* st, int step, hipStream_t stream);
+                           DevState* st, int step, hipStream_t stream, int slot = 0);
+
+// Two-sided truncation: when eps_right[step] < eps_left[step], copies the
+// right isometry (UtR, UxR: `bytes` bytes each, 16-byte multiple) over the
+// left one and makes the right side's diagnostics the step's own; records
+// the side either way.
+hipError_t launch_choose_side(DevState* st, int step, void* Ut, void* Ux, const void* UtR, const void* UxR,
+                              size_t bytes, hipStream_t stream);
 
 // Normalisation of step n: c_n = max|T|, T /= c_n, lnz_acc += ln(c_n) / 2^n.
 hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStream_t stream);
-// trace = sum_{x,y} T[x,x,y,y] for T of dims [Dx,Dx,Dy,Dy].
-hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream);
+// trace = sum_{x,y} T[x,x,y,y] for T of dims [Dx,Dx,Dy,Dy] (into *out, a
+// device address, default st->trace).
+hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream, double* out = nullptr);
+// I <- I * factor / c_n (c_n of the last normalisation, read on the device).
+hipError_t launch_scale_by_norm(double* I, size_t count, const DevState* st, double factor, hipStream_t stream);
 // E <- (E + E^T) / 2 for an n x n matrix.
 hipError_t launch_symmetrize(double* E, int n, hipStream_t stream);
 

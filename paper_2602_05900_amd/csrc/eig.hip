@@ -602,7 +602,7 @@ __global__ __launch_bounds__(256) void eig_select_kernel(const double* __restric
 }
 
 __global__ __launch_bounds__(64) void eig_stats_kernel(const double* __restrict__ theta, int p, int n, int k,
-                                                       const EigCtl* ctl, DevState* st, int step) {
+                                                       const EigCtl* ctl, DevState* st, int step, int slot) {
     if (threadIdx.x != 0 || step >= 64) return;
     double err;
     if (p == n) {   // every eigenvalue known: discarded weight summed directly
@@ -618,26 +618,75 @@ __global__ __launch_bounds__(64) void eig_stats_kernel(const double* __restrict_
         const double tr = ctl->trace;
         err = tr != 0.0 ? (tr - kept) / tr : 0.0;
     }
-    st->trunc_err[step] = err;
-    st->cut_gap[step] = k < n ? (k < p ? (theta[k - 1] - theta[k]) / theta[0] : NAN) : INFINITY;
-    st->info[step] = ctl->iters;
-    st->eig_resid[step] = ctl->resid;
-    st->eig_sweeps[step] = ctl->sweeps;
+    const double gap = k < n ? (k < p ? (theta[k - 1] - theta[k]) / theta[0] : NAN) : INFINITY;
+    if (slot == 0) {
+        st->trunc_err[step] = err;
+        st->eps_left[step] = err;
+        st->cut_gap[step] = gap;
+        st->info[step] = ctl->iters;
+        st->eig_resid[step] = ctl->resid;
+        st->eig_sweeps[step] = ctl->sweeps;
+        st->side[step] = 0;
+    } else {
+        st->eps_right[step] = err;
+        st->r_cut_gap[step] = gap;
+        st->r_info[step] = ctl->iters;
+        st->r_resid[step] = ctl->resid;
+        st->r_sweeps[step] = ctl->sweeps;
+    }
+}
+
+// Two-sided truncation (the side with the smaller discarded weight wins,
+// ties keep the left one).  Every block reads the same two numbers, so all
+// take the same branch; block 0 records the outcome.
+__global__ __launch_bounds__(256) void choose_side_kernel(DevState* st, int step, uint4* __restrict__ Ut,
+                                                          uint4* __restrict__ Ux, const uint4* __restrict__ UtR,
+                                                          const uint4* __restrict__ UxR, size_t words) {
+    if (step >= 64) return;
+    const bool right = st->eps_right[step] < st->eps_left[step];
+    if (right) {
+        for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) {
+            Ut[i] = UtR[i];
+            Ux[i] = UxR[i];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->side[step] = right ? 1 : 0;
+        if (right) {
+            st->trunc_err[step] = st->eps_right[step];
+            st->cut_gap[step] = st->r_cut_gap[step];
+            st->info[step] = st->r_info[step];
+            st->eig_resid[step] = st->r_resid[step];
+            st->eig_sweeps[step] = st->r_sweeps[step];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- host side
 
 static unsigned grid_for(long count, int per) { return (unsigned)((count + per - 1) / per); }
 
+hipError_t launch_choose_side(DevState* st, int step, void* Ut, void* Ux, const void* UtR, const void* UxR,
+                              size_t bytes, hipStream_t stream) {
+    if (bytes % 16) return hipErrorInvalidValue;
+    const size_t words = bytes / 16;
+    unsigned blocks = grid_for((long)words, 256);
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(choose_side_kernel, dim3(blocks), dim3(256), 0, stream, st, step, static_cast<uint4*>(Ut),
+                       static_cast<uint4*>(Ux), static_cast<const uint4*>(UtR), static_cast<const uint4*>(UxR), words);
+    return hipGetLastError();
+}
+
 hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
                            unsigned long long seed, int maxit, double tol, const Buf& Ut, const Buf& Ux,
-                           DevState* st, int step, hipStream_t stream) {
+                           DevState* st, int step, hipStream_t stream, int slot) {
     if (n < 1 || k < 1 || k > n) return hipErrorInvalidValue;
     if (n <= EIG_PMAX) {
         hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(256), 0, stream, E, n, (double*)nullptr, 0, 1, seed, w.ctl);
         hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(EIG_JT), 0, stream, E, n, n, w.theta, w.S, w.ctl, 0);
         hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, w.S, n, n, dx, k, Ut, Ux);
-        hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, n, n, k, w.ctl, st, step);
+        hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, n, n, k, w.ctl, st, step, slot);
         return hipGetLastError();
     }
     const int p = eig_block(n, k);
@@ -699,7 +748,7 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
                            seed * 131 + it, w.ctl);
     }
     hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, V, p, n, dx, k, Ut, Ux);
-    hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, p, n, k, w.ctl, st, step);
+    hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, p, n, k, w.ctl, st, step, slot);
     return hipGetLastError();
 }
 

@@ -603,7 +603,8 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     // start (with its swizzled k chunk) and the LDS offset of the KiB it fills
     const int lrow = lane >> 1;
     // An operand in the panel layout (PA, PB: 32 x 16 panels, rows a
-    // multiple of 32, row length K) gives each wave load one contiguous KiB
+    // multiple of 32, row length lda / ldb >= K, the operand starting at a
+    // 16-column boundary of it) gives each wave load one contiguous KiB
     // (32 cache lines per KiB become 8); the K step then advances by a panel.
     const __bf16* gsrc[LPW];
     int dsto[LPW];
@@ -622,7 +623,8 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         if (panel) {
             const int last = ((isA ? M : N) + 31) / 32 - 1;
             const int blk = min(((isA ? m0 : n0) >> 5) + rb, last);
-            gsrc[j] = (isA ? A + pl * a_plane : B + pl * b_plane) + (long)blk * (K >> 4) * 512 + lrow * 16 + 8 * c;
+            gsrc[j] = (isA ? A + pl * a_plane : B + pl * b_plane) + (long)blk * ((isA ? lda : ldb) >> 4) * 512 +
+                      lrow * 16 + 8 * c;
             kmul[j] = 32;   // panel (k / 16) starts at 512 (k / 16) elements
         } else {
             const int row = isA ? min(m0 + rloc, M - 1) : min(ncol(rloc), N - 1);
@@ -854,13 +856,13 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
     (void)products;
     const bool split = A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3;
     if (A.panel_k || B.panel_k) {
-        // panel-layout operands (row length K, whole 32-row panels) go to the
-        // direct-to-LDS kernel: both operands of the environment products and
-        // of Y, the A operand (Y itself) of T'
+        // panel-layout operands (row length lda / ldb >= K, whole 32-row
+        // panels) go to the direct-to-LDS kernel: both operands of the
+        // environment products and of Y, the A operand (Y itself) of T'
         const bool base = split && K >= 16 && K % 16 == 0 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
                           ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0 &&
-                          (!A.panel_k || (A.panel_k == K && M % 32 == 0)) &&
-                          (!B.panel_k || (B.panel_k == K && N % 32 == 0));
+                          (!A.panel_k || (A.panel_k == lda && K <= lda && lda % 16 == 0 && M % 32 == 0)) &&
+                          (!B.panel_k || (B.panel_k == ldb && K <= ldb && ldb % 16 == 0 && N % 32 == 0));
         const bool both = base && A.panel_k && B.panel_k && N > 64;
         if constexpr (ROLE == 0) {
             // half environments and E (N = K = D^2): mid-size tiles

@@ -15,6 +15,14 @@
 //   P4 = T as [(u,r), (l,d)]; Y[l,d,u,r1,r2] = X P4^T            (K = Dx Dy, the D^7 term)
 //   T'[d,u,l,r] = Y Ut^T  (written already x<->y exchanged)      (K = Dx^2)
 //   c_n = max|T'|, T' /= c_n, ln Z accumulator += ln(c_n) / 2^n
+// Two-sided truncation (HOTRG's choice between the two fused legs) also
+// builds the right environment from P1, P2 of the mirrored tensor, solves it
+// and keeps the isometry with the smaller discarded weight, on the device.
+// Impurity tensors I (observables) follow T with the same isometry:
+//   X_I = U P3(I)^T;  Y_I = [X_I | X] [P4(T) | P4(I)]^T  (one product, K = 2 Dx Dy)
+//   I' = Y_I Ut^T / (2 c_n)
+// X, X_I and P4(T), P4(I) are column blocks of two wide operand buffers, so
+// each Y_I is a single launch over the doubled K.
 // All products are the one index-mapped MFMA kernel (gemm.hip).
 #include <math.h>
 #include <string.h>
@@ -31,7 +39,7 @@ using namespace hotrg;
 namespace {
 
 constexpr int kMaxQ = 16;
-constexpr int kEventsPerStep = 10;
+constexpr int kEventsPerStep = 11;
 
 struct StepDims {
     int dx, dy, dp;
@@ -70,10 +78,15 @@ size_t buf_bytes(Fmt f, size_t count) {
     return (size_t)fmt_planes(f) * round_up(std::max<size_t>(count, 1), 64) * fmt_plane_elem_bytes(f);
 }
 
+int popcount2(int m) { return (m & 1) + ((m >> 1) & 1); }
+
 struct Layout {
     size_t nT = 0, nP = 0, nAB = 0, nE = 0, nU = 0, nX = 0, nEig = 0;
+    int nimp = 0;   // impurity tensors carried (one per observable slot set)
     size_t oState, oT, oPa, oPb, oAh, oBh, oE, oEigV0, oEigV1, oEigW, oEigPart, oEigG, oEigS, oEigTheta, oEigL,
         oEigD, oEigCtl, oUt, oUx, oX, oY, total;
+    size_t oI[2] = {0, 0};                                   // impurity tensors (FP64)
+    size_t oER = 0, oEigVR0 = 0, oEigVR1 = 0, oUtR = 0, oUxR = 0;  // two-sided
 };
 
 constexpr double kEigTol = 1e-12;
@@ -84,6 +97,9 @@ int step_cap(const hotrg_params* p) { return p->max_steps > 0 ? p->max_steps : H
 bool valid_params(const hotrg_params* p) {
     if (!p) return false;
     if (p->max_steps < 0 || p->max_steps > HOTRG_MAX_STEPS) return false;
+    if (p->two_sided != 0 && p->two_sided != 1) return false;
+    if (p->observables & ~(HOTRG_OBS_MAGNETIZATION | HOTRG_OBS_BOND_ENERGY)) return false;
+    if (!isfinite(p->field)) return false;
     if (p->dmax < 1 || p->dmax > HOTRG_MAX_DIM) return false;
     if (p->precision < HOTRG_FP64 || p->precision > HOTRG_BF16X6) return false;
     if (p->model == HOTRG_ISING) {
@@ -94,6 +110,9 @@ bool valid_params(const hotrg_params* p) {
         if (!p->custom_tensor) return false;
         if (p->custom_dx < 1 || p->custom_dx > HOTRG_MAX_DIM) return false;
         if (p->custom_dy < 1 || p->custom_dy > HOTRG_MAX_DIM) return false;
+        if (p->field != 0.0) return false;
+        for (int j = 0; j < 2; ++j)
+            if ((p->observables >> j & 1) && !p->custom_impurity[j]) return false;
         return true;
     } else {
         return false;
@@ -144,6 +163,8 @@ Layout plan(const hotrg_params* p) {
         L.nX = std::max(L.nX, dp * x * x * y * y);
     }
     const Fmt f = fmt_of(p->precision);
+    L.nimp = popcount2(p->observables);
+    const size_t wide = 1 + (size_t)L.nimp;   // column blocks of the X and P4 operands
     size_t o = 0;
     auto take = [&](size_t bytes) {
         const size_t at = o;
@@ -152,8 +173,9 @@ Layout plan(const hotrg_params* p) {
     };
     L.oState = take(sizeof(DevState));
     L.oT = take(buf_bytes(Fmt::F64, L.nT));
+    for (int j = 0; j < L.nimp; ++j) L.oI[j] = take(buf_bytes(Fmt::F64, L.nT));
     L.oPa = take(buf_bytes(f, L.nP));
-    L.oPb = take(buf_bytes(f, L.nP));
+    L.oPb = take(buf_bytes(f, L.nP * wide));
     L.oAh = take(buf_bytes(f, L.nAB));
     L.oBh = take(buf_bytes(f, L.nAB));
     L.oE = take(buf_bytes(Fmt::F64, L.nE));
@@ -170,7 +192,14 @@ Layout plan(const hotrg_params* p) {
     L.oEigCtl = take(sizeof(EigCtl));
     L.oUt = take(buf_bytes(f, L.nU));
     L.oUx = take(buf_bytes(f, L.nU));
-    L.oX = take(buf_bytes(f, L.nX));
+    if (p->two_sided) {
+        L.oER = take(buf_bytes(Fmt::F64, L.nE));
+        L.oEigVR0 = take(8 * L.nEig * pb);
+        L.oEigVR1 = take(8 * L.nEig * pb);
+        L.oUtR = take(buf_bytes(f, L.nU));
+        L.oUxR = take(buf_bytes(f, L.nU));
+    }
+    L.oX = take(buf_bytes(f, L.nX * wide));
     L.oY = take(buf_bytes(f, L.nX));
     L.total = o;
     return L;
@@ -180,14 +209,29 @@ Buf make_buf(char* base, size_t off, Fmt f, size_t count) {
     return Buf{base + off, f, round_up(std::max<size_t>(count, 1), 64)};
 }
 
-// T0[x,x',y,y'] = sum_s Q[s,x]Q[s,x']Q[s,y]Q[s,y'], Q = W^(1/2).  W = a I + b 1 1^T
-// for both models (Ising: a = 2 sinh(beta J), b = exp(-beta J); Potts:
-// a = exp(beta J) - 1, b = 1), so Q = sqrt(a) I + (sqrt(a + q b) - sqrt(a)) / q 1 1^T.
-std::vector<double> model_tensor(const hotrg_params* p) {
+// T0[x,x',y,y'] = sum_s g(s) Q[s,x]Q[s,x']Q[s,y]Q[s,y'], Q = W^(1/2), g(s) =
+// exp(beta h f(s)) the field's site factor (f = sigma for Ising with s = 0
+// the +1 state, f = delta(s, 0) for Potts).  W = a I + b 1 1^T for both
+// models (Ising: a = 2 sinh(beta J), b = exp(-beta J); Potts:
+// a = exp(beta J) - 1, b = 1), so Q = sqrt(a) I + c 1 1^T with
+// c = (sqrt(a + q b) - sqrt(a)) / q, and Q^-1 = (I - c / (sqrt(a) + q c) 1 1^T) / sqrt(a).
+// Impurity tensors of the observables:
+//   slot 0 (order parameter m(s) = sigma, or (q delta(s,0) - 1)/(q - 1)):
+//     S = sum_s m(s) g(s) Q[s,.]^4, one copy giving Z <m>;
+//   slot 1 (bond energy e(s,s') = -J sigma sigma', or -J delta(s,s')): T0
+//     with its d leg contracted with G = Q^-1 (e o W) Q^-1, so the y bond
+//     below the site carries e(s,s') W(s,s'); one copy gives Z <e_b>.
+struct ModelTensors {
+    std::vector<double> T, I[2];
+};
+
+ModelTensors model_tensors(const hotrg_params* p) {
     const int q = p->q;
-    const double bj = p->coupling / p->temperature;
+    const double beta = 1.0 / p->temperature;
+    const double bj = p->coupling * beta;
+    const bool ising = p->model == HOTRG_ISING;
     double a, b;
-    if (p->model == HOTRG_ISING) {
+    if (ising) {
         a = 2.0 * sinh(bj);
         b = exp(-bj);
     } else {
@@ -196,20 +240,65 @@ std::vector<double> model_tensor(const hotrg_params* p) {
     }
     const double sa = sqrt(a);
     const double off = (sqrt(a + q * b) - sa) / q;
-    std::vector<double> Q((size_t)q * q);
+    std::vector<double> Q((size_t)q * q), Qi((size_t)q * q), We((size_t)q * q);
+    const double ioff = -off / (sa * (sa + q * off));
     for (int i = 0; i < q; ++i)
-        for (int j = 0; j < q; ++j) Q[(size_t)i * q + j] = off + (i == j ? sa : 0.0);
-    std::vector<double> T((size_t)q * q * q * q, 0.0);
-    for (int x = 0; x < q; ++x)
-        for (int xp = 0; xp < q; ++xp)
-            for (int y = 0; y < q; ++y)
-                for (int yp = 0; yp < q; ++yp) {
-                    double s = 0.0;
-                    for (int k = 0; k < q; ++k)
-                        s += Q[(size_t)k * q + x] * Q[(size_t)k * q + xp] * Q[(size_t)k * q + y] * Q[(size_t)k * q + yp];
-                    T[(((size_t)x * q + xp) * q + y) * q + yp] = s;
-                }
-    return T;
+        for (int j = 0; j < q; ++j) {
+            Q[(size_t)i * q + j] = off + (i == j ? sa : 0.0);
+            Qi[(size_t)i * q + j] = ioff + (i == j ? 1.0 / sa : 0.0);
+            const double w = (i == j ? a : 0.0) + b;
+            const double e = ising ? -p->coupling * (i == j ? 1.0 : -1.0) : (i == j ? -p->coupling : 0.0);
+            We[(size_t)i * q + j] = e * w;
+        }
+    std::vector<double> g(q), m(q);
+    for (int k = 0; k < q; ++k) {
+        const double fs = ising ? (k == 0 ? 1.0 : -1.0) : (k == 0 ? 1.0 : 0.0);
+        g[k] = exp(beta * p->field * fs);
+        m[k] = ising ? (k == 0 ? 1.0 : -1.0) : (k == 0 ? 1.0 : -1.0 / (q - 1.0));
+    }
+    auto site = [&](const std::vector<double>& wts) {
+        std::vector<double> T((size_t)q * q * q * q, 0.0);
+        for (int x = 0; x < q; ++x)
+            for (int xp = 0; xp < q; ++xp)
+                for (int y = 0; y < q; ++y)
+                    for (int yp = 0; yp < q; ++yp) {
+                        double s = 0.0;
+                        for (int k = 0; k < q; ++k)
+                            s += wts[k] * Q[(size_t)k * q + x] * Q[(size_t)k * q + xp] * Q[(size_t)k * q + y] *
+                                 Q[(size_t)k * q + yp];
+                        T[(((size_t)x * q + xp) * q + y) * q + yp] = s;
+                    }
+        return T;
+    };
+    ModelTensors mt;
+    mt.T = site(g);
+    if (p->observables & HOTRG_OBS_MAGNETIZATION) {
+        std::vector<double> mg(q);
+        for (int k = 0; k < q; ++k) mg[k] = m[k] * g[k];
+        mt.I[0] = site(mg);
+    }
+    if (p->observables & HOTRG_OBS_BOND_ENERGY) {
+        // G = Qi We Qi
+        std::vector<double> t((size_t)q * q, 0.0), G((size_t)q * q, 0.0);
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j)
+                for (int k = 0; k < q; ++k) t[(size_t)i * q + j] += Qi[(size_t)i * q + k] * We[(size_t)k * q + j];
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j)
+                for (int k = 0; k < q; ++k) G[(size_t)i * q + j] += t[(size_t)i * q + k] * Qi[(size_t)k * q + j];
+        std::vector<double> TG((size_t)q * q * q * q, 0.0);
+        for (int x = 0; x < q; ++x)
+            for (int xp = 0; xp < q; ++xp)
+                for (int y = 0; y < q; ++y)
+                    for (int yp = 0; yp < q; ++yp) {
+                        double s = 0.0;
+                        for (int k = 0; k < q; ++k)
+                            s += G[(size_t)y * q + k] * mt.T[(((size_t)x * q + xp) * q + k) * q + yp];
+                        TG[(((size_t)x * q + xp) * q + y) * q + yp] = s;
+                    }
+        mt.I[1] = TG;
+    }
+    return mt;
 }
 
 }  // namespace
@@ -226,6 +315,9 @@ struct hotrg_solve {
     int host_status = HOTRG_OK;
     int warm_n[2] = {0, 0};   // (n, p) of the Ritz block kept per step parity
     int warm_p[2] = {0, 0};
+    int warm_nr[2] = {0, 0};  // the same for the right environment (two-sided)
+    int warm_pr[2] = {0, 0};
+    int imp_slot[2] = {0, 0}; // observable slot of each carried impurity tensor
     bool timing = false;
     int timed_from = 0;  // first step recorded with events
     std::vector<hipEvent_t> ev;
@@ -245,7 +337,14 @@ struct hotrg_solve {
         w.ctl = reinterpret_cast<EigCtl*>(ws + L.oEigCtl);
         return w;
     }
+    EigWork eig_right() const {
+        EigWork w = eig();
+        w.V[0] = reinterpret_cast<double*>(ws + L.oEigVR0);
+        w.V[1] = reinterpret_cast<double*>(ws + L.oEigVR1);
+        return w;
+    }
     double* T() const { return reinterpret_cast<double*>(ws + L.oT); }
+    double* I(int j) const { return reinterpret_cast<double*>(ws + L.oI[j]); }
 };
 
 #define HIP_TRY(s, x)                                  \
@@ -277,6 +376,17 @@ int gemm(hotrg_solve* s, const Buf& A, long lda, const Buf& B, long ldb, const B
     return HOTRG_OK;
 }
 
+// Column block `blk` (of width w columns) of a wide operand buffer: panel
+// layout of row length ld, or row-major with row stride ld.
+Buf column_block(const Buf& B, int blk, long w, long ld, bool panel) {
+    Buf o = B;
+    const size_t el = fmt_plane_elem_bytes(B.fmt);
+    const long off = panel ? (long)blk * (w / 16) * 512 : (long)blk * w;
+    o.ptr = static_cast<char*>(B.ptr) + (size_t)off * el;
+    o.panel_k = panel ? ld : 0;
+    return o;
+}
+
 int enqueue_step(hotrg_solve* s) {
     const int n = s->steps + 1;       // 1-based step number
     const int Dx = s->dx, Dy = s->dy;
@@ -284,11 +394,13 @@ int enqueue_step(hotrg_solve* s) {
     const int nE = Dx * Dx;
     const Fmt f = s->fmt;
     const Layout& L = s->L;
+    const int nimp = L.nimp;
+    const bool two = s->p.two_sided != 0;
     char* w = s->ws;
-    const Buf Pa = make_buf(w, L.oPa, f, L.nP), Pb = make_buf(w, L.oPb, f, L.nP);
+    const Buf Pa = make_buf(w, L.oPa, f, L.nP), Pb = make_buf(w, L.oPb, f, L.nP * (1 + nimp));
     const Buf Ah = make_buf(w, L.oAh, f, L.nAB), Bh = make_buf(w, L.oBh, f, L.nAB);
     const Buf Ut = make_buf(w, L.oUt, f, L.nU), Ux = make_buf(w, L.oUx, f, L.nU);
-    const Buf X = make_buf(w, L.oX, f, L.nX), Y = make_buf(w, L.oY, f, L.nX);
+    const Buf X = make_buf(w, L.oX, f, L.nX * (1 + nimp)), Y = make_buf(w, L.oY, f, L.nX);
     double* E = reinterpret_cast<double*>(w + L.oE);
     const Buf Ebuf{E, Fmt::F64, 0};
     const Buf Tbuf{s->T(), Fmt::F64, 0};
@@ -310,38 +422,57 @@ int enqueue_step(hotrg_solve* s) {
         P1b.panel_k = P2b.panel_k = mxy;
         Ahb.panel_k = Bhb.panel_k = myy;
     }
-    record(s, step_index, 0);
-    {
-        const int p1[4] = {0, 3, 1, 2};  // P1[l,u,r,d]
-        const int p2[4] = {0, 2, 1, 3};  // P2[l,d,r,u]
+    const int m = Dx * Dy;
+    // rows (a, k), columns (b, k') -> [a,b,k,k'], i.e. row a Dx + b and
+    // column k Dy + k' of E's [Dx^2 x Dy^2] operand
+    const OutMap half = panel_env ? OutMap{Dy, Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, myy}
+                                  : OutMap{Dy, (long)Dx * Dy * Dy, Dy, Dy, (long)Dy * Dy, 1};
+    const OutMap env{Dx, (long)Dx * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};  // -> E[(a1a2),(b1b2)]
+    // The left environment takes P1 = T as [(l,u),(r,d)], P2 = T as
+    // [(l,d),(r,u)]; the right one the same re-layouts of the mirrored
+    // tensor T[r,l,d,u]: [(r,u),(l,d)] and [(r,d),(l,u)].
+    auto environment = [&](const int* p1, const int* p2, double* Eout) -> int {
+        int r;
         HIP_TRY(s, launch_permute4(s->T(), dims, p1, P1b, s->stream));
         HIP_TRY(s, launch_permute4(s->T(), dims, p2, P2b, s->stream));
-    }
-    record(s, step_index, 1);
+        if (Eout == E) record(s, step_index, 1);
+        if ((r = gemm(s, P1b, m, P1b, m, Ah, m, m, m, half))) return r;
+        if ((r = gemm(s, P2b, m, P2b, m, Bh, m, m, m, half))) return r;
+        const Buf Eo{Eout, Fmt::F64, 0};
+        if ((r = gemm(s, Ahb, (long)Dy * Dy, Bhb, (long)Dy * Dy, Eo, nE, nE, Dy * Dy, env))) return r;
+        HIP_TRY(s, launch_symmetrize(Eout, nE, s->stream));
+        return HOTRG_OK;
+    };
+    record(s, step_index, 0);
     {
-        const int m = Dx * Dy;
-        // rows (a, k), columns (b, k') -> [a,b,k,k'], i.e. row a Dx + b and
-        // column k Dy + k' of E's [Dx^2 x Dy^2] operand
-        const OutMap half = panel_env ? OutMap{Dy, Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, myy}
-                                      : OutMap{Dy, (long)Dx * Dy * Dy, Dy, Dy, (long)Dy * Dy, 1};
-        if ((rc = gemm(s, P1b, m, P1b, m, Ah, m, m, m, half))) return rc;
-        if ((rc = gemm(s, P2b, m, P2b, m, Bh, m, m, m, half))) return rc;
-        const OutMap env{Dx, (long)Dx * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};  // -> E[(a1a2),(b1b2)]
-        if ((rc = gemm(s, Ahb, (long)Dy * Dy, Bhb, (long)Dy * Dy, Ebuf, nE, nE, Dy * Dy, env))) return rc;
-        HIP_TRY(s, launch_symmetrize(E, nE, s->stream));
+        const int p1[4] = {0, 3, 1, 2}, p2[4] = {0, 2, 1, 3};
+        if ((rc = environment(p1, p2, E))) return rc;
+    }
+    double* ER = two ? reinterpret_cast<double*>(w + L.oER) : nullptr;
+    if (two) {
+        const int p1[4] = {1, 3, 0, 2}, p2[4] = {1, 2, 0, 3};
+        if ((rc = environment(p1, p2, ER))) return rc;
     }
     record(s, step_index, 2);
-    // -- FP64 eigensolve and isometry
+    // -- FP64 eigensolve(s) and isometry
     {
         const int par = step_index & 1;
         const int pblk = nE > kEigPMax ? eig_block(nE, Dp) : nE;
-        const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;
         const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)n;
+        const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;
         HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, kEigMaxIt, kEigTol, Ut, Ux,
-                                   s->state(), n, s->stream));
+                                   s->state(), n, s->stream, 0));
+        if (two) {
+            const Buf UtR = make_buf(w, L.oUtR, f, L.nU), UxR = make_buf(w, L.oUxR, f, L.nU);
+            const bool warm_r = nE > kEigPMax && s->warm_nr[par] == nE && s->warm_pr[par] == pblk;
+            HIP_TRY(s, launch_eig_topk(ER, nE, Dp, Dx, s->eig_right(), par, warm_r, seed, kEigMaxIt,
+                                       kEigTol, UtR, UxR, s->state(), n, s->stream, 1));
+            HIP_TRY(s, launch_choose_side(s->state(), n, Ut.ptr, Ux.ptr, UtR.ptr, UxR.ptr, buf_bytes(f, L.nU),
+                                          s->stream));
+        }
         if (nE > kEigPMax) {
-            s->warm_n[par] = nE;
-            s->warm_p[par] = pblk;
+            s->warm_n[par] = s->warm_nr[par] = nE;
+            s->warm_p[par] = s->warm_pr[par] = pblk;
         }
     }
     record(s, step_index, 3);
@@ -349,81 +480,131 @@ int enqueue_step(hotrg_solve* s) {
     // both with rows of Kp = Dx Dy elements, are written in the 32 x 16 panel
     // layout when the split formats are used and the shapes allow it (Kp a
     // multiple of 32, more than 64 columns of Y), so that every tile load of
-    // the D^7 product is one contiguous KiB.
+    // the D^7 product is one contiguous KiB.  With impurity tensors both are
+    // column blocks of wider buffers (row length Kx):
+    //   X buffer:  [X_0 | X | X_1]        P4 buffer: [P4(I_1) | P4(T) | P4(I_0)]
+    // (one impurity: [X_0 | X] and [P4(T) | P4(I_0)]), so that
+    //   Y_0 = [X_0 | X] [P4(T) | P4(I_0)]^T and Y_1 = [X | X_1] [P4(I_1) | P4(T)]^T
+    // are single products over K = 2 Kp.
     const long Kp = (long)Dx * Dy;
-    const bool panel = (f == Fmt::BF16x2 || f == Fmt::BF16x3) && Kp % 32 == 0 && Kp > 64;
-    // -- X = U . T  -> X[l,d,r1,a2,k]
-    {
+    const long Kx = Kp * (1 + nimp);
+    const bool panel = split && Kp % 32 == 0 && Kp > 64;
+    const int xblk_T = nimp >= 1 ? 1 : 0;                 // X's block
+    const int bblk_T = nimp == 2 ? 1 : 0;                 // P4(T)'s block
+    auto xblk_imp = [&](int j) { return j == 0 ? 0 : 2; };
+    auto bblk_imp = [&](int j) { return nimp == 2 ? (j == 0 ? 2 : 0) : 1; };
+    // rows (l, a2), columns (d r1, k): offset l Dy Dx Kx + a2 Dy + (d r1) Kx + k,
+    // i.e. row l Dy Dx + (d r1) and column a2 Dy + k of the [Dp Dy Dx x Kp] block
+    // With Dy and Dx Dy multiples of 16, a tile takes 16 (d r1) x 16 k
+    // columns, so its rows of X are whole runs of 16 panel rows.
+    OutMap xm = panel ? OutMap{Dx, (long)Dy * Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, Kx}
+                      : OutMap{Dx, (long)Dy * Dx * Kx, Dy, Dy, Kx, 1};
+    if (panel && Dy % 16 == 0 && Kp % 16 == 0) xm.ngroup = Dy;
+    auto x_product = [&](const double* src, int blk) -> int {
         const int p3[4] = {2, 1, 3, 0};  // P3[d,r,u,l]
-        HIP_TRY(s, launch_permute4(s->T(), dims, p3, Pa, s->stream));
-    }
-    record(s, step_index, 4);
-    {
-        // rows (l, a2), columns (d r1, k): offset l Dy Dx Kp + a2 Dy + (d r1) Kp + k,
-        // i.e. row l Dy Dx + (d r1) and column a2 Dy + k of the [Dp Dy Dx x Kp] matrix
-        // With Dy and Dx Dy multiples of 16, a tile takes 16 (d r1) x 16 k
-        // columns, so its rows of X are whole runs of 16 panel rows.
-        OutMap xm = panel ? OutMap{Dx, (long)Dy * Dx, 0, Dy, 1, 0, 0, Dy, 0, 1, Kp}
-                          : OutMap{Dx, (long)Dy * Dx * Kp, Dy, Dy, Kp, 1};
-        if (panel && Dy % 16 == 0 && Kp % 16 == 0) xm.ngroup = Dy;
-        if ((rc = gemm(s, Ux, Dx, Pa, Dx, X, Dp * Dx, Dy * Dx * Dy, Dx, xm, GemmRole::X))) return rc;
-    }
+        HIP_TRY(s, launch_permute4(src, dims, p3, Pa, s->stream));
+        if (src == s->T()) record(s, step_index, 4);
+        Buf Xo = X;
+        Xo.ptr = column_block(X, blk, Kp, Kx, panel).ptr;
+        return gemm(s, Ux, Dx, Pa, Dx, Xo, Dp * Dx, Dy * Dx * Dy, Dx, xm, GemmRole::X);
+    };
+    auto p4_into = [&](const double* src, int blk) -> int {
+        const int p4[4] = {3, 1, 0, 2};  // P4[u,r,l,d]
+        Buf Po = column_block(Pb, blk, Kp, Kx, panel);
+        if (nimp) {
+            Po.cols = Kp;
+            Po.ld = Kx;
+        }
+        HIP_TRY(s, launch_permute4(src, dims, p4, Po, s->stream));
+        return HOTRG_OK;
+    };
+    const OutMap ym{Dx, (long)Dy * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};   // -> Y[l,d,u,r1,r2]
+    const OutMap tm{(long)Dy * Dy, Dp, (long)Dp * Dp, Dp, 0, 1};         // -> next T[d,u,l,r]
+    // -- X = U . T  -> X[l,d,r1,a2,k]
+    if ((rc = x_product(s->T(), xblk_T))) return rc;
     record(s, step_index, 5);
     // -- Y = X . T  -> Y[l,d,u,r1,r2]
-    Buf Xin = X, Pin = Pb;
-    if (panel) Xin.panel_k = Pin.panel_k = Kp;
-    {
-        const int p4[4] = {3, 1, 0, 2};  // P4[u,r,l,d]
-        HIP_TRY(s, launch_permute4(s->T(), dims, p4, Pin, s->stream));
-    }
+    if ((rc = p4_into(s->T(), bblk_T))) return rc;
     record(s, step_index, 6);
-    {
-        const OutMap ym{Dx, (long)Dy * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};
-        if ((rc = gemm(s, Xin, Kp, Pin, Kp, Y, Dp * Dy * Dx, Dy * Dx, (int)Kp, ym, GemmRole::Y))) return rc;
-    }
+    if ((rc = gemm(s, column_block(X, xblk_T, Kp, Kx, panel), Kx, column_block(Pb, bblk_T, Kp, Kx, panel), Kx, Y,
+                   Dp * Dy * Dx, Dy * Dx, (int)Kp, ym, GemmRole::Y)))
+        return rc;
     record(s, step_index, 7);
     // -- T' = Y . U  -> next T[d,u,l,r] (x <-> y exchanged), FP64
-    {
-        const OutMap tm{(long)Dy * Dy, Dp, (long)Dp * Dp, Dp, 0, 1};
-        if ((rc = gemm(s, Y, (long)Dx * Dx, Ut, (long)Dx * Dx, Tbuf, Dp * Dy * Dy, Dp, Dx * Dx, tm, GemmRole::TP)))
-            return rc;
-    }
+    if ((rc = gemm(s, Y, (long)Dx * Dx, Ut, (long)Dx * Dx, Tbuf, Dp * Dy * Dy, Dp, Dx * Dx, tm, GemmRole::TP)))
+        return rc;
     record(s, step_index, 8);
-    HIP_TRY(s, launch_normalize(s->T(), (size_t)Dy * Dy * Dp * Dp, s->state(), n, s->stream));
+    const size_t nnext = (size_t)Dy * Dy * Dp * Dp;
+    HIP_TRY(s, launch_normalize(s->T(), nnext, s->state(), n, s->stream));
     record(s, step_index, 9);
+    // -- impurity tensors: I' = U^T (I (x) T + T (x) I) U / (2 c_n)
+    if (nimp) {
+        for (int j = 0; j < nimp; ++j) {
+            if ((rc = x_product(s->I(j), xblk_imp(j)))) return rc;
+            if ((rc = p4_into(s->I(j), bblk_imp(j)))) return rc;
+        }
+        for (int j = 0; j < nimp; ++j) {
+            const int ax = j == 0 ? 0 : 1;                       // [X_0 | X] or [X | X_1]
+            const int bx = j == 0 ? bblk_T : 0;                  // [P4(T) | P4(I_0)] or [P4(I_1) | P4(T)]
+            if ((rc = gemm(s, column_block(X, ax, Kp, Kx, panel), Kx, column_block(Pb, bx, Kp, Kx, panel), Kx, Y,
+                           Dp * Dy * Dx, Dy * Dx, (int)(2 * Kp), ym, GemmRole::Y)))
+                return rc;
+            const Buf Io{s->I(j), Fmt::F64, 0};
+            if ((rc = gemm(s, Y, (long)Dx * Dx, Ut, (long)Dx * Dx, Io, Dp * Dy * Dy, Dp, Dx * Dx, tm, GemmRole::TP)))
+                return rc;
+            HIP_TRY(s, launch_scale_by_norm(s->I(j), nnext, s->state(), 0.5, s->stream));
+        }
+    }
+    record(s, step_index, 10);
     s->dx = Dy;
     s->dy = Dp;
     s->steps = n;
     return HOTRG_OK;
 }
 
-// Builds T0 for p on the host, normalises it by c_0 = max|T0|, uploads it and
-// a fresh device state (ln Z accumulator = ln c_0), and resets the step count.
+// Builds T0 (and the impurity tensors) for p on the host, normalises them by
+// c_0 = max|T0|, uploads them and a fresh device state (ln Z accumulator =
+// ln c_0), and resets the step count.
 int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     initial_dims(p, &s->dx, &s->dy);
     s->steps = 0;
     s->timed_from = 0;
-    s->warm_n[0] = s->warm_n[1] = 0;
-    s->warm_p[0] = s->warm_p[1] = 0;
-    std::vector<double> T0;
+    for (int i = 0; i < 2; ++i) s->warm_n[i] = s->warm_p[i] = s->warm_nr[i] = s->warm_pr[i] = 0;
+    const size_t count = (size_t)s->dx * s->dx * s->dy * s->dy;
+    ModelTensors mt;
     if (p->model == HOTRG_CUSTOM) {
-        T0.assign(p->custom_tensor, p->custom_tensor + (size_t)s->dx * s->dx * s->dy * s->dy);
+        mt.T.assign(p->custom_tensor, p->custom_tensor + count);
+        for (int j = 0; j < 2; ++j)
+            if (p->observables >> j & 1) mt.I[j].assign(p->custom_impurity[j], p->custom_impurity[j] + count);
     } else {
-        T0 = model_tensor(p);
+        mt = model_tensors(p);
     }
     double c0 = 0.0;
-    for (double v : T0) c0 = std::max(c0, fabs(v));
+    for (double v : mt.T) c0 = std::max(c0, fabs(v));
     if (!(c0 > 0.0) || !isfinite(c0)) return HOTRG_ENONFINITE;
-    for (double& v : T0) v /= c0;
+    for (double& v : mt.T) v /= c0;
+    int j = 0;
+    for (int slot = 0; slot < 2; ++slot) {
+        if (!(p->observables >> slot & 1)) continue;
+        for (double& v : mt.I[slot]) {
+            v /= c0;
+            if (!isfinite(v)) return HOTRG_ENONFINITE;
+        }
+        s->imp_slot[j++] = slot;
+    }
     std::vector<char> hs(sizeof(DevState), 0);
     DevState* h = reinterpret_cast<DevState*>(hs.data());
     h->lnz_acc = log(c0);
     h->c[0] = c0;
     h->c_cur = c0;
     if (hipMemcpyAsync(s->state(), h, sizeof(DevState), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->T(), T0.data(), T0.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
+        hipMemcpyAsync(s->T(), mt.T.data(), count * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess)
         return HOTRG_EHIP;
+    for (int i = 0; i < j; ++i)
+        if (hipMemcpyAsync(s->I(i), mt.I[s->imp_slot[i]].data(), count * sizeof(double), hipMemcpyHostToDevice,
+                           s->stream) != hipSuccess)
+            return HOTRG_EHIP;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return HOTRG_EHIP;
     return HOTRG_OK;
 }
 
@@ -451,6 +632,7 @@ int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes, v
     if (!s) return HOTRG_EINVAL;
     s->p = *p;
     s->p.custom_tensor = nullptr;
+    s->p.custom_impurity[0] = s->p.custom_impurity[1] = nullptr;
     s->stream = static_cast<hipStream_t>(stream);
     s->ws = static_cast<char*>(workspace);
     s->ws_bytes = ws_bytes;
@@ -477,6 +659,7 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
     s->L = L;
     s->p = *p;
     s->p.custom_tensor = nullptr;
+    s->p.custom_impurity[0] = s->p.custom_impurity[1] = nullptr;
     s->fmt = fmt_of(p->precision);
     s->products = products_of(p->precision);
     s->host_status = HOTRG_OK;
@@ -555,6 +738,35 @@ int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* 
     return HOTRG_OK;
 }
 
+int hotrg_step_sides(hotrg_solve* s, int n, double* eps_left, double* eps_right, int* side) {
+    if (!s || n < 1 || n > s->steps) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    if (eps_left) *eps_left = d.eps_left[n];
+    if (eps_right) *eps_right = s->p.two_sided ? d.eps_right[n] : NAN;
+    if (side) *side = d.side[n];
+    return HOTRG_OK;
+}
+
+int hotrg_observables(hotrg_solve* s, double values[2]) {
+    if (!s || !values) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    HIP_TRY(s, launch_trace(s->T(), s->dx, s->dy, s->state(), s->stream));
+    for (int j = 0; j < s->L.nimp; ++j)
+        HIP_TRY(s, launch_trace(s->I(j), s->dx, s->dy, s->state(), s->stream, &s->state()->imp_trace[j]));
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    if (!(d.trace != 0.0) || !isfinite(d.trace)) return HOTRG_ENONFINITE;
+    values[0] = values[1] = NAN;
+    for (int j = 0; j < s->L.nimp; ++j) values[s->imp_slot[j]] = d.imp_trace[j] / d.trace;
+    return HOTRG_OK;
+}
+
 int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]) {
     if (!s || !dims) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
@@ -607,6 +819,7 @@ int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed) {
         ms[HOTRG_STAGE_Y] += elapsed(s, i, 6, 7);
         ms[HOTRG_STAGE_TP] += elapsed(s, i, 7, 8);
         ms[HOTRG_STAGE_NORM] += elapsed(s, i, 8, 9);
+        ms[HOTRG_STAGE_OBS] += elapsed(s, i, 9, 10);
     }
     return HOTRG_OK;
 }

@@ -11,7 +11,12 @@ namespace hotrg {
 // ---------------------------------------------------------------- stores
 
 __device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
-    if (o.panel_k) idx = (size_t)panel_index((long)(idx / o.panel_k), (long)(idx % o.panel_k), o.panel_k);
+    if (o.cols) {
+        const long r = (long)(idx / o.cols), c = (long)(idx % o.cols);
+        idx = o.panel_k ? (size_t)panel_index(r, c, o.panel_k) : (size_t)(r * o.ld + c);
+    } else if (o.panel_k) {
+        idx = (size_t)panel_index((long)(idx / o.panel_k), (long)(idx % o.panel_k), o.panel_k);
+    }
     switch (o.fmt) {
         case Fmt::F64: static_cast<double*>(o.ptr)[idx] = v; break;
         case Fmt::F32: static_cast<float*>(o.ptr)[idx] = (float)v; break;
@@ -152,6 +157,21 @@ __global__ __launch_bounds__(256) void scale_kernel(double* __restrict__ T, size
         T[i] = T[i] / c;
 }
 
+__global__ __launch_bounds__(256) void scale_norm_kernel(double* __restrict__ I, size_t count, const DevState* st,
+                                                        double factor) {
+    const double f = factor / st->c_cur;
+    for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256)
+        I[i] = I[i] * f;
+}
+
+hipError_t launch_scale_by_norm(double* I, size_t count, const DevState* st, double factor, hipStream_t stream) {
+    size_t sb = (count + 255) / 256;
+    if (sb > 8192) sb = 8192;
+    if (sb < 1) sb = 1;
+    hipLaunchKernelGGL(scale_norm_kernel, dim3((unsigned)sb), dim3(256), 0, stream, I, count, st, factor);
+    return hipGetLastError();
+}
+
 hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStream_t stream) {
     size_t nb = (count + 255) / 256;
     if (nb > RED_BLOCKS) nb = RED_BLOCKS;
@@ -165,7 +185,7 @@ hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStr
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void trace_kernel(const double* __restrict__ T, int Dx, int Dy, DevState* st) {
+__global__ __launch_bounds__(256) void trace_kernel(const double* __restrict__ T, int Dx, int Dy, double* out) {
     __shared__ double sh[256];
     double s = 0.0;
     const int total = Dx * Dy;
@@ -174,11 +194,11 @@ __global__ __launch_bounds__(256) void trace_kernel(const double* __restrict__ T
         s += T[(((long)x * Dx + x) * Dy + y) * Dy + y];
     }
     s = block_sum<256>(s, sh);
-    if (threadIdx.x == 0) st->trace = s;
+    if (threadIdx.x == 0) *out = s;
 }
 
-hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream) {
-    hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, stream, T, Dx, Dy, st);
+hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream, double* out) {
+    hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, stream, T, Dx, Dy, out ? out : &st->trace);
     return hipGetLastError();
 }
 

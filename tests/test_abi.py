@@ -7,6 +7,7 @@ import re
 import subprocess
 import tempfile
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -49,17 +50,24 @@ def test_every_declared_function_is_exported(lib):
 def test_params_struct_matches_header(lib):
     from paper_2602_05900_amd import binding
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "hotrg.h"\n'
-           'int main(void){printf("%zu %zu %zu\\n", sizeof(hotrg_params), '
-           'offsetof(hotrg_params, custom_tensor), offsetof(hotrg_params, max_steps));return 0;}\n')
+           'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hotrg_params), '
+           'offsetof(hotrg_params, custom_tensor), offsetof(hotrg_params, max_steps), '
+           'offsetof(hotrg_params, field), offsetof(hotrg_params, two_sided), '
+           'offsetof(hotrg_params, observables), offsetof(hotrg_params, custom_impurity));return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "t")
         subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
-        size, off_t, off_m = (int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split())
+        out = subprocess.run([exe], capture_output=True, text=True).stdout.split()
+        size, off_t, off_m, off_f, off_2, off_o, off_i = (int(x) for x in out)
     assert ctypes.sizeof(binding.Params) == size
     assert binding.Params.custom_tensor.offset == off_t
     assert binding.Params.max_steps.offset == off_m
+    assert binding.Params.field.offset == off_f
+    assert binding.Params.two_sided.offset == off_2
+    assert binding.Params.observables.offset == off_o
+    assert binding.Params.custom_impurity.offset == off_i
 
 
 def test_workspace_sizing_and_validation(lib):
@@ -81,6 +89,35 @@ def test_workspace_sizing_and_validation(lib):
             < binding.workspace_bytes(model="potts", q=3, temperature=1.0, dmax=81, max_steps=10))
 
 
+def test_workspace_of_two_sided_and_observables(lib):
+    from paper_2602_05900_amd import binding
+    base = dict(model="ising", q=2, temperature=2.0, dmax=48, max_steps=30, precision="bf16x6")
+    w0 = binding.workspace_bytes(**base)
+    w2 = binding.workspace_bytes(**base, two_sided=True)
+    w_m = binding.workspace_bytes(**base, observables=("m",))
+    w_me = binding.workspace_bytes(**base, observables=("m", "e"))
+    assert w0 < w2 < w0 + 0.1 * w0            # a second E, Ritz blocks and isometry: D^4-sized
+    assert w0 < w_m < w_me                      # wider X and P4 buffers, impurity tensors
+    assert w_me - w0 < 2.5 * 48 ** 5 * 6        # two more D^5 column blocks of X (3 BF16 planes)
+    # invalid: unknown observable bit, non-finite field, field on a custom tensor,
+    # a custom observable without its impurity tensor, two_sided outside {0, 1}
+    p, _ = binding.make_params(**base)
+    p.observables = 4
+    assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+    p, _ = binding.make_params(**base, field=float("nan"))
+    assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+    p, _ = binding.make_params(**base)
+    p.two_sided = 2
+    assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+    t = np.ones((2, 2, 2, 2))
+    p, keep = binding.make_params(model="custom", tensor=t, dmax=4, field=0.5)
+    assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+    p, keep = binding.make_params(model="custom", tensor=t, dmax=4, observables=("m",), impurities={"m": t})
+    assert lib.hotrg_workspace_bytes(ctypes.byref(p)) > 0
+    p.custom_impurity[0] = ctypes.POINTER(ctypes.c_double)()
+    assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+
+
 def test_host_error_paths_without_device(lib):
     from paper_2602_05900_amd import binding
     p, _ = binding.make_params(model="ising", q=2, temperature=2.0, dmax=8)
@@ -95,6 +132,9 @@ def test_host_error_paths_without_device(lib):
     assert lib.hotrg_coarse_grain_batch(nulls, 2, 1) == binding.EINVAL
     v = ctypes.c_double()
     assert lib.hotrg_log_z(None, ctypes.byref(v), None) == binding.EINVAL
+    vals = (ctypes.c_double * 2)()
+    assert lib.hotrg_observables(None, vals) == binding.EINVAL
+    assert lib.hotrg_step_sides(None, 1, None, None, None) == binding.EINVAL
     lib.hotrg_destroy(None)
     assert lib.hotrg_strerror(binding.ENOMEM) == b"workspace too small"
     assert lib.hotrg_gemm_scratch_bytes(binding.FP64, 10, 10, 10) == 0
