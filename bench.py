@@ -119,6 +119,77 @@ def run_c2(serve, accounting, workloads, budget):
     return out
 
 
+def run_observables(binding, accounting):
+    """Two-sided truncation with the magnetisation and bond-energy impurity
+    tensors carried along.  (1) Ising, D = 24, 30 steps, FP64, 16
+    temperatures of the D = 24 grid (every fourth of linspace(1.8, 2.8, 64)),
+    field 1e-8 to select the ordered state below T_c, one solve at a time:
+    throughput, the direct internal energy 2 <e_b> - h <m> against Onsager
+    and <m> against Yang's spontaneous magnetisation.  (2) The same mode at
+    D = 48 in BF16x6 at four temperatures: throughput."""
+    import torch
+    ref = onsager_reference()
+    g = ref["grid"] if ref else None
+    idx = list(range(0, 64, 4))
+    temps = [g["temperatures"][i] for i in idx] if g else [1.8 + i / 63.0 for i in idx]
+    h = 1e-8
+    nimp = 2
+    out = {"workload": "Ising J=1, D=24, 30 steps, FP64, two-sided, observables m and e, h=1e-8, "
+                       "T = linspace(1.8, 2.8, 64)[::4], one solve at a time"}
+    s = binding.Solve(model="ising", q=2, temperature=temps[0], dmax=24, precision="fp64", max_steps=30,
+                      field=h, two_sided=True, observables=("m", "e"))
+    s.coarse_grain(30)
+    s.observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for t in temps:
+        s.reset(model="ising", q=2, temperature=t, dmax=24, precision="fp64", max_steps=30, field=h,
+                two_sided=True, observables=("m", "e"))
+        s.coarse_grain(30)
+        v = s.observables()
+        res.append((t, s.log_z(), v["m"], v["e"]))
+    wall = time.perf_counter() - t0
+    s.close()
+    flops = accounting.solve_flops(2, 24, 30, two_sided=True, nimp=nimp)
+    out.update({"solves": len(res), "seconds": wall, "tflops": len(res) * flops / wall / 1e12,
+                "flops_per_solve": flops})
+    if g:
+        tc = ref["critical"]["temperature"]
+        du, dm, dmf = [], [], []
+        for (t, _lnz, m, e), i in zip(res, idx):
+            u = 2.0 * e - h * m
+            far = abs(t - tc) > 0.1
+            if far:
+                du.append(abs(u - g["energy"][i]))
+                dm.append(abs(m - g["magnetisation"][i]))
+        out.update({"max_abs_du_direct_vs_onsager_off_critical": max(du),
+                    "max_abs_dm_vs_yang_off_critical": max(dm),
+                    "energy_direct": [2.0 * e - h * m for (_t, _l, m, e) in res],
+                    "magnetisation": [m for (_t, _l, m, _e) in res]})
+    # D = 48, BF16x6
+    temps48 = [2.0, 2.2, 2.4, 2.5]
+    s = binding.Solve(model="ising", q=2, temperature=temps48[0], dmax=48, precision="bf16x6", max_steps=30,
+                      field=h, two_sided=True, observables=("m", "e"))
+    s.coarse_grain(30)
+    s.observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in temps48:
+        s.reset(model="ising", q=2, temperature=t, dmax=48, precision="bf16x6", max_steps=30, field=h,
+                two_sided=True, observables=("m", "e"))
+        s.coarse_grain(30)
+        s.observables()
+    wall = time.perf_counter() - t0
+    s.close()
+    f48 = accounting.solve_flops(2, 48, 30, two_sided=True, nimp=nimp)
+    out["d48_bf16x6"] = {"workload": "Ising J=1, D=48, 30 steps, BF16x6, two-sided, observables m and e, "
+                                     "T in {2.0, 2.2, 2.4, 2.5}, one solve at a time",
+                         "solves": len(temps48), "seconds": wall, "tflops": len(temps48) * f48 / wall / 1e12,
+                         "flops_per_solve": f48}
+    return out
+
+
 def run_c5(binding, accounting):
     """Ising at Tc, D = 64, 40 steps, one solve in BF16x6 and one in FP64 on
     the same GPU: throughput and |delta f| between them and against Onsager."""
@@ -188,6 +259,8 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
     ap.add_argument("--no-c2", dest="c2", action="store_false", help="skip the D=24 temperature scan")
     ap.add_argument("--no-c5", dest="c5", action="store_false", help="skip the D=64 solve")
+    ap.add_argument("--no-observables", dest="observables", action="store_false",
+                    help="skip the two-sided / impurity-observable runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -329,6 +402,9 @@ def main():
     if args.c5:
         print("# C5: D=64 ...", file=sys.stderr, flush=True)
         line["c5"] = run_c5(binding, accounting)
+    if args.observables:
+        print("# observables: two-sided, m and e impurities ...", file=sys.stderr, flush=True)
+        line["observables"] = run_observables(binding, accounting)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))

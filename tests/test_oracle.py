@@ -260,5 +260,6 @@ def test_stored_onsager_grid_matches_the_oracle():
         t = g["temperatures"][i]
         assert abs(g["lnz_per_site"][i] - exact.onsager_lnz(t)) <= 1e-14
         assert abs(g["energy"][i] - exact.onsager_energy(t)) <= 1e-12
+        assert abs(g["magnetisation"][i] - exact.yang_magnetisation(t)) <= 1e-15
     assert abs(d["critical"]["lnz_per_site"] - exact.onsager_lnz_tc()) <= 1e-15
     assert abs(d["critical"]["energy"] + math.sqrt(2.0)) <= 1e-15
