@@ -50,6 +50,19 @@
 #define HOTRG_NARROW_NST 3    // two stages measured slower for T' (12.1 -> 16.1 ms per D = 48 solve)
 #define HOTRG_NARROW_MINW 1
 #endif
+#ifndef HOTRG_F32_STAGED
+#define HOTRG_F32_STAGED 1
+#endif
+// T' reading Y in FP32 (split on load): register-staged 64 x 64 tiles, two
+// waves, one prefetch stage (per D = 48 solve: 13.1 ms, against 13.5 with two
+// stages, 16-17 ms with 128 or 256 rows, 17-20 ms with one wave)
+#ifndef HOTRG_TP_BM
+#define HOTRG_TP_BM 64
+#define HOTRG_TP_WM 2
+#endif
+#ifndef HOTRG_TP_PF
+#define HOTRG_TP_PF 1
+#endif
 #ifndef HOTRG_MID_NST
 #define HOTRG_MID_NST 2    // two stages, up to three workgroups per CU (env 19.2 -> 18.3 ms per D = 48 solve)
 #define HOTRG_MID_MINW 2
@@ -300,7 +313,12 @@ template <> struct SplitProducts<6> {
 // 8(r/4) + 4(l/32) + r%4, column l%32).  K is staged 16 at a time (one MFMA
 // k-step per LDS stage), which lets a 256-row tile double-buffer three planes
 // of both operands in LDS.
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE>
+//
+// AF32: A is one FP32 array instead (the Y product's output, read by T'):
+// its rows are fetched as FP32 and split into the BF16 planes (hi, mid, lo
+// by round-to-nearest-even, the split the producers' epilogues use) as the
+// tile is written to LDS, so each element is split once.
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE, bool AF32 = false>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
 void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
                             const __bf16* __restrict__ B, long ldb, long b_plane,
@@ -341,7 +359,47 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     const int wn = wave - wm * WAVES_N;
 
     static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
-    u4 ra[PF][NPL][A_CH], rb[PF][NPL][B_CH];
+    constexpr int ARP = AF32 ? 2 : NPL;   // registers (u4) per A chunk: 8 floats, or the planes
+    u4 ra[PF][ARP][A_CH], rb[PF][NPL][B_CH];
+
+    // 8 FP32 values of row `row` from column k (zeros outside), kept raw
+    auto fetch_a32 = [&](int nrows, int row, int k, u4 (&dst)[ARP]) {
+        const float* base = reinterpret_cast<const float*>(A);
+        if (row < nrows && vec && k + 8 <= K) {
+            const u4* src = reinterpret_cast<const u4*>(base + (long)row * lda + k);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        } else {
+            float e[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) e[q] = (row < nrows && k + q < K) ? base[(long)row * lda + k + q] : 0.f;
+            dst[0] = u4{__builtin_bit_cast(unsigned, e[0]), __builtin_bit_cast(unsigned, e[1]),
+                        __builtin_bit_cast(unsigned, e[2]), __builtin_bit_cast(unsigned, e[3])};
+            dst[1] = u4{__builtin_bit_cast(unsigned, e[4]), __builtin_bit_cast(unsigned, e[5]),
+                        __builtin_bit_cast(unsigned, e[6]), __builtin_bit_cast(unsigned, e[7])};
+        }
+    };
+    // the NPL planes of 8 raw FP32 values
+    auto split8 = [&](const u4 (&raw)[ARP], u4 (&pl)[NPL]) {
+        unsigned short e[NPL][8];
+        // components copied out by name first: __builtin_bit_cast of an
+        // indexed vector component was measured to read component 0
+        const unsigned w[8] = {raw[0].x, raw[0].y, raw[0].z, raw[0].w, raw[1].x, raw[1].y, raw[1].z, raw[1].w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float f = __builtin_bit_cast(float, w[q]);
+            const __bf16 hi = (__bf16)f;
+            const float rem = f - (float)hi;
+            const __bf16 md = (__bf16)rem;
+            e[0][q] = __builtin_bit_cast(unsigned short, hi);
+            e[1][q] = __builtin_bit_cast(unsigned short, md);
+            if constexpr (NPL == 3) e[2][q] = __builtin_bit_cast(unsigned short, (__bf16)(rem - (float)md));
+        }
+#pragma unroll
+        for (int p = 0; p < NPL; ++p)
+            pl[p] = u4{e[p][0] | (unsigned)e[p][1] << 16, e[p][2] | (unsigned)e[p][3] << 16,
+                       e[p][4] | (unsigned)e[p][5] << 16, e[p][6] | (unsigned)e[p][7] << 16};
+    };
 
     auto fetch = [&](const __bf16* base, long ld, long pstride, int nrows, int row, int k, u4 (&dst)[NPL]) {
         if (row < nrows && vec && k + 8 <= K) {
@@ -368,10 +426,13 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
 #pragma unroll
         for (int i = 0; i < A_CH; ++i) {
             const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
-            u4 t[NPL];
-            fetch(A, lda, a_plane, c < BM * CPR ? M : 0, m0 + row, k0 + 8 * kc, t);
+            u4 t[ARP];
+            if constexpr (AF32)
+                fetch_a32(c < BM * CPR ? M : 0, m0 + row, k0 + 8 * kc, t);
+            else
+                fetch(A, lda, a_plane, c < BM * CPR ? M : 0, m0 + row, k0 + 8 * kc, t);
 #pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) ra[S][pl][i] = t[pl];
+            for (int pl = 0; pl < ARP; ++pl) ra[S][pl][i] = t[pl];
         }
 #pragma unroll
         for (int i = 0; i < B_CH; ++i) {
@@ -387,9 +448,20 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
 #pragma unroll
         for (int i = 0; i < A_CH; ++i) {
             const int c = tid + i * NT, row = c / CPR, kc = c - (c / CPR) * CPR;
-            if (c < BM * CPR)
+            if (c < BM * CPR) {
+                u4 t[NPL];
+                if constexpr (AF32) {
+                    u4 raw[ARP];
 #pragma unroll
-                for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&As[buf][pl][row * LDK + 8 * kc]) = ra[S][pl][i];
+                    for (int q = 0; q < ARP; ++q) raw[q] = ra[S][q][i];
+                    split8(raw, t);
+                } else {
+#pragma unroll
+                    for (int pl = 0; pl < NPL; ++pl) t[pl] = ra[S][pl][i];
+                }
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl) *reinterpret_cast<u4*>(&As[buf][pl][row * LDK + 8 * kc]) = t[pl];
+            }
         }
 #pragma unroll
         for (int i = 0; i < B_CH; ++i) {
@@ -486,7 +558,7 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     }
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE>
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE, bool AF32 = false>
 static hipError_t run_gemm_p32(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
                                const Store& st, const OutMap& mp, hipStream_t stream)
 {
@@ -496,9 +568,9 @@ static hipError_t run_gemm_p32(const Buf& A, long lda, const Buf& B, long ldb, i
     const int per_xcd = (int)((tiles + 7) / 8);
     const long grid = 8L * per_xcd;
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    const bool vec = lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 &&
-                     ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
-    hipLaunchKernelGGL((gemm_nt_bf16p32_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, PF, ROLE>), dim3((unsigned)grid),
+    const bool vec = (AF32 ? lda % 4 == 0 : lda % 8 == 0 && (long)A.plane % 8 == 0) && ldb % 8 == 0 &&
+                     (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
+    hipLaunchKernelGGL((gemm_nt_bf16p32_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, PF, ROLE, AF32>), dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
                        per_xcd, vec ? 1 : 0);
@@ -715,7 +787,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     constexpr int REG = NPL * SLAB;                // one wave's region
     constexpr int PER_ARRAY = STAGE / REG;
     if constexpr (PER_ARRAY > 0 && NW <= PER_ARRAY * NST) {
-        if (vec_out) {
+        if (vec_out == 1) {
             typedef unsigned int u4 __attribute__((ext_vector_type(4)));
             constexpr int CPR = WN / 8;            // 16-byte chunks per staged row
             constexpr int NCH = 16 * CPR;          // chunks per plane of a slab
@@ -778,6 +850,63 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             return;
         }
     }
+    // FP32 outputs (a product whose consumer splits its operand on load):
+    // the same 16-row slab staging with one 4-byte plane, 16-byte stores of
+    // 4 columns.  The value stored is the one the plane split above starts
+    // from, so a consumer that splits it gets the same planes.
+    constexpr int RW4 = WN + 4;                    // staged row, floats (a 16-byte multiple)
+    constexpr int SLAB4 = 16 * RW4;                // floats of a 16-row slab
+    constexpr int PER_ARRAY4 = STAGE / (2 * SLAB4);
+    if constexpr (PER_ARRAY4 > 0 && NW <= PER_ARRAY4 * NST) {
+        if (vec_out == 2) {
+            typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+            constexpr int CPR = WN / 4;            // 16-byte chunks per staged row
+            constexpr int NCH = 16 * CPR;
+            static_assert(NCH % 64 == 0, "whole chunks per lane");
+            constexpr int CPL = NCH / 64;
+            __syncthreads();   // every wave is done reading the stages
+            const int ar = wave / PER_ARRAY4;
+            float* reg = reinterpret_cast<float*>(ar == 0 ? S0 : (ar == 1 ? S1 : S2)) + (wave - ar * PER_ARRAY4) * SLAB4;
+            float* outp = static_cast<float*>(store.ptr);
+            MapPart ccol[CPL];
+            bool cok[CPL];
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = lane + 64 * t;
+                const int n = ncol(wn * WN + (c % CPR) * 4);
+                cok[t] = n < N;
+                ccol[t] = cok[t] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) {
+                            const int r = 8 * h + rr;
+                            const int row = 8 * (rr >> 2) + 4 * fk + (rr & 3);
+                            reg[row * RW4 + j * 32 + frow] = (float)(store.alpha * (double)acc[i][j][r]);
+                        }
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's staging writes are done
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) {
+                        const int c = lane + 64 * t;
+                        const int row = c / CPR;
+                        const int m = m0 + wm * WM + i * 32 + 16 * h + row;
+                        if (cok[t] && m < M) {
+                            const long off = map_off(mp, map_row(mp, (unsigned)m), ccol[t]);
+                            *reinterpret_cast<u4*>(outp + off) =
+                                *reinterpret_cast<const u4*>(reg + row * RW4 + (c % CPR) * 4);
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // staging reads are done before the region is rewritten
+                }
+            }
+            return;
+        }
+    }
 
     MapPart coff[FN];
     bool cin[FN];
@@ -815,8 +944,12 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
                        mp.cs_hi % 8 == 0;
     const bool pn_ok = mp.panel_k != 0 && mp.panel_k % 16 == 0 && mp.cc_lo == 1 && mp.rc_hi % 8 == 0 &&
                        mp.rc_lo % 8 == 0 && mp.cc_hi % 8 == 0;
-    const int vec_out = same_planes && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 && st.plane % 8 == 0 &&
-                        ((uintptr_t)st.ptr & 15) == 0;
+    int vec_out = same_planes && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 && st.plane % 8 == 0 &&
+                  ((uintptr_t)st.ptr & 15) == 0;
+    // FP32 output: runs of 4 columns contiguous and 16-byte aligned (row-major maps)
+    if (HOTRG_F32_STAGED && !vec_out && st.fmt == (int)Fmt::F32 && mp.panel_k == 0 && mp.cs_lo == 1 && mp.rs_hi % 4 == 0 &&
+        mp.rs_lo % 4 == 0 && mp.cs_hi % 4 == 0 && mp.sn % 4 == 0 && N % 4 == 0 && ((uintptr_t)st.ptr & 15) == 0)
+        vec_out = 2;
     const int tiles_m = (M + BM - 1) / BM;
     const int tiles_n = (N + BN - 1) / BN;
     const long tiles = (long)tiles_m * tiles_n;
@@ -827,7 +960,7 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
                        dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
-                       per_xcd, ngrp, vec_out ? 1 : 0);
+                       per_xcd, ngrp, vec_out);
     return hipGetLastError();
 }
 
@@ -855,6 +988,16 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
 {
     (void)products;
     const bool split = A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3;
+    if (A.fmt == Fmt::F32 && (B.fmt == Fmt::BF16x2 || B.fmt == Fmt::BF16x3)) {
+        // T' = Y . U with Y kept in FP32 by its producer: the A tile is split
+        // into the planes of B's format as it is written to LDS
+        if (A.panel_k || B.panel_k) return hipErrorInvalidValue;
+        return B.fmt == Fmt::BF16x2
+                   ? run_gemm_p32<3, HOTRG_TP_BM, 64, HOTRG_TP_WM, 1, HOTRG_TP_PF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
+                                                                                     stream)
+                   : run_gemm_p32<6, HOTRG_TP_BM, 64, HOTRG_TP_WM, 1, HOTRG_TP_PF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
+                                                                                     stream);
+    }
     if (A.panel_k || B.panel_k) {
         // panel-layout operands (row length lda / ldb >= K, whole 32-row
         // panels) go to the direct-to-LDS kernel: both operands of the
@@ -970,7 +1113,9 @@ hipError_t launch_gemm_nt(const Buf& A, long lda, const Buf& B, long ldb, const 
                           int products, GemmRole role, hipStream_t stream)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    if (A.fmt != B.fmt || map.sm < 1 || map.sn < 1) return hipErrorInvalidValue;
+    // operands in one format, or an FP32 A split on load into B's BF16 planes
+    const bool f32_split = A.fmt == Fmt::F32 && (B.fmt == Fmt::BF16x2 || B.fmt == Fmt::BF16x3);
+    if ((A.fmt != B.fmt && !f32_split) || map.sm < 1 || map.sn < 1) return hipErrorInvalidValue;
     Store st{C.ptr, C.plane, (int)C.fmt, alpha};
     switch (role) {
         case GemmRole::X: return dispatch<1>(A, lda, B, ldb, M, N, K, st, map, products, stream);

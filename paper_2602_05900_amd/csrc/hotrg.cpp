@@ -80,6 +80,14 @@ size_t buf_bytes(Fmt f, size_t count) {
 
 int popcount2(int m) { return (m & 1) + ((m >> 1) & 1); }
 
+// Y is kept in FP32 in the split modes: T' splits it into planes as it loads
+// its tiles, so Y is written and read at 4 bytes an element instead of 6
+// (BF16x3 planes), with the same planes reaching the products.
+#ifndef HOTRG_Y_F32
+#define HOTRG_Y_F32 1
+#endif
+Fmt y_fmt(Fmt f) { return HOTRG_Y_F32 && (f == Fmt::BF16x2 || f == Fmt::BF16x3) ? Fmt::F32 : f; }
+
 struct Layout {
     size_t nT = 0, nP = 0, nAB = 0, nE = 0, nU = 0, nX = 0, nEig = 0;
     int nimp = 0;   // impurity tensors carried (one per observable slot set)
@@ -200,7 +208,7 @@ Layout plan(const hotrg_params* p) {
         L.oUxR = take(buf_bytes(f, L.nU));
     }
     L.oX = take(buf_bytes(f, L.nX * wide));
-    L.oY = take(buf_bytes(f, L.nX));
+    L.oY = take(buf_bytes(y_fmt(f), L.nX));
     L.total = o;
     return L;
 }
@@ -400,7 +408,7 @@ int enqueue_step(hotrg_solve* s) {
     const Buf Pa = make_buf(w, L.oPa, f, L.nP), Pb = make_buf(w, L.oPb, f, L.nP * (1 + nimp));
     const Buf Ah = make_buf(w, L.oAh, f, L.nAB), Bh = make_buf(w, L.oBh, f, L.nAB);
     const Buf Ut = make_buf(w, L.oUt, f, L.nU), Ux = make_buf(w, L.oUx, f, L.nU);
-    const Buf X = make_buf(w, L.oX, f, L.nX * (1 + nimp)), Y = make_buf(w, L.oY, f, L.nX);
+    const Buf X = make_buf(w, L.oX, f, L.nX * (1 + nimp)), Y = make_buf(w, L.oY, y_fmt(f), L.nX);
     double* E = reinterpret_cast<double*>(w + L.oE);
     const Buf Ebuf{E, Fmt::F64, 0};
     const Buf Tbuf{s->T(), Fmt::F64, 0};
