@@ -41,6 +41,8 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 TRAFFIC_PROFILE = {"bf16x6": os.path.join(ROOT, "profiles", "gemm_y_bf16x6_ising_d48_traffic.md")}
 ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 6}
+# Y's output: FP32 in the split modes (its consumer splits it on load)
+Y_OUT_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4}
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc"}
 
@@ -277,7 +279,7 @@ def main():
     flops_solve = accounting.solve_flops(2, args.dmax, args.nsteps)
     dims = accounting.step_dims(2, 2, args.dmax, args.nsteps)
     y_flops = sum(accounting.stage_flops(*d)["y"] for d in dims)
-    y_bytes = sum(accounting.y_bytes(*d, ELEM_BYTES[args.precision]) for d in dims)
+    y_bytes = sum(accounting.y_bytes(*d, ELEM_BYTES[args.precision], Y_OUT_BYTES[args.precision]) for d in dims)
 
     def batch(first, count):
         return [workloads.Request(rid=first + i, arrival=0.0, model="ising", q=2,

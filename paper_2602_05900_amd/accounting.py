@@ -45,8 +45,10 @@ def y_flops(q: int, dmax: int, nsteps: int) -> float:
     return sum(stage_flops(*d)["y"] for d in step_dims(q, q, dmax, nsteps))
 
 
-def y_bytes(dx: int, dy: int, dp: int, elem_bytes: int) -> float:
+def y_bytes(dx: int, dy: int, dp: int, elem_bytes: int, out_bytes: int | None = None) -> float:
     """Compulsory HBM traffic of one Y product: read X (D' Dx^2 Dy^2) and the
-    re-laid-out T (Dx^2 Dy^2) once, write Y (D' Dx^2 Dy^2) once."""
+    re-laid-out T (Dx^2 Dy^2) once at elem_bytes an element, write Y
+    (D' Dx^2 Dy^2) once at out_bytes an element (default elem_bytes)."""
     n5 = dp * dx * dx * dy * dy
-    return float(elem_bytes) * (2 * n5 + dx * dx * dy * dy)
+    ob = elem_bytes if out_bytes is None else out_bytes
+    return float(elem_bytes) * (n5 + dx * dx * dy * dy) + float(ob) * n5
