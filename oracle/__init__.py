@@ -11,4 +11,7 @@ Modules
            Phys. Rev. B 86, 045139 (2012)).
 ``exact``  independent pins: brute-force spin sums, spin and tensor transfer
            matrices, Onsager's exact solution.
+``itebd``  imaginary-time evolution of an infinite two-site chain (Sec. II.A,
+           Eq. (1); the iTEBD algorithm it cites, Vidal, PRL 98, 070201
+           (2007), in Hastings' inverse-free update), NumPy FP64.
 """

@@ -72,3 +72,36 @@ def request_stream(rate_hz: float = 50.0, duration_s: float = 60.0, seed: int = 
         out.append(Request(rid, t, model, q, temp, d, n))
         rid += 1
     return out
+
+
+def random_chain_states(batch: int, chi: int, d: int = 2, seed: int = 0) -> np.ndarray:
+    """Initial two-site unit cells of `batch` infinite chains, one row per
+    chain: B1[d][chi][chi], B2[d][chi][chi] (standard normal entries) and the
+    bond weights l1[chi], l2[chi] (all 1/sqrt(chi)), flattened in that
+    order.  Different chains start from different random states."""
+    rng = np.random.default_rng(seed)
+    n = d * chi * chi
+    out = np.empty((batch, 2 * n + 2 * chi))
+    out[:, :2 * n] = rng.standard_normal((batch, 2 * n))
+    out[:, 2 * n:] = 1.0 / math.sqrt(chi)
+    return out
+
+
+def heisenberg_bond(J: float = 1.0) -> np.ndarray:
+    """Two-site Hamiltonian J S.S of spin-1/2, basis |s t> with s, t in
+    {up, down} (index 2 s + t), as a 4 x 4 matrix."""
+    h = np.zeros((4, 4))
+    h[0, 0] = h[3, 3] = 0.25 * J
+    h[1, 1] = h[2, 2] = -0.25 * J
+    h[1, 2] = h[2, 1] = 0.5 * J
+    return h
+
+
+def ising_transverse_bond(g: float, J: float = 1.0) -> np.ndarray:
+    """Two-site term of the transverse-field Ising chain
+    H = -J sum sz sz - g sum sx (Pauli matrices), the field split evenly
+    over the two bonds of each site, as a 4 x 4 matrix."""
+    sz = np.diag([1.0, -1.0])
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]])
+    one = np.eye(2)
+    return -J * np.kron(sz, sz) - 0.5 * g * (np.kron(sx, one) + np.kron(one, sx))
