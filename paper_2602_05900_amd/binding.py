@@ -34,7 +34,10 @@ EXPORTS = [
     "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
+    "itebd_state_len", "itebd_workspace_bytes", "itebd_init", "itebd_evolve", "itebd_energy",
+    "itebd_copy_states", "itebd_info", "itebd_destroy",
 ]
+ITEBD_MAX_CHI = 32
 
 
 class HotrgError(RuntimeError):
@@ -102,6 +105,17 @@ def load() -> ctypes.CDLL:
     lib.hotrg_gemm_nt.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long,
                                   c_void_p, c_double, c_long, c_long, c_long, c_long, c_long, c_long,
                                   c_void_p, c_void_p]
+    lib.itebd_state_len.argtypes = [c_int]
+    lib.itebd_state_len.restype = c_size_t
+    lib.itebd_workspace_bytes.argtypes = [c_int, c_int]
+    lib.itebd_workspace_bytes.restype = c_size_t
+    lib.itebd_init.argtypes = [c_int, c_int, P(c_double), P(c_double), c_void_p, c_size_t, c_void_p, P(c_void_p)]
+    lib.itebd_evolve.argtypes = [c_void_p, c_double, c_int]
+    lib.itebd_energy.argtypes = [c_void_p, P(c_double)]
+    lib.itebd_copy_states.argtypes = [c_void_p, P(c_double), c_size_t]
+    lib.itebd_info.argtypes = [c_void_p, P(ctypes.c_long), P(c_int)]
+    lib.itebd_destroy.argtypes = [c_void_p]
+    lib.itebd_destroy.restype = None
     for name in EXPORTS:
         getattr(lib, name)  # every declared entry point must resolve
     _lib = lib
@@ -276,6 +290,67 @@ class Solve:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.hotrg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Chains:
+    """A batch of infinite chains evolved in imaginary time on the device
+    (include/itebd.h).  h: the two-site term (4 x 4); states: rows of
+    itebd_state_len(chi) doubles (B1, B2, lambda_1, lambda_2)."""
+
+    def __init__(self, h, states, chi: int, stream=None, device="cuda"):
+        import numpy as np
+        lib = load()
+        self._lib = lib
+        self.chi = chi
+        st = np.ascontiguousarray(states, dtype=np.float64)
+        self.batch = st.shape[0]
+        if st.ndim != 2 or st.shape[1] != lib.itebd_state_len(chi):
+            raise ValueError("states must have itebd_state_len(chi) columns")
+        hh = np.ascontiguousarray(h, dtype=np.float64).reshape(16)
+        nbytes = lib.itebd_workspace_bytes(self.batch, chi)
+        if nbytes == 0:
+            raise HotrgError(EINVAL, "itebd_workspace_bytes")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        dp = ctypes.POINTER(ctypes.c_double)
+        h_ = ctypes.c_void_p()
+        _check(lib.itebd_init(self.batch, chi, hh.ctypes.data_as(dp), st.ctypes.data_as(dp),
+                              ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(nbytes),
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h_)), "itebd_init")
+        self._h = h_
+
+    def evolve(self, tau: float, nupdates: int) -> "Chains":
+        _check(self._lib.itebd_evolve(self._h, float(tau), int(nupdates)), "itebd_evolve")
+        return self
+
+    def energies(self):
+        import numpy as np
+        out = np.empty(self.batch)
+        _check(self._lib.itebd_energy(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "itebd_energy")
+        return out
+
+    def states(self):
+        import numpy as np
+        out = np.empty((self.batch, self._lib.itebd_state_len(self.chi)))
+        _check(self._lib.itebd_copy_states(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
+               "itebd_copy_states")
+        return out
+
+    def info(self):
+        u, m = ctypes.c_long(), ctypes.c_int()
+        _check(self._lib.itebd_info(self._h, ctypes.byref(u), ctypes.byref(m)), "itebd_info")
+        return u.value, m.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.itebd_destroy(self._h)
             self._h = None
 
     def __del__(self):

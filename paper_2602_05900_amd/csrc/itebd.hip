@@ -1,0 +1,504 @@
+// iTEBD on the device: many independent infinite chains, one workgroup per
+// chain, the whole two-site unit cell and the SVD work matrices in LDS, all
+// FP64.  The C ABI is declared in include/itebd.h.
+//
+// One bond update (Sec. II.A, Eq. (1); the inverse-free form of the iTEBD
+// update), n = 2 chi:
+//   P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b]          (contraction)
+//   P <- G P on the physical pair (s, t) of every (a, b)     (gate)
+//   W = diag(lambda_2 (x) 1) P V0                             (V0: warm start or 1)
+//   one-sided Jacobi on the columns of W, rotations also applied to V
+//     -> W = X S, V = right singular vectors (unordered)
+//   keep the chi largest; sign gauge on the kept columns of V
+//   B2' = V_kept^T, B1' = P V_kept / |S_kept|, lambda_1' = S_kept / |S_kept|
+//   exchange the sites' roles
+// The Jacobi sweep visits all column pairs in n - 1 rounds of n/2 disjoint
+// pairs (round-robin ordering, the systolic schedule of Sec. II.B used for
+// one-sided rotations); eight lanes own a pair: they form the three dot
+// products over their rows, reduce them with butterfly shuffles (every lane
+// gets the same bits), and rotate their rows of W and V.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/itebd.h"
+
+namespace {
+
+constexpr int kMaxChi = ITEBD_MAX_CHI;
+constexpr int kMaxN = 2 * kMaxChi;
+constexpr int kThreads = 256;
+constexpr int kUpdatesPerLaunch = 32;
+constexpr int kMaxSweeps = 40;
+constexpr double kTol = 1e-14;   // rotate a pair while |w_p.w_q| > kTol |w_p| |w_q|
+
+struct Gate {
+    double g[16];   // exp(-tau h), row-major [(s' t'), (s t)]
+};
+
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask); }
+
+__global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restrict__ states,
+                                                                double* __restrict__ vprev,
+                                                                int* __restrict__ sweeps_out, int chi, Gate G,
+                                                                long base, int nupd)
+{
+    __shared__ double sB1[2 * kMaxChi * kMaxChi];
+    __shared__ double sB2[2 * kMaxChi * kMaxChi];
+    __shared__ double sP[kMaxN * kMaxN];
+    __shared__ double sW[kMaxN * kMaxN];
+    __shared__ double sV[kMaxN * kMaxN];
+    __shared__ double sl1[kMaxChi], sl2[kMaxChi];
+    __shared__ double ssig[kMaxN], ssgn[kMaxChi];
+    __shared__ int sord[kMaxChi];
+    __shared__ int srot;
+    __shared__ double snrm;
+
+    const int tid = threadIdx.x;
+    const int n = 2 * chi;
+    const int nb = 2 * chi * chi;
+    const long len = 2L * nb + 2 * chi;
+    double* st = states + (long)blockIdx.x * len;
+    double* vp = vprev + (long)blockIdx.x * 2 * n * n;
+
+    for (int i = tid; i < nb; i += kThreads) {
+        sB1[i] = st[i];
+        sB2[i] = st[nb + i];
+    }
+    for (int i = tid; i < chi; i += kThreads) {
+        sl1[i] = st[2 * nb + i];
+        sl2[i] = st[2 * nb + chi + i];
+    }
+    __syncthreads();
+
+    int max_sweeps = 0;
+    for (int u = 0; u < nupd; ++u) {
+        const long count = base + u;
+        const int par = (int)(count & 1);
+        const bool warm = count >= 2;
+
+        // contraction P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b]
+        for (int idx = tid; idx < n * n; idx += kThreads) {
+            const int r = idx / n, k = idx - (idx / n) * n;
+            const int a = r >> 1, s = r & 1, t = k / chi, b = k - (k / chi) * chi;
+            const double* x = sB1 + (s * chi + a) * chi;
+            const double* y = sB2 + t * chi * chi + b;
+            double acc = 0.0;
+            for (int c = 0; c < chi; ++c) acc = fma(x[c], y[c * chi], acc);
+            sP[idx] = acc;
+        }
+        __syncthreads();
+        // gate on the physical pair of every (a, b)
+        for (int idx = tid; idx < chi * chi; idx += kThreads) {
+            const int a = idx / chi, b = idx - (idx / chi) * chi;
+            double v[4], w[4];
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) v[2 * s + t] = sP[(2 * a + s) * n + t * chi + b];
+            for (int o = 0; o < 4; ++o) {
+                double acc = 0.0;
+                for (int i = 0; i < 4; ++i) acc = fma(G.g[4 * o + i], v[i], acc);
+                w[o] = acc;
+            }
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) sP[(2 * a + s) * n + t * chi + b] = w[2 * s + t];
+        }
+        // starting right basis: the same bond's vectors of two updates ago, or 1
+        double* vpar = vp + (long)par * n * n;
+        for (int idx = tid; idx < n * n; idx += kThreads) {
+            const int i = idx / n, j = idx - (idx / n) * n;
+            sV[idx] = warm ? vpar[idx] : (i == j ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        // W = diag(lambda_2 (x) 1) P V
+        for (int idx = tid; idx < n * n; idx += kThreads) {
+            const int r = idx / n, j = idx - (idx / n) * n;
+            double acc;
+            if (warm) {
+                acc = 0.0;
+                for (int k = 0; k < n; ++k) acc = fma(sP[r * n + k], sV[k * n + j], acc);
+            } else {
+                acc = sP[idx];
+            }
+            sW[idx] = sl2[r >> 1] * acc;
+        }
+        __syncthreads();
+
+        // one-sided Jacobi
+        const int g = tid >> 3, l8 = tid & 7;
+        const int npair = n >> 1;
+        int sweeps = kMaxSweeps;
+        for (int sw = 0; sw < kMaxSweeps; ++sw) {
+            if (tid == 0) srot = 0;
+            __syncthreads();
+            for (int rd = 0; rd < n - 1; ++rd) {
+                if (g < npair) {
+                    int p, q;
+                    if (g == 0) {
+                        p = rd;
+                        q = n - 1;
+                    } else {
+                        p = (rd + g) % (n - 1);
+                        q = (rd - g + n - 1) % (n - 1);
+                    }
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int i = l8; i < n; i += 8) {
+                        const double wp = sW[i * n + p], wq = sW[i * n + q];
+                        al = fma(wp, wp, al);
+                        be = fma(wq, wq, be);
+                        ga = fma(wp, wq, ga);
+                    }
+                    for (int off = 4; off > 0; off >>= 1) {
+                        al += shfl_xor_d(al, off);
+                        be += shfl_xor_d(be, off);
+                        ga += shfl_xor_d(ga, off);
+                    }
+                    if (fabs(ga) > kTol * sqrt(al * be)) {
+                        const double z = (be - al) / (2.0 * ga);
+                        const double t = fabs(z) > 1e150 ? 0.5 / z
+                                                         : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+                        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                        for (int i = l8; i < n; i += 8) {
+                            const double wp = sW[i * n + p], wq = sW[i * n + q];
+                            sW[i * n + p] = c * wp - s * wq;
+                            sW[i * n + q] = s * wp + c * wq;
+                            const double vp_ = sV[i * n + p], vq = sV[i * n + q];
+                            sV[i * n + p] = c * vp_ - s * vq;
+                            sV[i * n + q] = s * vp_ + c * vq;
+                        }
+                        if (l8 == 0) srot = 1;
+                    }
+                }
+                __syncthreads();
+            }
+            const int any = srot;
+            __syncthreads();
+            if (!any) {
+                sweeps = sw + 1;
+                break;
+            }
+        }
+        max_sweeps = max(max_sweeps, sweeps);
+
+        // singular values, the chi largest (ties: lower column first)
+        for (int j = tid; j < n; j += kThreads) {
+            double acc = 0.0;
+            for (int i = 0; i < n; ++i) acc = fma(sW[i * n + j], sW[i * n + j], acc);
+            ssig[j] = sqrt(acc);
+        }
+        __syncthreads();
+        for (int j = tid; j < n; j += kThreads) {
+            int rank = 0;
+            for (int i = 0; i < n; ++i) rank += (ssig[i] > ssig[j]) || (ssig[i] == ssig[j] && i < j);
+            if (rank < chi) sord[rank] = j;
+        }
+        __syncthreads();
+        // sign gauge of the kept right vectors; norm of the kept values
+        for (int c = tid; c < chi; c += kThreads) {
+            const int j = sord[c];
+            double best = -1.0;
+            int bi = 0;
+            for (int i = 0; i < n; ++i) {
+                const double a = fabs(sV[i * n + j]);
+                if (a > best) {
+                    best = a;
+                    bi = i;
+                }
+            }
+            ssgn[c] = sV[bi * n + j] < 0.0 ? -1.0 : 1.0;
+        }
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int c = 0; c < chi; ++c) acc = fma(ssig[sord[c]], ssig[sord[c]], acc);
+            snrm = sqrt(acc);
+        }
+        // the bond's right vectors for the next warm start
+        for (int idx = tid; idx < n * n; idx += kThreads) vpar[idx] = sV[idx];
+        __syncthreads();
+        // new tensors, roles exchanged: B1 <- B2' = V_kept^T, B2 <- B1' = P V_kept / nrm
+        const double inv = 1.0 / snrm;
+        for (int idx = tid; idx < nb; idx += kThreads) {
+            const int t = idx / (chi * chi), rem = idx - t * chi * chi;
+            const int c = rem / chi, b = rem - (rem / chi) * chi;
+            sB1[idx] = ssgn[c] * sV[(t * chi + b) * n + sord[c]];
+        }
+        for (int idx = tid; idx < nb; idx += kThreads) {
+            const int s = idx / (chi * chi), rem = idx - s * chi * chi;
+            const int a = rem / chi, c = rem - (rem / chi) * chi;
+            const int j = sord[c];
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc = fma(sP[(2 * a + s) * n + k], sV[k * n + j], acc);
+            sB2[idx] = ssgn[c] * inv * acc;
+        }
+        for (int c = tid; c < chi; c += kThreads) {
+            const double old = sl2[c];
+            sl2[c] = ssig[sord[c]] * inv;
+            sl1[c] = old;
+        }
+        __syncthreads();
+    }
+
+    for (int i = tid; i < nb; i += kThreads) {
+        st[i] = sB1[i];
+        st[nb + i] = sB2[i];
+    }
+    for (int i = tid; i < chi; i += kThreads) {
+        st[2 * nb + i] = sl1[i];
+        st[2 * nb + chi + i] = sl2[i];
+    }
+    if (tid == 0) sweeps_out[blockIdx.x] = max_sweeps;
+}
+
+// Energy per site of every chain: <h> on bond (B1, B2) weighted by lambda_2
+// and on bond (B2, B1) weighted by lambda_1, averaged.  Fixed-order sums.
+__global__ __launch_bounds__(kThreads) void itebd_energy_kernel(const double* __restrict__ states, int chi,
+                                                                Gate H, double* __restrict__ energies)
+{
+    __shared__ double sP[kMaxN * kMaxN];
+    __shared__ double red[2][kThreads];
+    const int tid = threadIdx.x;
+    const int n = 2 * chi;
+    const int nb = 2 * chi * chi;
+    const long len = 2L * nb + 2 * chi;
+    const double* st = states + (long)blockIdx.x * len;
+    double e[2];
+    for (int bond = 0; bond < 2; ++bond) {
+        const double* X = st + (bond == 0 ? 0 : nb);
+        const double* Y = st + (bond == 0 ? nb : 0);
+        const double* lw = st + 2 * nb + (bond == 0 ? chi : 0);
+        for (int idx = tid; idx < n * n; idx += kThreads) {
+            const int r = idx / n, k = idx - (idx / n) * n;
+            const int a = r >> 1, s = r & 1, t = k / chi, b = k - (k / chi) * chi;
+            double acc = 0.0;
+            for (int c = 0; c < chi; ++c) acc = fma(X[(s * chi + a) * chi + c], Y[(t * chi + c) * chi + b], acc);
+            sP[idx] = lw[a] * acc;
+        }
+        __syncthreads();
+        double num = 0.0, den = 0.0;
+        for (int idx = tid; idx < chi * chi; idx += kThreads) {
+            const int a = idx / chi, b = idx - (idx / chi) * chi;
+            double v[4];
+            for (int s = 0; s < 2; ++s)
+                for (int t = 0; t < 2; ++t) v[2 * s + t] = sP[(2 * a + s) * n + t * chi + b];
+            for (int o = 0; o < 4; ++o) {
+                double hv = 0.0;
+                for (int i = 0; i < 4; ++i) hv = fma(H.g[4 * o + i], v[i], hv);
+                num = fma(v[o], hv, num);
+                den = fma(v[o], v[o], den);
+            }
+        }
+        red[0][tid] = num;
+        red[1][tid] = den;
+        __syncthreads();
+        for (int s = kThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                red[0][tid] += red[0][tid + s];
+                red[1][tid] += red[1][tid + s];
+            }
+            __syncthreads();
+        }
+        e[bond] = red[0][0] / red[1][0];
+        __syncthreads();
+    }
+    if (tid == 0) energies[blockIdx.x] = 0.5 * (e[0] + e[1]);
+}
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    size_t states, vprev, sweeps, energies, total;
+};
+
+Layout plan(int batch, int chi) {
+    const size_t len = 4 * (size_t)chi * chi + 2 * (size_t)chi;
+    const size_t n = 2 * (size_t)chi;
+    Layout L;
+    size_t o = 0;
+    L.states = o;
+    o = round_up(o + 8 * len * batch, 256);
+    L.vprev = o;
+    o = round_up(o + 8 * 2 * n * n * batch, 256);
+    L.sweeps = o;
+    o = round_up(o + 4 * (size_t)batch, 256);
+    L.energies = o;
+    o = round_up(o + 8 * (size_t)batch, 256);
+    L.total = o;
+    return L;
+}
+
+// G = exp(-tau h) for a real symmetric 4 x 4 h: cyclic Jacobi eigen-
+// decomposition h = Q diag(w) Q^T on the host, then Q diag(exp(-tau w)) Q^T.
+Gate gate_of(const double* h, double tau) {
+    double A[16], Q[16];
+    memcpy(A, h, sizeof A);
+    for (int i = 0; i < 16; ++i) Q[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) off += A[4 * p + q] * A[4 * p + q];
+        if (off < 1e-300) break;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                const double apq = A[4 * p + q];
+                if (apq == 0.0) continue;
+                const double z = (A[4 * q + q] - A[4 * p + p]) / (2.0 * apq);
+                const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int k = 0; k < 4; ++k) {   // A <- J^T A J, columns then rows
+                    const double akp = A[4 * k + p], akq = A[4 * k + q];
+                    A[4 * k + p] = c * akp - s * akq;
+                    A[4 * k + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double apk = A[4 * p + k], aqk = A[4 * q + k];
+                    A[4 * p + k] = c * apk - s * aqk;
+                    A[4 * q + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double qkp = Q[4 * k + p], qkq = Q[4 * k + q];
+                    Q[4 * k + p] = c * qkp - s * qkq;
+                    Q[4 * k + q] = s * qkp + c * qkq;
+                }
+            }
+    }
+    Gate G;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k) acc += Q[4 * i + k] * exp(-tau * A[4 * k + k]) * Q[4 * j + k];
+            G.g[4 * i + j] = acc;
+        }
+    return G;
+}
+
+}  // namespace
+
+struct itebd_batch {
+    int batch = 0, chi = 0;
+    double h[16];
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L;
+    long updates = 0;
+    int host_status = HOTRG_OK;
+    double* states() const { return reinterpret_cast<double*>(ws + L.states); }
+};
+
+extern "C" {
+
+size_t itebd_state_len(int chi) {
+    if (chi < 1 || chi > ITEBD_MAX_CHI) return 0;
+    return 4 * (size_t)chi * chi + 2 * (size_t)chi;
+}
+
+size_t itebd_workspace_bytes(int batch, int chi) {
+    if (batch < 1 || batch > (1 << 20) || chi < 1 || chi > ITEBD_MAX_CHI) return 0;
+    return plan(batch, chi).total;
+}
+
+int itebd_init(int batch, int chi, const double* h, const double* states, void* workspace, size_t ws_bytes,
+               void* stream, itebd_batch** out) {
+    if (!out) return HOTRG_EINVAL;
+    *out = nullptr;
+    if (batch < 1 || batch > (1 << 20) || chi < 1 || chi > ITEBD_MAX_CHI || !h || !states || !workspace ||
+        ((uintptr_t)workspace & 255u))
+        return HOTRG_EINVAL;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            if (!isfinite(h[4 * i + j]) || h[4 * i + j] != h[4 * j + i]) return HOTRG_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return HOTRG_ENODEV;
+    const Layout L = plan(batch, chi);
+    if (ws_bytes < L.total) return HOTRG_ENOMEM;
+    itebd_batch* b = new (std::nothrow) itebd_batch();
+    if (!b) return HOTRG_EINVAL;
+    b->batch = batch;
+    b->chi = chi;
+    memcpy(b->h, h, sizeof b->h);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->ws = static_cast<char*>(workspace);
+    b->L = L;
+    const size_t bytes = 8 * itebd_state_len(chi) * (size_t)batch;
+    if (hipMemcpyAsync(b->states(), states, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemsetAsync(b->ws + L.sweeps, 0, 4 * (size_t)batch, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        delete b;
+        return HOTRG_EHIP;
+    }
+    *out = b;
+    return HOTRG_OK;
+}
+
+int itebd_evolve(itebd_batch* b, double tau, int nupdates) {
+    if (!b || nupdates < 0 || !(tau > 0.0) || !isfinite(tau)) return HOTRG_EINVAL;
+    if (b->host_status) return HOTRG_ESTATE;
+    const Gate G = gate_of(b->h, tau);
+    double* vprev = reinterpret_cast<double*>(b->ws + b->L.vprev);
+    int* sweeps = reinterpret_cast<int*>(b->ws + b->L.sweeps);
+    for (int done = 0; done < nupdates;) {
+        const int k = std::min(kUpdatesPerLaunch, nupdates - done);
+        hipLaunchKernelGGL(itebd_update_kernel, dim3((unsigned)b->batch), dim3(kThreads), 0, b->stream, b->states(),
+                           vprev, sweeps, b->chi, G, b->updates, k);
+        if (hipGetLastError() != hipSuccess) {
+            b->host_status = HOTRG_EHIP;
+            return HOTRG_EHIP;
+        }
+        b->updates += k;
+        done += k;
+    }
+    return HOTRG_OK;
+}
+
+int itebd_energy(itebd_batch* b, double* energies) {
+    if (!b || !energies) return HOTRG_EINVAL;
+    if (b->host_status) return b->host_status;
+    Gate H;
+    memcpy(H.g, b->h, sizeof H.g);
+    double* dev = reinterpret_cast<double*>(b->ws + b->L.energies);
+    hipLaunchKernelGGL(itebd_energy_kernel, dim3((unsigned)b->batch), dim3(kThreads), 0, b->stream, b->states(),
+                       b->chi, H, dev);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(energies, dev, 8 * (size_t)b->batch, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return HOTRG_EHIP;
+    return HOTRG_OK;
+}
+
+int itebd_copy_states(itebd_batch* b, double* host, size_t capacity) {
+    if (!b || !host) return HOTRG_EINVAL;
+    const size_t count = itebd_state_len(b->chi) * (size_t)b->batch;
+    if (capacity < count) return HOTRG_EINVAL;
+    if (hipMemcpyAsync(host, b->states(), 8 * count, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return HOTRG_EHIP;
+    return HOTRG_OK;
+}
+
+int itebd_info(itebd_batch* b, long* updates, int* max_sweeps) {
+    if (!b) return HOTRG_EINVAL;
+    if (updates) *updates = b->updates;
+    if (max_sweeps) {
+        int* host = new (std::nothrow) int[b->batch];
+        if (!host) return HOTRG_EINVAL;
+        const bool ok = hipMemcpyAsync(host, b->ws + b->L.sweeps, 4 * (size_t)b->batch, hipMemcpyDeviceToHost,
+                                       b->stream) == hipSuccess &&
+                        hipStreamSynchronize(b->stream) == hipSuccess;
+        int m = 0;
+        for (int i = 0; ok && i < b->batch; ++i) m = std::max(m, host[i]);
+        delete[] host;
+        if (!ok) return HOTRG_EHIP;
+        *max_sweeps = m;
+    }
+    return HOTRG_OK;
+}
+
+void itebd_destroy(itebd_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+}  // extern "C"

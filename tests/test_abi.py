@@ -2,6 +2,7 @@
 GPU and exports every function include/hotrg.h declares, and the host-only
 entry points (workspace sizing, parameter validation, strings) behave."""
 import ctypes
+import glob
 import os
 import re
 import subprocess
@@ -15,9 +16,12 @@ HEADER = os.path.join(ROOT, "include", "hotrg.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hotrg_[a-z0-9_]+)\s*\(", text)))
+    """Every function declared in include/*.h (hotrg_* and itebd_*)."""
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:hotrg|itebd)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +33,8 @@ def lib():
 
 
 def test_header_is_plain_c():
-    src = '#include "hotrg.h"\nint main(void) { hotrg_params p; (void)p; return HOTRG_OK; }\n'
+    src = ('#include "hotrg.h"\n#include "itebd.h"\n'
+           'int main(void) { hotrg_params p; (void)p; return HOTRG_OK + (int)itebd_state_len(1); }\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
@@ -41,6 +46,7 @@ def test_header_is_plain_c():
 def test_every_declared_function_is_exported(lib):
     names = declared_functions()
     assert "hotrg_init_tensor" in names and "hotrg_coarse_grain" in names and "hotrg_log_z" in names
+    assert "itebd_init" in names and "itebd_evolve" in names
     from paper_2602_05900_amd import binding
     for n in names:
         assert hasattr(lib, n), n
@@ -116,6 +122,22 @@ def test_workspace_of_two_sided_and_observables(lib):
     assert lib.hotrg_workspace_bytes(ctypes.byref(p)) > 0
     p.custom_impurity[0] = ctypes.POINTER(ctypes.c_double)()
     assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_itebd_sizes_and_error_paths(lib):
+    from paper_2602_05900_amd import binding
+    assert lib.itebd_state_len(8) == 4 * 64 + 16
+    assert lib.itebd_state_len(0) == 0 and lib.itebd_state_len(33) == 0
+    assert lib.itebd_workspace_bytes(0, 8) == 0 and lib.itebd_workspace_bytes(4, 33) == 0
+    w = lib.itebd_workspace_bytes(256, 32)
+    # states, two warm-start bases per chain (n^2 each, n = 64), counters
+    assert 256 * (4 * 1024 + 64) * 8 + 256 * 2 * 64 * 64 * 8 <= w < 1.01 * (256 * (4160 + 8192) * 8) + 8192
+    h = ctypes.c_void_p()
+    assert lib.itebd_init(1, 8, None, None, None, 0, None, ctypes.byref(h)) == binding.EINVAL
+    assert lib.itebd_evolve(None, 0.1, 1) == binding.EINVAL
+    assert lib.itebd_energy(None, None) == binding.EINVAL
+    assert lib.itebd_info(None, None, None) == binding.EINVAL
+    lib.itebd_destroy(None)
 
 
 def test_host_error_paths_without_device(lib):

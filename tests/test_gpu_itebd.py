@@ -1,0 +1,98 @@
+"""GPU parity of the batched iTEBD path (include/itebd.h) against the FP64
+oracle (oracle/itebd.py) on the same seeded initial states.
+
+FP64 bars: energies per site to 1e-12 relative, bond weights to 1e-10 and
+tensors (after the shared sign gauge) to 1e-9 absolute where the singular
+values at the cut are distinct (the transverse-field Ising chain); for the
+Heisenberg chain, whose Schmidt spectrum has SU(2) multiplets that a cut
+can split, energies only, to 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import itebd as oracle
+from paper_2602_05900_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_run(h, states, chi, schedule):
+    from paper_2602_05900_amd import binding
+    c = binding.Chains(h, states, chi)
+    for tau, n in schedule:
+        c.evolve(tau, n)
+    return c
+
+
+def oracle_run(h, row, chi, schedule):
+    st = oracle.unpack(row, chi)
+    for tau, n in schedule:
+        st = oracle.evolve(st, h, tau, n, chi)
+    return st
+
+
+@pytest.mark.parametrize("chi,nup", [(1, 40), (4, 120), (8, 200), (16, 120), (32, 60)])
+def test_tfim_parity(gpu_lib, chi, nup):
+    h = workloads.ising_transverse_bond(1.5)
+    states = workloads.random_chain_states(3, chi, seed=20 + chi)
+    sched = ((0.05, nup),)
+    c = gpu_run(h, states, chi, sched)
+    e = c.energies()
+    got = c.states()
+    nb = 2 * chi * chi
+    for i in range(3):
+        ref = oracle_run(h, states[i], chi, sched)
+        er = oracle.energy_per_site(ref, h)
+        assert abs(e[i] - er) <= 1e-12 * abs(er)
+        g = oracle.unpack(got[i], chi)
+        np.testing.assert_allclose(g.l1, ref.l1, atol=1e-10)
+        np.testing.assert_allclose(g.l2, ref.l2, atol=1e-10)
+        np.testing.assert_allclose(g.B1, ref.B1, atol=1e-9)
+        np.testing.assert_allclose(g.B2, ref.B2, atol=1e-9)
+    assert c.info()[0] == nup
+    assert c.info()[1] < 40
+
+
+def test_heisenberg_energy_parity_at_the_benchmark_bond_dimension(gpu_lib):
+    chi = 30
+    h = workloads.heisenberg_bond()
+    states = workloads.random_chain_states(2, chi, seed=5)
+    sched = ((0.1, 40), (0.02, 40))
+    e = gpu_run(h, states, chi, sched).energies()
+    for i in range(2):
+        er = oracle.energy_per_site(oracle_run(h, states[i], chi, sched), h)
+        assert abs(e[i] - er) <= 1e-9 * abs(er)
+
+
+def test_updated_site_is_right_canonical(gpu_lib):
+    """After every update the new left site of the next bond is V_kept^T:
+    its rows are orthonormal (sum over physical and right index)."""
+    chi = 12
+    c = gpu_run(workloads.heisenberg_bond(), workloads.random_chain_states(2, chi, seed=9), chi, ((0.05, 301),))
+    for row in c.states():
+        B1 = oracle.unpack(row, chi).B1
+        R = B1.transpose(1, 0, 2).reshape(chi, -1)
+        np.testing.assert_allclose(R @ R.T, np.eye(chi), atol=1e-12)
+
+
+def test_chains_in_a_batch_are_independent(gpu_lib):
+    chi = 8
+    h = workloads.ising_transverse_bond(0.7)
+    states = workloads.random_chain_states(5, chi, seed=11)
+    all5 = gpu_run(h, states, chi, ((0.05, 64),)).states()
+    one = gpu_run(h, states[3:4], chi, ((0.05, 64),)).states()
+    assert np.array_equal(all5[3], one[0])
+
+
+def test_gpu_chains_approach_exact_energies(gpu_lib):
+    """Trend: transverse-field Ising (g = 1.5, chi = 16) near its exact
+    energy and the Heisenberg chain (chi = 32) near the Bethe energy after a
+    short tau schedule; every chain of the batch above its ground state."""
+    sched = ((0.1, 200), (0.05, 400), (0.01, 1600))
+    h = workloads.ising_transverse_bond(1.5)
+    e = gpu_run(h, workloads.random_chain_states(4, 16, seed=1), 16, sched).energies()
+    ex = oracle.tfim_energy(1.5)
+    assert np.all(e > ex) and np.all(e - ex < 1.5e-3)
+    h = workloads.heisenberg_bond()
+    e = gpu_run(h, workloads.random_chain_states(4, 32, seed=2), 32, sched).energies()
+    assert np.all(e > oracle.BETHE_HEISENBERG) and np.all(e - oracle.BETHE_HEISENBERG < 1.5e-3)
