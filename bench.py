@@ -192,6 +192,54 @@ def run_observables(binding, accounting):
     return out
 
 
+def run_itebd(binding, workloads):
+    """iTEBD of the S = 1/2 antiferromagnetic Heisenberg chain (the paper's
+    iTEBD workload), FP64, random initial states: (1) 256 chains at
+    D_b = 30 for 10,000 bond updates at tau = 0.01 (aggregate updates/s and
+    the energy per site against the Bethe value); (2) time per bond update
+    against D_b for one chain and for 256 chains (1,000 updates each), with
+    the fitted exponent x of time ~ D_b^x."""
+    import math
+    import numpy as np
+    import torch
+    h = workloads.heisenberg_bond()
+    bethe = 0.25 - math.log(2.0)
+    out = {"workload": "S=1/2 AF Heisenberg chain, FP64, random initial states, one workgroup per chain"}
+    chi, batch, nup = 30, 256, 10000
+    c = binding.Chains(h, workloads.random_chain_states(batch, chi, seed=2026), chi)
+    c.evolve(0.1, 200)
+    c.energies()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.evolve(0.01, nup)
+    e = c.energies()
+    dt = time.perf_counter() - t0
+    out["d30_batch256"] = {"chains": batch, "bond_updates_per_chain": nup, "seconds": dt,
+                           "updates_per_s": batch * nup / dt, "us_per_update_per_chain": dt / nup * 1e6,
+                           "energy_mean": float(np.mean(e)), "energy_minus_bethe_max": float(np.max(e) - bethe),
+                           "energy_minus_bethe_min": float(np.min(e) - bethe),
+                           "max_jacobi_sweeps_last_launch": c.info()[1]}
+    c.close()
+    scan = {}
+    for b in (1, 256):
+        rows = []
+        for d in (4, 8, 12, 16, 20, 24, 30):
+            c = binding.Chains(h, workloads.random_chain_states(b, d, seed=d), d)
+            c.evolve(0.05, 64)
+            c.energies()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.evolve(0.05, 1000)
+            c.energies()
+            dt = time.perf_counter() - t0
+            rows.append((d, dt / 1000 * 1e6))
+            c.close()
+        x = np.polyfit(np.log([r[0] for r in rows]), np.log([r[1] for r in rows]), 1)[0]
+        scan[f"batch{b}"] = {"us_per_update": {str(d): t for d, t in rows}, "fit_exponent": float(x)}
+    out["scaling"] = scan
+    return out
+
+
 def run_c5(binding, accounting):
     """Ising at Tc, D = 64, 40 steps, one solve in BF16x6 and one in FP64 on
     the same GPU: throughput and |delta f| between them and against Onsager."""
@@ -263,6 +311,7 @@ def main():
     ap.add_argument("--no-c5", dest="c5", action="store_false", help="skip the D=64 solve")
     ap.add_argument("--no-observables", dest="observables", action="store_false",
                     help="skip the two-sided / impurity-observable runs")
+    ap.add_argument("--no-itebd", dest="itebd", action="store_false", help="skip the iTEBD runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -407,6 +456,10 @@ def main():
     if args.observables:
         print("# observables: two-sided, m and e impurities ...", file=sys.stderr, flush=True)
         line["observables"] = run_observables(binding, accounting)
+    if args.itebd:
+        print("# iTEBD: Heisenberg chains ...", file=sys.stderr, flush=True)
+        from paper_2602_05900_amd import workloads as wl
+        line["itebd"] = run_itebd(binding, wl)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))

@@ -34,7 +34,15 @@ constexpr int kMaxN = 2 * kMaxChi;
 constexpr int kThreads = 256;
 constexpr int kUpdatesPerLaunch = 32;
 constexpr int kMaxSweeps = 40;
-constexpr double kTol = 1e-14;   // rotate a pair while |w_p.w_q| > kTol |w_p| |w_q|
+#ifndef ITEBD_TOL
+#define ITEBD_TOL 1e-14
+#endif
+#ifndef ITEBD_ABS
+#define ITEBD_ABS 0
+#endif
+// rotate a pair while |w_p.w_q| > kTol |w_p| |w_q| (relative test), or, with
+// the absolute test, while |w_p.w_q| > kTol |W|_F^2
+constexpr double kTol = ITEBD_TOL;
 
 struct Gate {
     double g[16];   // exp(-tau h), row-major [(s' t'), (s t)]
@@ -128,6 +136,11 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
         __syncthreads();
 
         // one-sided Jacobi
+        double fro2 = 0.0;
+        if (ITEBD_ABS) {
+            // |W|_F^2 (invariant under the rotations): every thread sums the same terms in the same order
+            for (int i = 0; i < n * n; ++i) fro2 = fma(sW[i], sW[i], fro2);
+        }
         const int g = tid >> 3, l8 = tid & 7;
         const int npair = n >> 1;
         int sweeps = kMaxSweeps;
@@ -156,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
                         be += shfl_xor_d(be, off);
                         ga += shfl_xor_d(ga, off);
                     }
-                    if (fabs(ga) > kTol * sqrt(al * be)) {
+                    if (fabs(ga) > kTol * (ITEBD_ABS ? fro2 : sqrt(al * be))) {
                         const double z = (be - al) / (2.0 * ga);
                         const double t = fabs(z) > 1e150 ? 0.5 / z
                                                          : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
