@@ -21,7 +21,11 @@ leg order, a dropped term, a transposed operand) shows up as a mismatch:
                            network (what an impurity-tensor estimator converges
                            to when nothing is truncated);
 * ``yang_magnetisation``   the spontaneous magnetisation of the square-lattice
-                           Ising model below T_c (Onsager / Yang).
+                           Ising model below T_c (Onsager / Yang);
+* ``trotter_ring_lnz``     ln Tr (G_odd G_even)^M of a spin-1/2 ring by exact
+                           diagonalisation, G = exp(-tau h) from scipy's expm;
+* ``tfim_free_energy``     free energy per site of the transverse-field Ising
+                           chain at temperature T (free fermions).
 """
 from __future__ import annotations
 
@@ -29,7 +33,7 @@ import itertools
 import math
 
 import numpy as np
-from scipy import integrate, special
+from scipy import integrate, linalg as sla, special
 
 CATALAN = 0.915965594177219015054603514932384110774
 
@@ -263,3 +267,53 @@ def finite_difference_energy(temperatures: np.ndarray, lnz: np.ndarray) -> np.nd
     d[0] = (-3.0 * g[0] + 4.0 * g[1] - g[2]) / (2.0 * h)
     d[-1] = (3.0 * g[-1] - 4.0 * g[-2] + g[-3]) / (2.0 * h)
     return T * T * d
+
+
+# --------------------------------------------------------------------------
+# Quantum chains: exact Trotterized rings and the free-fermion chain
+# --------------------------------------------------------------------------
+
+def _two_site_operator(G: np.ndarray, L: int, i: int, j: int) -> np.ndarray:
+    """The 2^L x 2^L matrix of a two-site operator G[(s_i' s_j'), (s_i s_j)]
+    acting on sites i and j of an L-site spin-1/2 ring (site 0 most
+    significant in the basis index)."""
+    dim = 2 ** L
+    out = np.zeros((dim, dim))
+    for col in range(dim):
+        si = (col >> (L - 1 - i)) & 1
+        sj = (col >> (L - 1 - j)) & 1
+        base = col & ~(1 << (L - 1 - i)) & ~(1 << (L - 1 - j))
+        for a in range(2):
+            for b in range(2):
+                row = base | (a << (L - 1 - i)) | (b << (L - 1 - j))
+                out[row, col] += G[2 * a + b, 2 * si + sj]
+    return out
+
+
+def trotter_ring_lnz(h: np.ndarray, tau: float, L: int, M: int) -> float:
+    """ln Tr U^M with U = G_odd G_even on a ring of L (even) sites:
+    G_even the product of G = expm(-tau h) on bonds (0,1), (2,3), ...,
+    G_odd on bonds (1,2), (3,4), ..., (L-1, 0)."""
+    G = sla.expm(-tau * np.asarray(h, dtype=np.float64))
+    dim = 2 ** L
+    Ge = np.eye(dim)
+    Go = np.eye(dim)
+    for j in range(0, L, 2):
+        Ge = _two_site_operator(G, L, j, j + 1) @ Ge
+    for j in range(1, L, 2):
+        Go = _two_site_operator(G, L, j, (j + 1) % L) @ Go
+    U = Go @ Ge
+    c = float(np.max(np.abs(U)))
+    P = np.linalg.matrix_power(U / c, M)
+    return M * math.log(c) + math.log(float(np.trace(P)))
+
+
+def tfim_free_energy(g: float, temperature: float, J: float = 1.0) -> float:
+    """Free energy per site of H = -J sum sz sz - g sum sx (Pauli) on the
+    infinite chain: -(T/pi) int_0^pi ln(2 cosh(e_k / T)) dk with
+    e_k = sqrt(J^2 + g^2 + 2 J g cos k)."""
+    def integrand(k):
+        e = math.sqrt(J * J + g * g + 2.0 * J * g * math.cos(k)) / temperature
+        return e + math.log1p(math.exp(-2.0 * e))     # ln(2 cosh e)
+    val, _ = integrate.quad(integrand, 0.0, math.pi, epsabs=1e-13, epsrel=1e-13, limit=400)
+    return -temperature * val / math.pi

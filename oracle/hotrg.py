@@ -249,7 +249,7 @@ class StepResult:
 
 
 def coarse_grain_step(T: np.ndarray, dmax: int, two_sided: bool = False,
-                      impurities=()) -> StepResult:
+                      impurities=(), exchange: bool = True) -> StepResult:
     """One HOTRG step on T[l, r, d, u] with dims [Dx, Dx, Dy, Dy].
 
     X[l,a2,r1,d,k] = sum_{a1}     U[a1,a2,l] T[a1,r1,d,k]
@@ -266,6 +266,9 @@ def coarse_grain_step(T: np.ndarray, dmax: int, two_sided: bool = False,
     impurities: tensors I of T's dims; each becomes
     I' = U^T (I (x) T + T (x) I) U / (2 c_n), the bottom copy written first,
     exchanged like T.
+
+    exchange=False keeps T'[l, r, d, u] as it is, so the next step merges
+    along the same axis again (dims [Dx, Dx, Dy, Dy] -> [D', D', Dy, Dy]).
     """
     Dx = T.shape[0]
     if T.shape[1] != Dx or T.shape[3] != T.shape[2]:
@@ -289,8 +292,9 @@ def coarse_grain_step(T: np.ndarray, dmax: int, two_sided: bool = False,
         YI = (np.einsum("lbrdk,bsku->lrdsu", XI, T, optimize=True)      # impurity in the bottom copy
               + np.einsum("lbrdk,bsku->lrdsu", X, I, optimize=True))    # impurity in the top copy
         Ip = 0.5 * np.einsum("lrdsu,rsm->lmdu", YI, U3, optimize=True) / c
-        nxt.append(np.ascontiguousarray(Ip.transpose(2, 3, 0, 1)))
-    return StepResult(T_next=np.ascontiguousarray(Tp.transpose(2, 3, 0, 1)), c=c, trunc=tr,
+        nxt.append(np.ascontiguousarray(Ip.transpose(2, 3, 0, 1) if exchange else Ip))
+    Tn = Tp.transpose(2, 3, 0, 1) if exchange else Tp
+    return StepResult(T_next=np.ascontiguousarray(Tn), c=c, trunc=tr,
                       eps_left=eps_left, eps_right=eps_right, side=side, impurities_next=nxt)
 
 
@@ -314,7 +318,7 @@ class Solve:
 
 
 def solve_tensor(T0: np.ndarray, dmax: int, nsteps: int, keep_tensor: bool = True,
-                 two_sided: bool = False, impurities=()) -> Solve:
+                 two_sided: bool = False, impurities=(), schedule=None) -> Solve:
     """Run nsteps HOTRG steps from the local tensor T0 and return ln Z / N.
 
     ln Z/N = ln c_0 + sum_{n=1..nsteps} ln(c_n)/2^n + ln(sum_{x,y} T[x,x,y,y]) / 2^nsteps,
@@ -330,7 +334,7 @@ def solve_tensor(T0: np.ndarray, dmax: int, nsteps: int, keep_tensor: bool = Tru
     lnz = math.log(c0)
     for n in range(1, nsteps + 1):
         out.dims.append((T.shape[0], T.shape[2]))
-        step = coarse_grain_step(T, dmax, two_sided, imps)
+        step = coarse_grain_step(T, dmax, two_sided, imps, True if schedule is None else bool(schedule[n - 1]))
         T = step.T_next
         imps = step.impurities_next
         out.c.append(step.c)
