@@ -66,6 +66,9 @@ extern "C" {
 #define HOTRG_ISING   0  /* q = 2, H = -J sum s s'                              */
 #define HOTRG_POTTS   1  /* q states, H = -J sum delta(s, s')                  */
 #define HOTRG_CUSTOM  2  /* caller-supplied initial tensor (FP64, host memory) */
+#define HOTRG_QCHAIN  3  /* spin-1/2 chain, bond term bond_h, Trotter step tau:
+                            one tensor per two-site block and step (x = space,
+                            y = imaginary time), see hotrg_log_z_chain      */
 
 #define HOTRG_FP64    0  /* contractions in FP64 MFMA                          */
 #define HOTRG_FP32    1  /* contractions in FP32 MFMA, FP32 accumulation       */
@@ -114,6 +117,9 @@ typedef struct hotrg_params {
     const double* custom_impurity[2]; /* HOTRG_CUSTOM: the impurity tensors of
                             slots 0 and 1 (host, dims of custom_tensor), read
                             during init only, for the bits set in observables */
+    const double* bond_h; /* HOTRG_QCHAIN: two-site term h, real symmetric 4 x 4,
+                            row-major, basis |s t> = 2 s + t (read at init)   */
+    double tau;          /* HOTRG_QCHAIN: Trotter step (> 0)                   */
 } hotrg_params;
 
 /* Bytes of device workspace one solve with these parameters needs, for any
@@ -158,6 +164,18 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p);
  * ESTATE (handle already failed), EHIP. */
 int hotrg_coarse_grain(hotrg_solve* s, int nsteps);
 
+/* hotrg_coarse_grain with a choice of axis: exchange = 1 is the usual step
+ * (merge along y, then exchange x and y); exchange = 0 keeps the axes, so the
+ * next step merges along y again (dims (Dx, Dy) -> (D', Dy)).  For a quantum
+ * chain (HOTRG_QCHAIN, y = imaginary time) k steps with exchange = 0 are
+ * operator evolution to beta = 2^k tau: only the space bonds are truncated.
+ * Before each step the library checks that its dims fit the workspace (sized
+ * for the alternating schedule up to max_steps); a schedule that reaches
+ * larger dims gets ENOMEM with nothing enqueued for that step.
+ * Errors: EINVAL (nsteps < 0, exchange not 0/1, step cap), ENOMEM, ESTATE,
+ * EHIP. */
+int hotrg_coarse_grain_axis(hotrg_solve* s, int nsteps, int exchange);
+
 /* Serving form of hotrg_coarse_grain for a group of independent solves:
  * enqueues nsteps steps on each of the count handles in solves[], step by
  * step across the group (step 1 of every handle, then step 2, ...), each on
@@ -179,6 +197,19 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps);
  * -temperature * lnz_per_site.
  * Errors: any latched device error; ENONFINITE if the final trace is <= 0. */
 int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites);
+
+/* ln Z per tensor of the network that is infinite along x and periodic
+ * along y with the current tensor's extent (2^steps original tensors in
+ * each column, for HOTRG_QCHAIN after y-only steps: beta = 2^steps tau):
+ * y is closed by the trace t[l, r] = sum_s T[l, r, s, s], and the infinite
+ * chain of columns contributes the dominant eigenvalue of t,
+ *   ln Z/N = ln c_0 + sum_n ln(c_n) / 2^n + ln(lambda_max(t)) / 2^steps,
+ * lambda_max from 64 normalised squarings of t on the device (FP64; a
+ * modulus-degenerate pair +-lambda gives ln |lambda|).  For HOTRG_QCHAIN the
+ * free energy per site is -(ln Z/N) / (2 tau).  Synchronises.  Errors:
+ * latched device errors; ENONFINITE if the trace of the last square is not
+ * positive; EINVAL (Dx > 96). */
+int hotrg_log_z_chain(hotrg_solve* s, double* lnz_per_tensor);
 
 /* Synchronises and reports diagnostics of step n (1..steps taken): the
  * normalisation c_n = max|T'|, the truncation error (discarded eigenvalue

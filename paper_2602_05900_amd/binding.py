@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(PKG, "libhotrg.so")
 # status codes
 OK, EINVAL, ENOMEM, EHIP, EEIG, ENONFINITE, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 # models and precisions
-ISING, POTTS, CUSTOM = 0, 1, 2
+ISING, POTTS, CUSTOM, QCHAIN = 0, 1, 2, 3
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
-MODELS = {"ising": ISING, "potts": POTTS, "custom": CUSTOM}
+MODELS = {"ising": ISING, "potts": POTTS, "custom": CUSTOM, "qchain": QCHAIN}
 MAX_STEPS = 60
 STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm", "obs"]
 # observable slots (hotrg_observables): order parameter per site, energy of one y bond
@@ -30,7 +30,7 @@ OBSERVABLES = {"m": OBS_MAGNETIZATION, "e": OBS_BOND_ENERGY}
 
 EXPORTS = [
     "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain",
-    "hotrg_coarse_grain_batch", "hotrg_log_z",
+    "hotrg_coarse_grain_batch", "hotrg_coarse_grain_axis", "hotrg_log_z", "hotrg_log_z_chain",
     "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
@@ -62,6 +62,8 @@ class Params(ctypes.Structure):
         ("two_sided", ctypes.c_int),
         ("observables", ctypes.c_int),
         ("custom_impurity", ctypes.POINTER(ctypes.c_double) * 2),
+        ("bond_h", ctypes.POINTER(ctypes.c_double)),
+        ("tau", ctypes.c_double),
     ]
 
 
@@ -85,6 +87,8 @@ def load() -> ctypes.CDLL:
     lib.hotrg_reset.argtypes = [c_void_p, P(Params)]
     lib.hotrg_coarse_grain.argtypes = [c_void_p, c_int]
     lib.hotrg_coarse_grain_batch.argtypes = [P(c_void_p), c_int, c_int]
+    lib.hotrg_coarse_grain_axis.argtypes = [c_void_p, c_int, c_int]
+    lib.hotrg_log_z_chain.argtypes = [c_void_p, P(c_double)]
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
     lib.hotrg_eig_info.argtypes = [c_void_p, c_int, P(c_int), P(c_int), P(c_double)]
@@ -148,7 +152,8 @@ def runtime_version() -> int:
 
 def make_params(model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
                 precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0,
-                field: float = 0.0, two_sided: bool = False, observables=(), impurities=None) -> tuple:
+                field: float = 0.0, two_sided: bool = False, observables=(), impurities=None,
+                bond_h=None, tau: float = 0.0) -> tuple:
     """hotrg_params plus the host arrays it points to (kept alive by the caller).
 
     observables: names from OBSERVABLES ("m", "e"); for the custom model,
@@ -168,6 +173,12 @@ def make_params(model: str = "ising", q: int = 2, temperature: float = 2.0, dmax
         mask |= OBSERVABLES[o]
     p.observables = mask
     keep = []
+    if model == "qchain":
+        import numpy as np
+        hb = np.ascontiguousarray(bond_h, dtype=np.float64).reshape(16)
+        keep.append(hb)
+        p.bond_h = hb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.tau = tau
     if model == "custom":
         import numpy as np
         t = np.ascontiguousarray(tensor, dtype=np.float64)
@@ -197,11 +208,12 @@ class Solve:
     def __init__(self, model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
                  precision: str = "fp64", coupling: float = 1.0, tensor=None, stream=None,
                  workspace=None, device="cuda", max_steps: int = 0, field: float = 0.0,
-                 two_sided: bool = False, observables=(), impurities=None):
+                 two_sided: bool = False, observables=(), impurities=None, bond_h=None, tau: float = 0.0):
         lib = load()
         self._lib = lib
         p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps,
-                              field, two_sided, observables, impurities)
+                              field, two_sided, observables, impurities, bond_h, tau)
+        self.tau = tau
         nbytes = lib.hotrg_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise HotrgError(EINVAL, "hotrg_workspace_bytes")
@@ -229,9 +241,18 @@ class Solve:
         self.temperature = temperature
         return self
 
-    def coarse_grain(self, nsteps: int) -> "Solve":
-        _check(self._lib.hotrg_coarse_grain(self._h, int(nsteps)), "hotrg_coarse_grain")
+    def coarse_grain(self, nsteps: int, exchange: bool = True) -> "Solve":
+        if exchange:
+            _check(self._lib.hotrg_coarse_grain(self._h, int(nsteps)), "hotrg_coarse_grain")
+        else:
+            _check(self._lib.hotrg_coarse_grain_axis(self._h, int(nsteps), 0), "hotrg_coarse_grain_axis")
         return self
+
+    def log_z_chain(self) -> float:
+        """ln Z per tensor with x infinite and y closed (hotrg_log_z_chain)."""
+        v = ctypes.c_double()
+        _check(self._lib.hotrg_log_z_chain(self._h, ctypes.byref(v)), "hotrg_log_z_chain")
+        return v.value
 
     def log_z(self) -> float:
         v = ctypes.c_double()

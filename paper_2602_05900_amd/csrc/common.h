@@ -107,6 +107,8 @@ struct DevState {
     int r_sweeps[64];
     double r_resid[64];
     double imp_trace[2];  // sum_{x,y} I[x,x,y,y] of the impurity tensors
+    double chain_lnz;     // ln lambda_max of the y-traced tensor (hotrg_log_z_chain)
+    int chain_ok;         // 1 if the last normalised square had a positive trace
     double partial[1024]; // partial maxima of the normalisation reduction
 };
 
@@ -172,6 +174,10 @@ hipError_t launch_normalize(double* T, size_t count, DevState* st, int n, hipStr
 // trace = sum_{x,y} T[x,x,y,y] for T of dims [Dx,Dx,Dy,Dy] (into *out, a
 // device address, default st->trace).
 hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream_t stream, double* out = nullptr);
+// ln lambda_max of t[l, r] = sum_s T[l, r, s, s] (T of dims [Dx, Dx, Dy, Dy],
+// Dx <= 96) by `squarings` normalised squarings in one workgroup, into
+// st->chain_lnz and st->chain_ok.
+hipError_t launch_chain_lnz(const double* T, int Dx, int Dy, int squarings, DevState* st, hipStream_t stream);
 // I <- I * factor / c_n (c_n of the last normalisation, read on the device).
 hipError_t launch_scale_by_norm(double* I, size_t count, const DevState* st, double factor, hipStream_t stream);
 // E <- (E + E^T) / 2 for an n x n matrix.

@@ -114,6 +114,13 @@ bool valid_params(const hotrg_params* p) {
         if (p->q != 2) return false;
     } else if (p->model == HOTRG_POTTS) {
         if (p->q < 2 || p->q > kMaxQ) return false;
+    } else if (p->model == HOTRG_QCHAIN) {
+        if (!p->bond_h || !(p->tau > 0.0) || !isfinite(p->tau)) return false;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                if (!isfinite(p->bond_h[4 * i + j]) || p->bond_h[4 * i + j] != p->bond_h[4 * j + i]) return false;
+        if (p->field != 0.0 || p->observables) return false;
+        return true;
     } else if (p->model == HOTRG_CUSTOM) {
         if (!p->custom_tensor) return false;
         if (p->custom_dx < 1 || p->custom_dx > HOTRG_MAX_DIM) return false;
@@ -137,7 +144,9 @@ void initial_dims(const hotrg_params* p, int* dx, int* dy);
 bool eig_feasible(const hotrg_params* p);
 
 void initial_dims(const hotrg_params* p, int* dx, int* dy) {
-    if (p->model == HOTRG_CUSTOM) {
+    if (p->model == HOTRG_QCHAIN) {
+        *dx = *dy = 4;   // split bond of the gate, two spins of a block
+    } else if (p->model == HOTRG_CUSTOM) {
         *dx = p->custom_dx;
         *dy = p->custom_dy;
     } else {
@@ -309,6 +318,101 @@ ModelTensors model_tensors(const hotrg_params* p) {
     return mt;
 }
 
+// Eigendecomposition a = Q diag(w) Q^T of a real symmetric 4 x 4 matrix by
+// cyclic Jacobi rotations (host, FP64).
+void sym_eig4(const double* a, double* w, double* Q) {
+    double A[16];
+    memcpy(A, a, sizeof A);
+    for (int i = 0; i < 16; ++i) Q[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q) {
+                tot += A[4 * p + q] * A[4 * p + q];
+                if (p != q) off += A[4 * p + q] * A[4 * p + q];
+            }
+        if (off <= 1e-32 * tot || off < 1e-300) break;
+        for (int p = 0; p < 4; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                const double apq = A[4 * p + q];
+                if (apq == 0.0) continue;
+                const double z = (A[4 * q + q] - A[4 * p + p]) / (2.0 * apq);
+                const double t = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                for (int k = 0; k < 4; ++k) {
+                    const double akp = A[4 * k + p], akq = A[4 * k + q];
+                    A[4 * k + p] = c * akp - sn * akq;
+                    A[4 * k + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double apk = A[4 * p + k], aqk = A[4 * q + k];
+                    A[4 * p + k] = c * apk - sn * aqk;
+                    A[4 * q + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < 4; ++k) {
+                    const double qkp = Q[4 * k + p], qkq = Q[4 * k + q];
+                    Q[4 * k + p] = c * qkp - sn * qkq;
+                    Q[4 * k + q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    for (int i = 0; i < 4; ++i) w[i] = A[4 * i + i];
+}
+
+// Block tensor of a spin-1/2 chain (one tensor = two sites x one Trotter
+// step of U = G_odd G_even, G = exp(-tau h)):
+//   G[(s1' s2'),(s1 s2)] = sum_k A_k[s1', s1] B_k[s2', s2] from the SVD of the
+//   rearranged R[(s1' s1), (s2' s2)] (through the eigenvectors of R^T R);
+//   T[l, r, (s0 s1), (s0' s1')] = sum_{x,y} B_l[s0', x] A_r[s1', y] G[(x y), (s0 s1)]
+// x = the split bonds (space), y = the block's spins below/above (time).
+std::vector<double> qchain_tensor(const double* h, double tau) {
+    double w[4], Q[16], G[16];
+    sym_eig4(h, w, Q);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k) acc += Q[4 * i + k] * exp(-tau * w[k]) * Q[4 * j + k];
+            G[4 * i + j] = acc;
+        }
+    double R[16], RtR[16], sv[4], V[16];
+    for (int a = 0; a < 2; ++a)          // s1'
+        for (int b = 0; b < 2; ++b)      // s2'
+            for (int c = 0; c < 2; ++c)  // s1
+                for (int d = 0; d < 2; ++d) R[4 * (2 * a + c) + (2 * b + d)] = G[4 * (2 * a + b) + (2 * c + d)];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k) acc += R[4 * k + i] * R[4 * k + j];
+            RtR[4 * i + j] = acc;
+        }
+    sym_eig4(RtR, sv, V);
+    double A[4][4], B[4][4];   // A[k][(s1' s1)], B[k][(s2' s2)]
+    for (int k = 0; k < 4; ++k) {
+        const double sig = sqrt(fmax(sv[k], 0.0));
+        const double rs = sqrt(sig);
+        for (int i = 0; i < 4; ++i) {
+            B[k][i] = rs * V[4 * i + k];
+            double u = 0.0;
+            for (int j = 0; j < 4; ++j) u += R[4 * i + j] * V[4 * j + k];
+            A[k][i] = sig > 1e-300 ? u / rs : 0.0;
+        }
+    }
+    std::vector<double> T(256, 0.0);
+    for (int l = 0; l < 4; ++l)
+        for (int r = 0; r < 4; ++r)
+            for (int s0 = 0; s0 < 2; ++s0)
+                for (int s1 = 0; s1 < 2; ++s1)
+                    for (int p0 = 0; p0 < 2; ++p0)
+                        for (int p1 = 0; p1 < 2; ++p1) {
+                            double acc = 0.0;
+                            for (int x = 0; x < 2; ++x)
+                                for (int y = 0; y < 2; ++y)
+                                    acc += B[l][2 * p0 + x] * A[r][2 * p1 + y] * G[4 * (2 * x + y) + (2 * s0 + s1)];
+                            T[((l * 4 + r) * 4 + (2 * s0 + s1)) * 4 + (2 * p0 + p1)] = acc;
+                        }
+    return T;
+}
+
 }  // namespace
 
 struct hotrg_solve {
@@ -395,11 +499,23 @@ Buf column_block(const Buf& B, int blk, long w, long ld, bool panel) {
     return o;
 }
 
-int enqueue_step(hotrg_solve* s) {
+// Whether a step from dims (Dx, Dy) fits the workspace carved for the handle.
+bool step_fits(const Layout& L, int Dx, int Dy, int Dp) {
+    const size_t x = Dx, y = Dy, dp = Dp;
+    if (std::max(x * x * y * y, y * y * dp * dp) > L.nT || dp * dp * y * y > L.nT) return false;
+    if (x * x * y * y > L.nP || x * x * y * y > L.nAB || x * x * x * x > L.nE) return false;
+    if (dp * x * x > L.nU || dp * x * x * y * y > L.nX) return false;
+    const int n = Dx * Dx;
+    if (n > kEigPMax && ((size_t)n > L.nEig || eig_block(n, Dp) <= Dp)) return false;
+    return true;
+}
+
+int enqueue_step(hotrg_solve* s, bool exchange = true) {
     const int n = s->steps + 1;       // 1-based step number
     const int Dx = s->dx, Dy = s->dy;
     const int Dp = (int)std::min<long>(s->p.dmax, (long)Dx * Dx);
     const int nE = Dx * Dx;
+    if (!step_fits(s->L, Dx, Dy, Dp)) return HOTRG_ENOMEM;
     const Fmt f = s->fmt;
     const Layout& L = s->L;
     const int nimp = L.nimp;
@@ -527,7 +643,9 @@ int enqueue_step(hotrg_solve* s) {
         return HOTRG_OK;
     };
     const OutMap ym{Dx, (long)Dy * Dx * Dx, Dx, Dx, (long)Dx * Dx, 1};   // -> Y[l,d,u,r1,r2]
-    const OutMap tm{(long)Dy * Dy, Dp, (long)Dp * Dp, Dp, 0, 1};         // -> next T[d,u,l,r]
+    // -> next T[d,u,l,r] (x <-> y exchanged), or T[l,r,d,u] kept
+    const OutMap tm = exchange ? OutMap{(long)Dy * Dy, Dp, (long)Dp * Dp, Dp, 0, 1}
+                               : OutMap{(long)Dy * Dy, (long)Dp * Dy * Dy, 1, Dp, 0, (long)Dy * Dy};
     // -- X = U . T  -> X[l,d,r1,a2,k]
     if ((rc = x_product(s->T(), xblk_T))) return rc;
     record(s, step_index, 5);
@@ -564,8 +682,12 @@ int enqueue_step(hotrg_solve* s) {
         }
     }
     record(s, step_index, 10);
-    s->dx = Dy;
-    s->dy = Dp;
+    if (exchange) {
+        s->dx = Dy;
+        s->dy = Dp;
+    } else {
+        s->dx = Dp;
+    }
     s->steps = n;
     return HOTRG_OK;
 }
@@ -580,7 +702,9 @@ int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     for (int i = 0; i < 2; ++i) s->warm_n[i] = s->warm_p[i] = s->warm_nr[i] = s->warm_pr[i] = 0;
     const size_t count = (size_t)s->dx * s->dx * s->dy * s->dy;
     ModelTensors mt;
-    if (p->model == HOTRG_CUSTOM) {
+    if (p->model == HOTRG_QCHAIN) {
+        mt.T = qchain_tensor(p->bond_h, p->tau);
+    } else if (p->model == HOTRG_CUSTOM) {
         mt.T.assign(p->custom_tensor, p->custom_tensor + count);
         for (int j = 0; j < 2; ++j)
             if (p->observables >> j & 1) mt.I[j].assign(p->custom_impurity[j], p->custom_impurity[j] + count);
@@ -641,6 +765,7 @@ int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes, v
     s->p = *p;
     s->p.custom_tensor = nullptr;
     s->p.custom_impurity[0] = s->p.custom_impurity[1] = nullptr;
+    s->p.bond_h = nullptr;
     s->stream = static_cast<hipStream_t>(stream);
     s->ws = static_cast<char*>(workspace);
     s->ws_bytes = ws_bytes;
@@ -668,6 +793,7 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
     s->p = *p;
     s->p.custom_tensor = nullptr;
     s->p.custom_impurity[0] = s->p.custom_impurity[1] = nullptr;
+    s->p.bond_h = nullptr;
     s->fmt = fmt_of(p->precision);
     s->products = products_of(p->precision);
     s->host_status = HOTRG_OK;
@@ -682,6 +808,31 @@ int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
         const int rc = enqueue_step(s);
         if (rc) return rc;
     }
+    return HOTRG_OK;
+}
+
+int hotrg_coarse_grain_axis(hotrg_solve* s, int nsteps, int exchange) {
+    if (!s || nsteps < 0 || (exchange != 0 && exchange != 1)) return HOTRG_EINVAL;
+    if (s->host_status) return HOTRG_ESTATE;
+    if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
+    for (int i = 0; i < nsteps; ++i) {
+        const int rc = enqueue_step(s, exchange != 0);
+        if (rc) return rc;
+    }
+    return HOTRG_OK;
+}
+
+int hotrg_log_z_chain(hotrg_solve* s, double* lnz_per_tensor) {
+    if (!s || !lnz_per_tensor) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    if (s->dx > 96) return HOTRG_EINVAL;
+    HIP_TRY(s, launch_chain_lnz(s->T(), s->dx, s->dy, 64, s->state(), s->stream));
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    if (!d.chain_ok) return HOTRG_ENONFINITE;
+    *lnz_per_tensor = d.lnz_acc + d.chain_lnz * ldexp(1.0, -s->steps);
     return HOTRG_OK;
 }
 

@@ -202,6 +202,59 @@ hipError_t launch_trace(const double* T, int Dx, int Dy, DevState* st, hipStream
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- chain closure
+
+// One workgroup: A = t (the y-traced tensor, Dx x Dx, in LDS), then
+// A <- A A / c_j with c_j = max|A A| and acc += ln(c_j) / 2^(j+1), so that
+// ln lambda_max = acc + ln(Tr A) / 2^squarings (exactly so as squarings grow,
+// for a dominant eigenvalue of largest modulus).  Fixed-order reductions.
+constexpr int kChainMax = 96;
+__global__ __launch_bounds__(256) void chain_lnz_kernel(const double* __restrict__ T, int Dx, int Dy, int squarings,
+                                                        DevState* st) {
+    __shared__ double A[kChainMax * kChainMax];
+    __shared__ double B[kChainMax * kChainMax];
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    const int nn = Dx * Dx;
+    for (int i = tid; i < nn; i += 256) {
+        const int l = i / Dx, r = i - (i / Dx) * Dx;
+        double acc = 0.0;
+        for (int s = 0; s < Dy; ++s) acc += T[(((long)l * Dx + r) * Dy + s) * Dy + s];
+        A[i] = acc;
+    }
+    __syncthreads();
+    double lacc = 0.0;
+    for (int j = 0; j < squarings; ++j) {
+        double m = 0.0;
+        for (int i = tid; i < nn; i += 256) {
+            const int a = i / Dx, b = i - (i / Dx) * Dx;
+            double acc = 0.0;
+            for (int k = 0; k < Dx; ++k) acc = fma(A[a * Dx + k], A[k * Dx + b], acc);
+            B[i] = acc;
+            m = fmax(m, fabs(acc));
+        }
+        m = block_max<256>(m, sh);
+        if (!(m > 0.0) || !isfinite(m)) break;
+        lacc += log(m) * ldexp(1.0, -(j + 1));
+        for (int i = tid; i < nn; i += 256) A[i] = B[i] / m;
+        __syncthreads();
+    }
+    double tr = 0.0;
+    for (int i = tid; i < Dx; i += 256) tr += A[i * Dx + i];
+    tr = block_sum<256>(tr, sh);
+    if (tid == 0) {
+        const bool ok = tr > 0.0 && isfinite(tr);
+        st->chain_ok = ok ? 1 : 0;
+        st->chain_lnz = ok ? lacc + log(tr) * ldexp(1.0, -squarings) : 0.0;
+    }
+}
+
+hipError_t launch_chain_lnz(const double* T, int Dx, int Dy, int squarings, DevState* st, hipStream_t stream) {
+    if (Dx < 1 || Dx > kChainMax || Dy < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(chain_lnz_kernel, dim3(1), dim3(256), 0, stream, T, Dx, Dy, squarings, st);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- E symmetrisation
 
 __global__ void symmetrize_kernel(double* __restrict__ E, int n) {

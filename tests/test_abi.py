@@ -59,14 +59,15 @@ def test_params_struct_matches_header(lib):
            'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(hotrg_params), '
            'offsetof(hotrg_params, custom_tensor), offsetof(hotrg_params, max_steps), '
            'offsetof(hotrg_params, field), offsetof(hotrg_params, two_sided), '
-           'offsetof(hotrg_params, observables), offsetof(hotrg_params, custom_impurity));return 0;}\n')
+           'offsetof(hotrg_params, observables), offsetof(hotrg_params, custom_impurity));'
+           'printf("%zu %zu\\n", offsetof(hotrg_params, bond_h), offsetof(hotrg_params, tau));return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "t")
         subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True).stdout.split()
-        size, off_t, off_m, off_f, off_2, off_o, off_i = (int(x) for x in out)
+        size, off_t, off_m, off_f, off_2, off_o, off_i, off_h, off_tau = (int(x) for x in out)
     assert ctypes.sizeof(binding.Params) == size
     assert binding.Params.custom_tensor.offset == off_t
     assert binding.Params.max_steps.offset == off_m
@@ -74,6 +75,7 @@ def test_params_struct_matches_header(lib):
     assert binding.Params.two_sided.offset == off_2
     assert binding.Params.observables.offset == off_o
     assert binding.Params.custom_impurity.offset == off_i
+    assert binding.Params.bond_h.offset == off_h and binding.Params.tau.offset == off_tau
 
 
 def test_workspace_sizing_and_validation(lib):
@@ -122,6 +124,19 @@ def test_workspace_of_two_sided_and_observables(lib):
     assert lib.hotrg_workspace_bytes(ctypes.byref(p)) > 0
     p.custom_impurity[0] = ctypes.POINTER(ctypes.c_double)()
     assert lib.hotrg_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_qchain_parameters(lib):
+    from paper_2602_05900_amd import binding, workloads
+    h = workloads.heisenberg_bond()
+    assert binding.workspace_bytes(model="qchain", dmax=16, bond_h=h, tau=0.05, max_steps=20) > 0
+    assert binding.workspace_bytes(model="qchain", dmax=16, bond_h=h, tau=0.0, max_steps=20) == 0
+    bad = h.copy()
+    bad[0, 1] = 1.0                                   # not symmetric
+    assert binding.workspace_bytes(model="qchain", dmax=16, bond_h=bad, tau=0.05) == 0
+    assert lib.hotrg_coarse_grain_axis(None, 1, 0) == binding.EINVAL
+    v = ctypes.c_double()
+    assert lib.hotrg_log_z_chain(None, ctypes.byref(v)) == binding.EINVAL
 
 
 def test_itebd_sizes_and_error_paths(lib):

@@ -1,0 +1,109 @@
+"""GPU parity of the quantum-chain path (HOTRG_QCHAIN, steps without the
+x/y exchange, hotrg_log_z_chain) against the FP64 oracle and exact results.
+
+FP64 bars: exact tori to 1e-12 relative; a random tensor under a mixed
+schedule to 1e-12 relative.  The imaginary-time steps of a quantum chain
+are held to 1e-9 relative on ln Z per tensor (so on f): while 2^n tau is
+small the evolution operator has fewer than D significant singular values,
+the early cuts fall inside the rounding noise (relative gaps 1e-19 to 1e-24
+at the cut, measured with the oracle), and which noise directions are kept
+is not unique; the kept noise still moves ln Z per tensor (~2 tau |f|,
+O(tau)) at the 1e-12 level.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact, hotrg, itebd, qchain
+from paper_2602_05900_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def solve(h, tau, dmax, **kw):
+    from paper_2602_05900_amd import binding
+    return binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=dmax, **kw)
+
+
+@pytest.mark.parametrize("model", ["heisenberg", "tfim"])
+@pytest.mark.parametrize("sched", [[True], [False], [True, False], [True, True]])
+def test_exact_tori(gpu_lib, model, sched):
+    """No truncation (every step keeps D' = Dx^2 = 16 states): ln Z of the
+    torus the schedule covers is the Trotterized ring's, by exact
+    diagonalisation."""
+    h = workloads.heisenberg_bond() if model == "heisenberg" else workloads.ising_transverse_bond(1.5)
+    tau = 0.1
+    s = solve(h, tau, 16, max_steps=4)
+    for e in sched:
+        s.coarse_grain(1, exchange=e)
+    Lx, Ly, sw = 1, 1, False
+    for e in sched:
+        if sw:
+            Lx *= 2
+        else:
+            Ly *= 2
+        if e:
+            sw = not sw
+    want = exact.trotter_ring_lnz(h, tau, 2 * Lx, Ly)
+    assert abs(s.log_z() * 2 ** len(sched) - want) < 1e-12 * abs(want)
+
+
+def test_random_tensor_schedule_parity(gpu_lib):
+    from paper_2602_05900_amd import binding
+    T = np.random.default_rng(4).uniform(0.0, 1.0, (4, 4, 4, 4))
+    sched = [False, False, True, False, False, True, True, False]
+    ref = hotrg.solve_tensor(T, 8, len(sched), keep_tensor=False, schedule=sched)
+    s = binding.Solve(model="custom", tensor=T, dmax=8)
+    for e in sched:
+        s.coarse_grain(1, exchange=e)
+    assert abs(s.log_z() - ref.lnz_per_site) <= 1e-12 * abs(ref.lnz_per_site)
+
+
+@pytest.mark.parametrize("T,k,D", [(1.0, 8, 16), (0.5, 10, 16), (0.25, 10, 24)])
+def test_tfim_finite_temperature_parity_and_exactness(gpu_lib, T, k, D):
+    h = workloads.ising_transverse_bond(1.5)
+    tau = (1.0 / T) / 2 ** k
+    ref = qchain.chain_lnz(qchain.block_tensor(h, tau), D, k)
+    s = solve(h, tau, D, max_steps=k)
+    s.coarse_grain(k, exchange=False)
+    got = s.log_z_chain()
+    assert abs(got - ref) <= 1e-9 * abs(ref)
+    f = -got / (2.0 * tau)
+    assert abs(f - exact.tfim_free_energy(1.5, T)) < 2e-5
+
+
+def test_heisenberg_limits(gpu_lib):
+    h = workloads.heisenberg_bond()
+    T = 20.0
+    s = solve(h, (1.0 / T) / 2 ** 8, 16, max_steps=8)
+    s.coarse_grain(8, exchange=False)
+    f = -s.log_z_chain() / (2.0 * s.tau)
+    assert abs(f - (-T * math.log(2.0) - 3.0 / (32.0 * T))) < 1e-4
+    s = solve(h, 0.05, 16, max_steps=14)
+    s.coarse_grain(14, exchange=False)
+    f = -s.log_z_chain() / (2.0 * 0.05)
+    assert 0.0 < f - itebd.BETHE_HEISENBERG < 2.5e-3
+    # SU(2) multiplets of the Heisenberg chain straddle the cuts, so the kept
+    # subspace is not unique: GPU and oracle are two valid truncations that
+    # agree to the truncation error (measured 1e-5 here), not to rounding
+    ref = qchain.free_energy(h, 0.05, 16, 14)
+    assert abs(f - ref) < 1e-4
+
+
+@pytest.mark.parametrize("precision", ["bf16x6", "fp32"])
+def test_reduced_precision_quantum_chain(gpu_lib, precision):
+    """Steady dims (48, 4) in the split formats (panel operands with four
+    time states) against the FP64 path.  At tau ~ 1e-3 the tensors are
+    O(1) (G ~ 1 - tau h) while the free energy lives in their O(tau) part,
+    so a resolution of ~1e-7 of max|T| (BF16x6, FP32) becomes ~1e-4 of f
+    (measured 9e-5 for BF16x6): the reduced precisions do not suit small
+    Trotter steps; an indexing or layout mistake would move ln Z by O(1)."""
+    h = workloads.heisenberg_bond()
+    tau = 1.0 / 2 ** 10
+    a = solve(h, tau, 48, max_steps=10)
+    a.coarse_grain(10, exchange=False)
+    b = solve(h, tau, 48, max_steps=10, precision=precision)
+    b.coarse_grain(10, exchange=False)
+    ra, rb = a.log_z_chain(), b.log_z_chain()
+    assert abs(rb - ra) < 5e-4 * abs(ra)
