@@ -240,6 +240,52 @@ def run_itebd(binding, workloads):
     return out
 
 
+def run_qchain(binding, workloads):
+    """HOTRG of the S = 1/2 antiferromagnetic Heisenberg chain mapped onto an
+    imaginary-time network (the paper's HOTRG workload), FP64: time per
+    coarse-graining step against D_b (12 steps along imaginary time,
+    beta = 1, tau = 2^-12) with the fitted exponent of time ~ D_b^x, and the
+    free energy per site at several temperatures (D_b = 32)."""
+    import math
+    import numpy as np
+    import torch
+    h = workloads.heisenberg_bond()
+    out = {"workload": "S=1/2 AF Heisenberg chain, Trotter step tau = beta / 2^k, k steps along imaginary "
+                       "time, then the infinite chain (dominant eigenvalue of the column transfer matrix), FP64"}
+    k = 12
+    tau = 1.0 / 2 ** k
+    rows = []
+    for d in (4, 8, 16, 24, 32, 48):
+        s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=d, max_steps=k)
+        s.coarse_grain(k, exchange=False)
+        s.log_z_chain()
+        s.reset(model="qchain", bond_h=h, tau=tau, dmax=d, max_steps=k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.coarse_grain(k, exchange=False)
+        s.log_z_chain()
+        dt = time.perf_counter() - t0
+        rows.append((d, dt / k * 1e3))
+        s.close()
+    x = np.polyfit(np.log([r[0] for r in rows[1:]]), np.log([r[1] for r in rows[1:]]), 1)[0]
+    out["ms_per_step"] = {str(d): t for d, t in rows}
+    out["fit_exponent_d8_to_d48"] = float(x)
+    fe = {}
+    for temp in (2.0, 1.0, 0.5, 0.25):
+        tau_t = (1.0 / temp) / 2 ** k
+        s = binding.Solve(model="qchain", bond_h=h, tau=tau_t, dmax=32, max_steps=k)
+        s.coarse_grain(k, exchange=False)
+        fe[str(temp)] = -s.log_z_chain() / (2.0 * tau_t)
+        s.close()
+    s = binding.Solve(model="qchain", bond_h=h, tau=0.05, dmax=32, max_steps=14)
+    s.coarse_grain(14, exchange=False)
+    e_low = -s.log_z_chain() / 0.1
+    s.close()
+    out["free_energy_d32"] = fe
+    out["beta_819_d32"] = {"free_energy": e_low, "minus_bethe": e_low - (0.25 - math.log(2.0))}
+    return out
+
+
 def run_c5(binding, accounting):
     """Ising at Tc, D = 64, 40 steps, one solve in BF16x6 and one in FP64 on
     the same GPU: throughput and |delta f| between them and against Onsager."""
@@ -312,6 +358,7 @@ def main():
     ap.add_argument("--no-observables", dest="observables", action="store_false",
                     help="skip the two-sided / impurity-observable runs")
     ap.add_argument("--no-itebd", dest="itebd", action="store_false", help="skip the iTEBD runs")
+    ap.add_argument("--no-qchain", dest="qchain", action="store_false", help="skip the quantum-chain HOTRG runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -460,6 +507,10 @@ def main():
         print("# iTEBD: Heisenberg chains ...", file=sys.stderr, flush=True)
         from paper_2602_05900_amd import workloads as wl
         line["itebd"] = run_itebd(binding, wl)
+    if args.qchain:
+        print("# quantum chain HOTRG ...", file=sys.stderr, flush=True)
+        from paper_2602_05900_amd import workloads as wl
+        line["qchain"] = run_qchain(binding, wl)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))

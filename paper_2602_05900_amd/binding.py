@@ -232,10 +232,12 @@ class Solve:
 
     def reset(self, model: str = "ising", q: int = 2, temperature: float = 2.0, dmax: int = 8,
               precision: str = "fp64", coupling: float = 1.0, tensor=None, max_steps: int = 0,
-              field: float = 0.0, two_sided: bool = False, observables=(), impurities=None) -> "Solve":
+              field: float = 0.0, two_sided: bool = False, observables=(), impurities=None,
+              bond_h=None, tau: float = 0.0) -> "Solve":
         """Restart this handle (same workspace, stream and eigensolver context)."""
         p, keep = make_params(model, q, temperature, dmax, precision, coupling, tensor, max_steps,
-                              field, two_sided, observables, impurities)
+                              field, two_sided, observables, impurities, bond_h, tau)
+        self.tau = tau
         _check(self._lib.hotrg_reset(self._h, ctypes.byref(p)), "hotrg_reset")
         del keep
         self.temperature = temperature
