@@ -83,6 +83,13 @@ int itebd_copy_states(itebd_batch* b, double* host, size_t capacity);
  * needed in the last launch (synchronises).  Either pointer may be NULL. */
 int itebd_info(itebd_batch* b, long* updates, int* max_sweeps);
 
+/* Work done so far, summed over the chains (synchronises): Jacobi sweeps
+ * and pair rotations applied.  One sweep over n = 2 chi columns forms the
+ * three dot products of every pair (n (n - 1) / 2 pairs, 6 n FLOPs each);
+ * a rotation updates two columns of M and of V (12 n FLOPs).  Either
+ * pointer may be NULL. */
+int itebd_work(itebd_batch* b, double* sweeps, double* rotations);
+
 /* Releases the host handle (waits for the stream first).  NULL is a no-op. */
 void itebd_destroy(itebd_batch* b);
 

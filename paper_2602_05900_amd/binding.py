@@ -35,7 +35,7 @@ EXPORTS = [
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
     "itebd_state_len", "itebd_workspace_bytes", "itebd_init", "itebd_evolve", "itebd_energy",
-    "itebd_copy_states", "itebd_info", "itebd_destroy",
+    "itebd_copy_states", "itebd_info", "itebd_work", "itebd_destroy",
 ]
 ITEBD_MAX_CHI = 32
 
@@ -118,6 +118,7 @@ def load() -> ctypes.CDLL:
     lib.itebd_energy.argtypes = [c_void_p, P(c_double)]
     lib.itebd_copy_states.argtypes = [c_void_p, P(c_double), c_size_t]
     lib.itebd_info.argtypes = [c_void_p, P(ctypes.c_long), P(c_int)]
+    lib.itebd_work.argtypes = [c_void_p, P(c_double), P(c_double)]
     lib.itebd_destroy.argtypes = [c_void_p]
     lib.itebd_destroy.restype = None
     for name in EXPORTS:
@@ -370,6 +371,12 @@ class Chains:
         u, m = ctypes.c_long(), ctypes.c_int()
         _check(self._lib.itebd_info(self._h, ctypes.byref(u), ctypes.byref(m)), "itebd_info")
         return u.value, m.value
+
+    def work(self):
+        """(Jacobi sweeps, pair rotations) summed over the chains so far."""
+        sw, rot = ctypes.c_double(), ctypes.c_double()
+        _check(self._lib.itebd_work(self._h, ctypes.byref(sw), ctypes.byref(rot)), "itebd_work")
+        return sw.value, rot.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,81 @@
+"""Stand-alone runs of the two chain workloads (for profiling and quick
+measurements), one JSON line each:
+
+    python -m paper_2602_05900_amd.chain_bench --what itebd  [--chains 256 --chi 30 --updates 2000]
+    python -m paper_2602_05900_amd.chain_bench --what qchain [--dmax 32 --steps 12]
+
+itebd: a batch of S = 1/2 antiferromagnetic Heisenberg chains from random
+states, FP64 (include/itebd.h); qchain: the same chain's free energy at
+beta = 1 by HOTRG along imaginary time (HOTRG_QCHAIN).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import torch
+
+from . import binding, workloads
+
+
+def itebd_flops(chi: int, updates: float, sweeps: float, rotations: float) -> float:
+    """FLOPs the device performs (see itebd_work): per update the contraction
+    (2 n^2 chi), the gate (32 chi^2), the warm-start product (2 n^3), the
+    singular values (2 n^2) and B1' (4 n chi^2); per sweep the pair dot
+    products (3 n^2 (n - 1)); per rotation 12 n; n = 2 chi."""
+    n = 2 * chi
+    per_update = 2 * n * n * chi + 32 * chi * chi + 2 * n ** 3 + 2 * n * n + 4 * n * chi * chi
+    return updates * per_update + sweeps * 3 * n * n * (n - 1) + rotations * 12 * n
+
+
+def run_itebd(chains: int, chi: int, updates: int, tau: float = 0.01) -> dict:
+    h = workloads.heisenberg_bond()
+    c = binding.Chains(h, workloads.random_chain_states(chains, chi, seed=2026), chi)
+    c.evolve(0.1, 200)
+    c.energies()
+    sw0, rot0 = c.work()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.evolve(tau, updates)
+    e = c.energies()
+    dt = time.perf_counter() - t0
+    sw1, rot1 = c.work()
+    flops = itebd_flops(chi, chains * updates, sw1 - sw0, rot1 - rot0)
+    c.close()
+    return {"chains": chains, "chi": chi, "bond_updates_per_chain": updates, "seconds": dt,
+            "updates_per_s": chains * updates / dt, "us_per_update_per_chain": dt / updates * 1e6,
+            "mean_jacobi_sweeps": (sw1 - sw0) / (chains * updates), "achieved_tflops": flops / dt / 1e12,
+            "energy_mean": float(e.mean()), "energy_minus_bethe_max": float(e.max() - (0.25 - math.log(2.0)))}
+
+
+def run_qchain(dmax: int, steps: int, temperature: float = 1.0) -> dict:
+    h = workloads.heisenberg_bond()
+    tau = (1.0 / temperature) / 2 ** steps
+    s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=dmax, max_steps=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.coarse_grain(steps, exchange=False)
+    f = -s.log_z_chain() / (2.0 * tau)
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"dmax": dmax, "steps": steps, "temperature": temperature, "seconds": dt,
+            "ms_per_step": dt / steps * 1e3, "free_energy": f}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--what", choices=("itebd", "qchain"), required=True)
+    ap.add_argument("--chains", type=int, default=256)
+    ap.add_argument("--chi", type=int, default=30)
+    ap.add_argument("--updates", type=int, default=2000)
+    ap.add_argument("--dmax", type=int, default=32)
+    ap.add_argument("--steps", type=int, default=12)
+    a = ap.parse_args()
+    out = run_itebd(a.chains, a.chi, a.updates) if a.what == "itebd" else run_qchain(a.dmax, a.steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

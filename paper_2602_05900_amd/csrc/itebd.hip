@@ -14,9 +14,17 @@
 //   exchange the sites' roles
 // The Jacobi sweep visits all column pairs in n - 1 rounds of n/2 disjoint
 // pairs (round-robin ordering, the systolic schedule of Sec. II.B used for
-// one-sided rotations); eight lanes own a pair: they form the three dot
-// products over their rows, reduce them with butterfly shuffles (every lane
-// gets the same bits), and rotate their rows of W and V.
+// one-sided rotations); sixteen lanes own a pair: they hold the pair's two
+// columns of W and of V in registers (rows l, l + 16, ...), form the three
+// dot products, reduce them over the sixteen lanes with DPP moves (every
+// lane gets the same bits: each stage adds two equal partial sums in either
+// order), and rotate their rows of W and V.  With 512 threads two waves share
+// each SIMD, so one wave's dependent FP64 chain (square roots, division)
+// overlaps the other's.  W and V are kept column-major with a column stride
+// ld = 8 (mod 32) doubles: the four pairs of a wave (consecutive column
+// indices) read 16 consecutive doubles each, starting 8 doubles apart in the
+// 32 double-wide banks, which covers every bank exactly twice (the least a
+// 64-lane 8-byte read can take).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -31,7 +39,13 @@ namespace {
 
 constexpr int kMaxChi = ITEBD_MAX_CHI;
 constexpr int kMaxN = 2 * kMaxChi;
-constexpr int kThreads = 256;
+// column stride of W and V: the smallest ld >= n with ld = 8 (mod 32)
+__host__ __device__ constexpr int col_stride(int n) { return ((n + 23) / 32) * 32 + 8; }
+constexpr int kMaxLd = col_stride(kMaxN);
+constexpr int kLanesPerPair = 16;
+constexpr int kRowsPerLane = kMaxN / kLanesPerPair;
+constexpr int kThreads = 256;                       // energy kernel
+constexpr int kUpdThreads = kLanesPerPair * kMaxN / 2;   // update kernel: one lane group per pair
 constexpr int kUpdatesPerLaunch = 32;
 constexpr int kMaxSweeps = 40;
 #ifndef ITEBD_TOL
@@ -48,49 +62,73 @@ struct Gate {
     double g[16];   // exp(-tau h), row-major [(s' t'), (s t)]
 };
 
-__device__ __forceinline__ double shfl_xor_d(double v, int mask) { return __shfl_xor(v, mask); }
+// a double from another lane of the same row through a DPP move of each half
+template <int Ctrl>
+__device__ __forceinline__ double dpp_d(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, Ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), Ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
 
-__global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restrict__ states,
+// sum over an aligned row of sixteen lanes: partner lane ^1 (quad_perm
+// [1,0,3,2]), ^2 (quad_perm [2,3,0,1]), the mirror lane 7 - l inside the
+// half-row (the other quad), then the mirror lane 15 - l inside the row (the
+// other half-row)
+__device__ __forceinline__ double sum16(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return v;
+}
+
+__global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __restrict__ states,
                                                                 double* __restrict__ vprev,
-                                                                int* __restrict__ sweeps_out, int chi, Gate G,
-                                                                long base, int nupd)
+                                                                int* __restrict__ sweeps_out,
+                                                                unsigned long long* __restrict__ work, int chi,
+                                                                Gate G, long base, int nupd)
 {
     __shared__ double sB1[2 * kMaxChi * kMaxChi];
     __shared__ double sB2[2 * kMaxChi * kMaxChi];
     __shared__ double sP[kMaxN * kMaxN];
-    __shared__ double sW[kMaxN * kMaxN];
-    __shared__ double sV[kMaxN * kMaxN];
+    __shared__ double sW[kMaxN * kMaxLd];   // column-major, stride ld
+    __shared__ double sV[kMaxN * kMaxLd];
     __shared__ double sl1[kMaxChi], sl2[kMaxChi];
     __shared__ double ssig[kMaxN], ssgn[kMaxChi];
     __shared__ int sord[kMaxChi];
     __shared__ int srot;
+    __shared__ unsigned int srotc;   // rotations applied in this update
     __shared__ double snrm;
 
     const int tid = threadIdx.x;
     const int n = 2 * chi;
+    const int ld = col_stride(n);
     const int nb = 2 * chi * chi;
     const long len = 2L * nb + 2 * chi;
     double* st = states + (long)blockIdx.x * len;
     double* vp = vprev + (long)blockIdx.x * 2 * n * n;
 
-    for (int i = tid; i < nb; i += kThreads) {
+    for (int i = tid; i < nb; i += kUpdThreads) {
         sB1[i] = st[i];
         sB2[i] = st[nb + i];
     }
-    for (int i = tid; i < chi; i += kThreads) {
+    for (int i = tid; i < chi; i += kUpdThreads) {
         sl1[i] = st[2 * nb + i];
         sl2[i] = st[2 * nb + chi + i];
     }
     __syncthreads();
 
     int max_sweeps = 0;
+    unsigned long long tot_sweeps = 0, tot_rot = 0;
     for (int u = 0; u < nupd; ++u) {
+        if (tid == 0) srotc = 0;
         const long count = base + u;
         const int par = (int)(count & 1);
         const bool warm = count >= 2;
 
         // contraction P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b]
-        for (int idx = tid; idx < n * n; idx += kThreads) {
+        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
             const int r = idx / n, k = idx - (idx / n) * n;
             const int a = r >> 1, s = r & 1, t = k / chi, b = k - (k / chi) * chi;
             const double* x = sB1 + (s * chi + a) * chi;
@@ -101,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
         }
         __syncthreads();
         // gate on the physical pair of every (a, b)
-        for (int idx = tid; idx < chi * chi; idx += kThreads) {
+        for (int idx = tid; idx < chi * chi; idx += kUpdThreads) {
             const int a = idx / chi, b = idx - (idx / chi) * chi;
             double v[4], w[4];
             for (int s = 0; s < 2; ++s)
@@ -115,23 +153,24 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
                 for (int t = 0; t < 2; ++t) sP[(2 * a + s) * n + t * chi + b] = w[2 * s + t];
         }
         // starting right basis: the same bond's vectors of two updates ago, or 1
+        // (stored column-major, n x n)
         double* vpar = vp + (long)par * n * n;
-        for (int idx = tid; idx < n * n; idx += kThreads) {
-            const int i = idx / n, j = idx - (idx / n) * n;
-            sV[idx] = warm ? vpar[idx] : (i == j ? 1.0 : 0.0);
+        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
+            const int j = idx / n, i = idx - (idx / n) * n;
+            sV[j * ld + i] = warm ? vpar[idx] : (i == j ? 1.0 : 0.0);
         }
         __syncthreads();
         // W = diag(lambda_2 (x) 1) P V
-        for (int idx = tid; idx < n * n; idx += kThreads) {
-            const int r = idx / n, j = idx - (idx / n) * n;
+        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
+            const int j = idx / n, r = idx - (idx / n) * n;
             double acc;
             if (warm) {
                 acc = 0.0;
-                for (int k = 0; k < n; ++k) acc = fma(sP[r * n + k], sV[k * n + j], acc);
+                for (int k = 0; k < n; ++k) acc = fma(sP[r * n + k], sV[j * ld + k], acc);
             } else {
-                acc = sP[idx];
+                acc = sP[r * n + j];
             }
-            sW[idx] = sl2[r >> 1] * acc;
+            sW[j * ld + r] = sl2[r >> 1] * acc;
         }
         __syncthreads();
 
@@ -139,9 +178,10 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
         double fro2 = 0.0;
         if (ITEBD_ABS) {
             // |W|_F^2 (invariant under the rotations): every thread sums the same terms in the same order
-            for (int i = 0; i < n * n; ++i) fro2 = fma(sW[i], sW[i], fro2);
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) fro2 = fma(sW[j * ld + i], sW[j * ld + i], fro2);
         }
-        const int g = tid >> 3, l8 = tid & 7;
+        const int g = tid / kLanesPerPair, lane = tid % kLanesPerPair;
         const int npair = n >> 1;
         int sweeps = kMaxSweeps;
         for (int sw = 0; sw < kMaxSweeps; ++sw) {
@@ -153,36 +193,62 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
                     if (g == 0) {
                         p = rd;
                         q = n - 1;
-                    } else {
-                        p = (rd + g) % (n - 1);
-                        q = (rd - g + n - 1) % (n - 1);
+                    } else {   // (rd + g) and (rd - g) modulo n - 1, with 1 <= g < n - 1
+                        p = rd + g;
+                        p -= p >= n - 1 ? n - 1 : 0;
+                        q = rd - g;
+                        q += q < 0 ? n - 1 : 0;
                     }
+                    double* Wp = sW + p * ld;
+                    double* Wq = sW + q * ld;
+                    double* Vp = sV + p * ld;
+                    double* Vq = sV + q * ld;
+                    // both columns of W and of V in registers: the V loads are in
+                    // flight while the dot products and the rotation are formed
+                    double wp[kRowsPerLane], wq[kRowsPerLane], vpr[kRowsPerLane], vqr[kRowsPerLane];
                     double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int i = l8; i < n; i += 8) {
-                        const double wp = sW[i * n + p], wq = sW[i * n + q];
-                        al = fma(wp, wp, al);
-                        be = fma(wq, wq, be);
-                        ga = fma(wp, wq, ga);
+#pragma unroll
+                    for (int r = 0; r < kRowsPerLane; ++r) {
+                        const int i = lane + kLanesPerPair * r;
+                        wp[r] = i < n ? Wp[i] : 0.0;
+                        wq[r] = i < n ? Wq[i] : 0.0;
                     }
-                    for (int off = 4; off > 0; off >>= 1) {
-                        al += shfl_xor_d(al, off);
-                        be += shfl_xor_d(be, off);
-                        ga += shfl_xor_d(ga, off);
+#pragma unroll
+                    for (int r = 0; r < kRowsPerLane; ++r) {
+                        const int i = lane + kLanesPerPair * r;
+                        vpr[r] = i < n ? Vp[i] : 0.0;
+                        vqr[r] = i < n ? Vq[i] : 0.0;
                     }
-                    if (fabs(ga) > kTol * (ITEBD_ABS ? fro2 : sqrt(al * be))) {
-                        const double z = (be - al) / (2.0 * ga);
-                        const double t = fabs(z) > 1e150 ? 0.5 / z
-                                                         : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z));
-                        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                        for (int i = l8; i < n; i += 8) {
-                            const double wp = sW[i * n + p], wq = sW[i * n + q];
-                            sW[i * n + p] = c * wp - s * wq;
-                            sW[i * n + q] = s * wp + c * wq;
-                            const double vp_ = sV[i * n + p], vq = sV[i * n + q];
-                            sV[i * n + p] = c * vp_ - s * vq;
-                            sV[i * n + q] = s * vp_ + c * vq;
+#pragma unroll
+                    for (int r = 0; r < kRowsPerLane; ++r) {
+                        al = fma(wp[r], wp[r], al);
+                        be = fma(wq[r], wq[r], be);
+                        ga = fma(wp[r], wq[r], ga);
+                    }
+                    al = sum16(al);
+                    be = sum16(be);
+                    ga = sum16(ga);
+                    // rotate while ga^2 > kTol^2 al be (relative test) or |ga| > kTol |W|_F^2
+                    if (ITEBD_ABS ? fabs(ga) > kTol * fro2 : ga * ga > (kTol * kTol) * (al * be)) {
+                        // the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga):
+                        // t = sign(d) 2ga / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al
+                        const double d = be - al, g2 = 2.0 * ga;
+                        const double t = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
+                        const double c = rsqrt(fma(t, t, 1.0)), s = c * t;
+#pragma unroll
+                        for (int r = 0; r < kRowsPerLane; ++r) {
+                            const int i = lane + kLanesPerPair * r;
+                            if (i < n) {
+                                Wp[i] = c * wp[r] - s * wq[r];
+                                Wq[i] = s * wp[r] + c * wq[r];
+                                Vp[i] = c * vpr[r] - s * vqr[r];
+                                Vq[i] = s * vpr[r] + c * vqr[r];
+                            }
                         }
-                        if (l8 == 0) srot = 1;
+                        if (lane == 0) {
+                            srot = 1;
+                            atomicAdd(&srotc, 1u);
+                        }
                     }
                 }
                 __syncthreads();
@@ -195,33 +261,35 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
             }
         }
         max_sweeps = max(max_sweeps, sweeps);
+        tot_sweeps += (unsigned long long)sweeps;
+        tot_rot += (unsigned long long)srotc;   // read after the sweeps' barriers
 
         // singular values, the chi largest (ties: lower column first)
-        for (int j = tid; j < n; j += kThreads) {
+        for (int j = tid; j < n; j += kUpdThreads) {
             double acc = 0.0;
-            for (int i = 0; i < n; ++i) acc = fma(sW[i * n + j], sW[i * n + j], acc);
+            for (int i = 0; i < n; ++i) acc = fma(sW[j * ld + i], sW[j * ld + i], acc);
             ssig[j] = sqrt(acc);
         }
         __syncthreads();
-        for (int j = tid; j < n; j += kThreads) {
+        for (int j = tid; j < n; j += kUpdThreads) {
             int rank = 0;
             for (int i = 0; i < n; ++i) rank += (ssig[i] > ssig[j]) || (ssig[i] == ssig[j] && i < j);
             if (rank < chi) sord[rank] = j;
         }
         __syncthreads();
         // sign gauge of the kept right vectors; norm of the kept values
-        for (int c = tid; c < chi; c += kThreads) {
+        for (int c = tid; c < chi; c += kUpdThreads) {
             const int j = sord[c];
             double best = -1.0;
             int bi = 0;
             for (int i = 0; i < n; ++i) {
-                const double a = fabs(sV[i * n + j]);
+                const double a = fabs(sV[j * ld + i]);
                 if (a > best) {
                     best = a;
                     bi = i;
                 }
             }
-            ssgn[c] = sV[bi * n + j] < 0.0 ? -1.0 : 1.0;
+            ssgn[c] = sV[j * ld + bi] < 0.0 ? -1.0 : 1.0;
         }
         if (tid == 0) {
             double acc = 0.0;
@@ -229,24 +297,27 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
             snrm = sqrt(acc);
         }
         // the bond's right vectors for the next warm start
-        for (int idx = tid; idx < n * n; idx += kThreads) vpar[idx] = sV[idx];
+        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
+            const int j = idx / n, i = idx - (idx / n) * n;
+            vpar[idx] = sV[j * ld + i];
+        }
         __syncthreads();
         // new tensors, roles exchanged: B1 <- B2' = V_kept^T, B2 <- B1' = P V_kept / nrm
         const double inv = 1.0 / snrm;
-        for (int idx = tid; idx < nb; idx += kThreads) {
+        for (int idx = tid; idx < nb; idx += kUpdThreads) {
             const int t = idx / (chi * chi), rem = idx - t * chi * chi;
             const int c = rem / chi, b = rem - (rem / chi) * chi;
-            sB1[idx] = ssgn[c] * sV[(t * chi + b) * n + sord[c]];
+            sB1[idx] = ssgn[c] * sV[sord[c] * ld + t * chi + b];
         }
-        for (int idx = tid; idx < nb; idx += kThreads) {
+        for (int idx = tid; idx < nb; idx += kUpdThreads) {
             const int s = idx / (chi * chi), rem = idx - s * chi * chi;
             const int a = rem / chi, c = rem - (rem / chi) * chi;
             const int j = sord[c];
             double acc = 0.0;
-            for (int k = 0; k < n; ++k) acc = fma(sP[(2 * a + s) * n + k], sV[k * n + j], acc);
+            for (int k = 0; k < n; ++k) acc = fma(sP[(2 * a + s) * n + k], sV[j * ld + k], acc);
             sB2[idx] = ssgn[c] * inv * acc;
         }
-        for (int c = tid; c < chi; c += kThreads) {
+        for (int c = tid; c < chi; c += kUpdThreads) {
             const double old = sl2[c];
             sl2[c] = ssig[sord[c]] * inv;
             sl1[c] = old;
@@ -254,15 +325,19 @@ __global__ __launch_bounds__(kThreads) void itebd_update_kernel(double* __restri
         __syncthreads();
     }
 
-    for (int i = tid; i < nb; i += kThreads) {
+    for (int i = tid; i < nb; i += kUpdThreads) {
         st[i] = sB1[i];
         st[nb + i] = sB2[i];
     }
-    for (int i = tid; i < chi; i += kThreads) {
+    for (int i = tid; i < chi; i += kUpdThreads) {
         st[2 * nb + i] = sl1[i];
         st[2 * nb + chi + i] = sl2[i];
     }
-    if (tid == 0) sweeps_out[blockIdx.x] = max_sweeps;
+    if (tid == 0) {
+        sweeps_out[blockIdx.x] = max_sweeps;
+        work[2 * blockIdx.x] += tot_sweeps;
+        work[2 * blockIdx.x + 1] += tot_rot;
+    }
 }
 
 // Energy per site of every chain: <h> on bond (B1, B2) weighted by lambda_2
@@ -322,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void itebd_energy_kernel(const double* __
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t states, vprev, sweeps, energies, total;
+    size_t states, vprev, sweeps, work, energies, total;
 };
 
 Layout plan(int batch, int chi) {
@@ -336,6 +411,8 @@ Layout plan(int batch, int chi) {
     o = round_up(o + 8 * 2 * n * n * batch, 256);
     L.sweeps = o;
     o = round_up(o + 4 * (size_t)batch, 256);
+    L.work = o;
+    o = round_up(o + 16 * (size_t)batch, 256);
     L.energies = o;
     o = round_up(o + 8 * (size_t)batch, 256);
     L.total = o;
@@ -437,6 +514,7 @@ int itebd_init(int batch, int chi, const double* h, const double* states, void* 
     const size_t bytes = 8 * itebd_state_len(chi) * (size_t)batch;
     if (hipMemcpyAsync(b->states(), states, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipMemsetAsync(b->ws + L.sweeps, 0, 4 * (size_t)batch, b->stream) != hipSuccess ||
+        hipMemsetAsync(b->ws + L.work, 0, 16 * (size_t)batch, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         delete b;
         return HOTRG_EHIP;
@@ -451,10 +529,11 @@ int itebd_evolve(itebd_batch* b, double tau, int nupdates) {
     const Gate G = gate_of(b->h, tau);
     double* vprev = reinterpret_cast<double*>(b->ws + b->L.vprev);
     int* sweeps = reinterpret_cast<int*>(b->ws + b->L.sweeps);
+    unsigned long long* work = reinterpret_cast<unsigned long long*>(b->ws + b->L.work);
     for (int done = 0; done < nupdates;) {
         const int k = std::min(kUpdatesPerLaunch, nupdates - done);
-        hipLaunchKernelGGL(itebd_update_kernel, dim3((unsigned)b->batch), dim3(kThreads), 0, b->stream, b->states(),
-                           vprev, sweeps, b->chi, G, b->updates, k);
+        hipLaunchKernelGGL(itebd_update_kernel, dim3((unsigned)b->batch), dim3(kUpdThreads), 0, b->stream, b->states(),
+                           vprev, sweeps, work, b->chi, G, b->updates, k);
         if (hipGetLastError() != hipSuccess) {
             b->host_status = HOTRG_EHIP;
             return HOTRG_EHIP;
@@ -487,6 +566,25 @@ int itebd_copy_states(itebd_batch* b, double* host, size_t capacity) {
     if (hipMemcpyAsync(host, b->states(), 8 * count, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return HOTRG_EHIP;
+    return HOTRG_OK;
+}
+
+int itebd_work(itebd_batch* b, double* sweeps, double* rotations) {
+    if (!b) return HOTRG_EINVAL;
+    unsigned long long* host = new (std::nothrow) unsigned long long[2 * (size_t)b->batch];
+    if (!host) return HOTRG_EINVAL;
+    const bool ok = hipMemcpyAsync(host, b->ws + b->L.work, 16 * (size_t)b->batch, hipMemcpyDeviceToHost,
+                                   b->stream) == hipSuccess &&
+                    hipStreamSynchronize(b->stream) == hipSuccess;
+    double sw = 0.0, rot = 0.0;
+    for (int i = 0; ok && i < b->batch; ++i) {
+        sw += (double)host[2 * i];
+        rot += (double)host[2 * i + 1];
+    }
+    delete[] host;
+    if (!ok) return HOTRG_EHIP;
+    if (sweeps) *sweeps = sw;
+    if (rotations) *rotations = rot;
     return HOTRG_OK;
 }
 

@@ -96,3 +96,22 @@ def test_gpu_chains_approach_exact_energies(gpu_lib):
     h = workloads.heisenberg_bond()
     e = gpu_run(h, workloads.random_chain_states(4, 32, seed=2), 32, sched).energies()
     assert np.all(e > oracle.BETHE_HEISENBERG) and np.all(e - oracle.BETHE_HEISENBERG < 1.5e-3)
+
+
+def test_work_counters_are_consistent(gpu_lib):
+    """itebd_work: at least one Jacobi sweep per update and chain, at most
+    n (n - 1) / 2 rotations per sweep (n = 2 chi), monotone across launches."""
+    chi, batch = 8, 4
+    h = workloads.heisenberg_bond()
+    from paper_2602_05900_amd import binding
+    c = binding.Chains(h, workloads.random_chain_states(batch, chi, seed=31), chi)
+    assert c.work() == (0.0, 0.0)
+    c.evolve(0.05, 50)
+    sw1, rot1 = c.work()
+    c.evolve(0.05, 30)
+    sw2, rot2 = c.work()
+    n = 2 * chi
+    assert batch * 50 <= sw1 <= batch * 50 * 64 and 0 < rot1 <= sw1 * n * (n - 1) / 2
+    assert sw2 - sw1 >= batch * 30 and rot2 >= rot1
+    assert sw1 == int(sw1) and rot1 == int(rot1)
+    c.close()
