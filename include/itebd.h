@@ -20,13 +20,16 @@
  * of the same bond's previous update; the kept right vectors have their
  * largest-magnitude entry made positive.
  *
- * Device mapping: one workgroup per chain holds the whole unit cell, the
- * evolved pair and the Jacobi matrices in LDS (chi <= 32), so a launch runs
- * many updates of a chain without touching HBM; a batch fills the chip.
+ * Device mapping: one workgroup per chain keeps the Jacobi matrices (W, V)
+ * in LDS (chi <= 32); the unit cell and the evolved pair go through the
+ * chain's slice of the workspace, which stays in L2, and a launch runs many
+ * updates of a chain.  Two chains share a CU, so a batch of twice the CU
+ * count fills the chip.
  *
  * Status codes are those of hotrg.h.  The caller owns the device workspace
- * (itebd_workspace_bytes) and the stream; nothing is allocated on the device
- * by the library.  All arithmetic is FP64.
+ * (itebd_workspace_bytes: state rows, the evolved pair and two bonds' right
+ * vectors per chain, counters) and the stream; nothing is allocated on the
+ * device by the library.  All arithmetic is FP64.
  */
 #ifndef ITEBD_H
 #define ITEBD_H

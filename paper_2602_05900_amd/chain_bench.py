@@ -1,7 +1,7 @@
 """Stand-alone runs of the two chain workloads (for profiling and quick
 measurements), one JSON line each:
 
-    python -m paper_2602_05900_amd.chain_bench --what itebd  [--chains 256 --chi 30 --updates 2000]
+    python -m paper_2602_05900_amd.chain_bench --what itebd  [--chains 512 --chi 30 --updates 2000]
     python -m paper_2602_05900_amd.chain_bench --what qchain [--dmax 32 --steps 12]
 
 itebd: a batch of S = 1/2 antiferromagnetic Heisenberg chains from random
@@ -67,7 +67,7 @@ def run_qchain(dmax: int, steps: int, temperature: float = 1.0) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--what", choices=("itebd", "qchain"), required=True)
-    ap.add_argument("--chains", type=int, default=256)
+    ap.add_argument("--chains", type=int, default=512)
     ap.add_argument("--chi", type=int, default=30)
     ap.add_argument("--updates", type=int, default=2000)
     ap.add_argument("--dmax", type=int, default=32)

@@ -1,6 +1,10 @@
 // iTEBD on the device: many independent infinite chains, one workgroup per
-// chain, the whole two-site unit cell and the SVD work matrices in LDS, all
-// FP64.  The C ABI is declared in include/itebd.h.
+// chain, all FP64.  The SVD work matrices (W, V) live in LDS (75 KB, so two
+// chains share a CU); B1 and B2 are staged into LDS from the chain's state
+// row at the start of each update and written back at its end, and the
+// evolved pair P goes to the chain's workspace slice (column-major, read
+// row-parallel by the products W = P V and B1' = P V_kept, and small enough
+// to stay in L2).  The C ABI is declared in include/itebd.h.
 //
 // One bond update (Sec. II.A, Eq. (1); the inverse-free form of the iTEBD
 // update), n = 2 chi:
@@ -46,6 +50,9 @@ constexpr int kLanesPerPair = 16;
 constexpr int kRowsPerLane = kMaxN / kLanesPerPair;
 constexpr int kThreads = 256;                       // energy kernel
 constexpr int kUpdThreads = kLanesPerPair * kMaxN / 2;   // update kernel: one lane group per pair
+// row-parallel products (W = P V, B1' = P V_kept): kUpdThreads / n >= 8 groups
+// of n lanes, each lane one row and at most this many columns
+constexpr int kMaxColsPerLane = (kMaxN + 7) / 8;
 constexpr int kUpdatesPerLaunch = 32;
 constexpr int kMaxSweeps = 40;
 #ifndef ITEBD_TOL
@@ -83,17 +90,16 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __restrict__ states,
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4))) void itebd_update_kernel(double* __restrict__ states,
                                                                 double* __restrict__ vprev,
+                                                                double* __restrict__ pair,
                                                                 int* __restrict__ sweeps_out,
                                                                 unsigned long long* __restrict__ work, int chi,
                                                                 Gate G, long base, int nupd)
 {
-    __shared__ double sB1[2 * kMaxChi * kMaxChi];
-    __shared__ double sB2[2 * kMaxChi * kMaxChi];
-    __shared__ double sP[kMaxN * kMaxN];
+    // 75 KB in all, so two chains share a CU
     __shared__ double sW[kMaxN * kMaxLd];   // column-major, stride ld
-    __shared__ double sV[kMaxN * kMaxLd];
+    __shared__ double sV[kMaxN * kMaxLd];   // also stages B1 and B2 at the start of an update
     __shared__ double sl1[kMaxChi], sl2[kMaxChi];
     __shared__ double ssig[kMaxN], ssgn[kMaxChi];
     __shared__ int sord[kMaxChi];
@@ -106,13 +112,12 @@ __global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __res
     const int ld = col_stride(n);
     const int nb = 2 * chi * chi;
     const long len = 2L * nb + 2 * chi;
-    double* st = states + (long)blockIdx.x * len;
+    double* st = states + (long)blockIdx.x * len;        // B1 and B2 are rewritten every update
     double* vp = vprev + (long)blockIdx.x * 2 * n * n;
+    double* gP = pair + (long)blockIdx.x * n * n;        // P, column-major: P[(a s),(t b)] at (t b) n + (a s)
+    const int ng = kUpdThreads / n;                      // lane groups of the row-parallel products (>= 8)
+    const int prow = tid % n, pgrp = tid / n;
 
-    for (int i = tid; i < nb; i += kUpdThreads) {
-        sB1[i] = st[i];
-        sB2[i] = st[nb + i];
-    }
     for (int i = tid; i < chi; i += kUpdThreads) {
         sl1[i] = st[2 * nb + i];
         sl2[i] = st[2 * nb + chi + i];
@@ -127,31 +132,36 @@ __global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __res
         const int par = (int)(count & 1);
         const bool warm = count >= 2;
 
-        // contraction P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b]
-        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
-            const int r = idx / n, k = idx - (idx / n) * n;
-            const int a = r >> 1, s = r & 1, t = k / chi, b = k - (k / chi) * chi;
-            const double* x = sB1 + (s * chi + a) * chi;
-            const double* y = sB2 + t * chi * chi + b;
-            double acc = 0.0;
-            for (int c = 0; c < chi; ++c) acc = fma(x[c], y[c * chi], acc);
-            sP[idx] = acc;
+        // stage B1 and B2 in the V buffer
+        double* sB1 = sV;
+        double* sB2 = sV + nb;
+        for (int i = tid; i < nb; i += kUpdThreads) {
+            sB1[i] = st[i];
+            sB2[i] = st[nb + i];
         }
         __syncthreads();
-        // gate on the physical pair of every (a, b)
+        // contraction P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b] and the gate on the
+        // physical pair: one (a, b) per thread, its four (s, t)
         for (int idx = tid; idx < chi * chi; idx += kUpdThreads) {
             const int a = idx / chi, b = idx - (idx / chi) * chi;
-            double v[4], w[4];
+            double v[4];
             for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) v[2 * s + t] = sP[(2 * a + s) * n + t * chi + b];
-            for (int o = 0; o < 4; ++o) {
-                double acc = 0.0;
-                for (int i = 0; i < 4; ++i) acc = fma(G.g[4 * o + i], v[i], acc);
-                w[o] = acc;
-            }
+                for (int t = 0; t < 2; ++t) {
+                    const double* x = sB1 + (s * chi + a) * chi;
+                    const double* y = sB2 + t * chi * chi + b;
+                    double acc = 0.0;
+                    for (int c = 0; c < chi; ++c) acc = fma(x[c], y[c * chi], acc);
+                    v[2 * s + t] = acc;
+                }
             for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) sP[(2 * a + s) * n + t * chi + b] = w[2 * s + t];
+                for (int t = 0; t < 2; ++t) {
+                    const int o = 2 * s + t;
+                    double acc = 0.0;
+                    for (int i = 0; i < 4; ++i) acc = fma(G.g[4 * o + i], v[i], acc);
+                    gP[(t * chi + b) * n + 2 * a + s] = acc;
+                }
         }
+        __syncthreads();   // P complete; the staged B1, B2 are no longer needed
         // starting right basis: the same bond's vectors of two updates ago, or 1
         // (stored column-major, n x n)
         double* vpar = vp + (long)par * n * n;
@@ -160,17 +170,33 @@ __global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __res
             sV[j * ld + i] = warm ? vpar[idx] : (i == j ? 1.0 : 0.0);
         }
         __syncthreads();
-        // W = diag(lambda_2 (x) 1) P V
-        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
-            const int j = idx / n, r = idx - (idx / n) * n;
-            double acc;
+        // W = diag(lambda_2 (x) 1) P V: thread (row r, group g) forms columns g, g + ng, ...
+        if (pgrp < ng) {
+            double acc[kMaxColsPerLane];
+#pragma unroll
+            for (int q = 0; q < kMaxColsPerLane; ++q) acc[q] = 0.0;
             if (warm) {
-                acc = 0.0;
-                for (int k = 0; k < n; ++k) acc = fma(sP[r * n + k], sV[j * ld + k], acc);
+                for (int k = 0; k < n; ++k) {
+                    const double pk = gP[k * n + prow];
+#pragma unroll
+                    for (int q = 0; q < kMaxColsPerLane; ++q) {
+                        const int j = pgrp + q * ng;
+                        if (j < n) acc[q] = fma(pk, sV[j * ld + k], acc[q]);
+                    }
+                }
             } else {
-                acc = sP[r * n + j];
+#pragma unroll
+                for (int q = 0; q < kMaxColsPerLane; ++q) {
+                    const int j = pgrp + q * ng;
+                    if (j < n) acc[q] = gP[j * n + prow];
+                }
             }
-            sW[j * ld + r] = sl2[r >> 1] * acc;
+            const double lam = sl2[prow >> 1];
+#pragma unroll
+            for (int q = 0; q < kMaxColsPerLane; ++q) {
+                const int j = pgrp + q * ng;
+                if (j < n) sW[j * ld + prow] = lam * acc[q];
+            }
         }
         __syncthreads();
 
@@ -302,20 +328,32 @@ __global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __res
             vpar[idx] = sV[j * ld + i];
         }
         __syncthreads();
-        // new tensors, roles exchanged: B1 <- B2' = V_kept^T, B2 <- B1' = P V_kept / nrm
+        // new tensors, roles exchanged, into the state row:
+        //   B1 <- B2' = V_kept^T, B2 <- B1' = P V_kept / nrm
         const double inv = 1.0 / snrm;
         for (int idx = tid; idx < nb; idx += kUpdThreads) {
             const int t = idx / (chi * chi), rem = idx - t * chi * chi;
             const int c = rem / chi, b = rem - (rem / chi) * chi;
-            sB1[idx] = ssgn[c] * sV[sord[c] * ld + t * chi + b];
+            st[idx] = ssgn[c] * sV[sord[c] * ld + t * chi + b];
         }
-        for (int idx = tid; idx < nb; idx += kUpdThreads) {
-            const int s = idx / (chi * chi), rem = idx - s * chi * chi;
-            const int a = rem / chi, c = rem - (rem / chi) * chi;
-            const int j = sord[c];
-            double acc = 0.0;
-            for (int k = 0; k < n; ++k) acc = fma(sP[(2 * a + s) * n + k], sV[j * ld + k], acc);
-            sB2[idx] = ssgn[c] * inv * acc;
+        if (pgrp < ng) {   // row (a s) = prow, kept columns c = g, g + ng, ...
+            double acc[kMaxColsPerLane];
+#pragma unroll
+            for (int q = 0; q < kMaxColsPerLane; ++q) acc[q] = 0.0;
+            for (int k = 0; k < n; ++k) {
+                const double pk = gP[k * n + prow];
+#pragma unroll
+                for (int q = 0; q < kMaxColsPerLane; ++q) {
+                    const int c = pgrp + q * ng;
+                    if (c < chi) acc[q] = fma(pk, sV[sord[c] * ld + k], acc[q]);
+                }
+            }
+            const int a = prow >> 1, sp = prow & 1;
+#pragma unroll
+            for (int q = 0; q < kMaxColsPerLane; ++q) {
+                const int c = pgrp + q * ng;
+                if (c < chi) st[nb + (sp * chi + a) * chi + c] = ssgn[c] * inv * acc[q];
+            }
         }
         for (int c = tid; c < chi; c += kUpdThreads) {
             const double old = sl2[c];
@@ -325,10 +363,6 @@ __global__ __launch_bounds__(kUpdThreads) void itebd_update_kernel(double* __res
         __syncthreads();
     }
 
-    for (int i = tid; i < nb; i += kUpdThreads) {
-        st[i] = sB1[i];
-        st[nb + i] = sB2[i];
-    }
     for (int i = tid; i < chi; i += kUpdThreads) {
         st[2 * nb + i] = sl1[i];
         st[2 * nb + chi + i] = sl2[i];
@@ -397,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void itebd_energy_kernel(const double* __
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t states, vprev, sweeps, work, energies, total;
+    size_t states, vprev, pair, sweeps, work, energies, total;
 };
 
 Layout plan(int batch, int chi) {
@@ -409,6 +443,8 @@ Layout plan(int batch, int chi) {
     o = round_up(o + 8 * len * batch, 256);
     L.vprev = o;
     o = round_up(o + 8 * 2 * n * n * batch, 256);
+    L.pair = o;
+    o = round_up(o + 8 * n * n * batch, 256);
     L.sweeps = o;
     o = round_up(o + 4 * (size_t)batch, 256);
     L.work = o;
@@ -528,12 +564,13 @@ int itebd_evolve(itebd_batch* b, double tau, int nupdates) {
     if (b->host_status) return HOTRG_ESTATE;
     const Gate G = gate_of(b->h, tau);
     double* vprev = reinterpret_cast<double*>(b->ws + b->L.vprev);
+    double* pair = reinterpret_cast<double*>(b->ws + b->L.pair);
     int* sweeps = reinterpret_cast<int*>(b->ws + b->L.sweeps);
     unsigned long long* work = reinterpret_cast<unsigned long long*>(b->ws + b->L.work);
     for (int done = 0; done < nupdates;) {
         const int k = std::min(kUpdatesPerLaunch, nupdates - done);
         hipLaunchKernelGGL(itebd_update_kernel, dim3((unsigned)b->batch), dim3(kUpdThreads), 0, b->stream, b->states(),
-                           vprev, sweeps, work, b->chi, G, b->updates, k);
+                           vprev, pair, sweeps, work, b->chi, G, b->updates, k);
         if (hipGetLastError() != hipSuccess) {
             b->host_status = HOTRG_EHIP;
             return HOTRG_EHIP;

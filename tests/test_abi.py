@@ -145,8 +145,9 @@ def test_itebd_sizes_and_error_paths(lib):
     assert lib.itebd_state_len(0) == 0 and lib.itebd_state_len(33) == 0
     assert lib.itebd_workspace_bytes(0, 8) == 0 and lib.itebd_workspace_bytes(4, 33) == 0
     w = lib.itebd_workspace_bytes(256, 32)
-    # states, two warm-start bases per chain (n^2 each, n = 64), counters
-    assert 256 * (4 * 1024 + 64) * 8 + 256 * 2 * 64 * 64 * 8 <= w < 1.01 * (256 * (4160 + 8192) * 8) + 8192
+    # states, the evolved pair and two warm-start bases per chain (n^2 each, n = 64), counters
+    per_chain = (4 * 1024 + 64) + 3 * 64 * 64
+    assert 256 * per_chain * 8 <= w < 1.01 * (256 * per_chain * 8) + 8192
     h = ctypes.c_void_p()
     assert lib.itebd_init(1, 8, None, None, None, 0, None, ctypes.byref(h)) == binding.EINVAL
     assert lib.itebd_evolve(None, 0.1, 1) == binding.EINVAL
