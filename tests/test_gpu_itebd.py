@@ -115,3 +115,26 @@ def test_work_counters_are_consistent(gpu_lib):
     assert sw2 - sw1 >= batch * 30 and rot2 >= rot1
     assert sw1 == int(sw1) and rot1 == int(rot1)
     c.close()
+
+
+def test_benchmark_configuration_sampled_chains(gpu_lib):
+    """The benchmark's launch configuration: 512 Heisenberg chains (two per
+    CU) at D_b = 30 under its warm-up schedule.  Sampled chains (first,
+    middle, last) against the oracle run one by one, to the Heisenberg bar
+    (1e-9 relative: SU(2) multiplets make the kept basis non-unique); the
+    last chain bitwise equal to the same chain run alone; every chain finite
+    and above the Bethe energy."""
+    chi, batch = 30, 512
+    h = workloads.heisenberg_bond()
+    states = workloads.random_chain_states(batch, chi, seed=2026)
+    sched = ((0.1, 96),)
+    c = gpu_run(h, states, chi, sched)
+    e = c.energies()
+    got = c.states()
+    c.close()
+    assert np.all(np.isfinite(e)) and np.all(e > oracle.BETHE_HEISENBERG)
+    for i in (0, 255, 511):
+        er = oracle.energy_per_site(oracle_run(h, states[i], chi, sched), h)
+        assert abs(e[i] - er) <= 1e-9 * abs(er), i
+    one = gpu_run(h, states[511:512], chi, sched).states()
+    assert np.array_equal(got[511], one[0])

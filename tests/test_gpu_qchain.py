@@ -107,3 +107,22 @@ def test_reduced_precision_quantum_chain(gpu_lib, precision):
     b.coarse_grain(10, exchange=False)
     ra, rb = a.log_z_chain(), b.log_z_chain()
     assert abs(rb - ra) < 5e-4 * abs(ra)
+
+
+@pytest.mark.parametrize("D", [32, 48])
+def test_benchmark_configuration_heisenberg(gpu_lib, D):
+    """The benchmark's quantum-chain configuration: S = 1/2 Heisenberg chain,
+    beta = 1, tau = 2^-12, 12 steps along imaginary time, D_b = 32 and 48,
+    against the oracle.  SU(2) multiplets straddle the cuts, so the two
+    sides are two valid truncations that agree to the truncation error, not
+    to rounding (bar 1e-4 on f, as for the low-temperature limit)."""
+    h = workloads.heisenberg_bond()
+    k = 12
+    tau = 1.0 / 2 ** k
+    s = solve(h, tau, D, max_steps=k)
+    s.coarse_grain(k, exchange=False)
+    f = -s.log_z_chain() / (2.0 * tau)
+    ref = -qchain.chain_lnz(qchain.block_tensor(h, tau), D, k) / (2.0 * tau)
+    assert abs(f - ref) < 1e-4
+    # high-temperature series at T = 1 as a coarse check of both
+    assert abs(f - (-math.log(2.0) - 3.0 / 32.0)) < 0.05
