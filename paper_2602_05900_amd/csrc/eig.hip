@@ -224,9 +224,11 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
     }
     __syncthreads();
     // Rotation test: an off-diagonal element is zeroed while it is large
-    // relative to its own diagonal pair.
+    // relative to its own diagonal pair, |hij| > 1e-14 sqrt|hii hjj|, taken
+    // squared (no square root on the round's critical path; off-diagonal
+    // elements below ~1e-154 count as zero).
     auto passes = [&](double hij, double hii, double hjj) {
-        return fabs(hij) > 1e-300 && fabs(hij) > 1e-14 * sqrt(fabs(hii * hjj));
+        return hij * hij > 1e-28 * fabs(hii * hjj) && fabs(hij) > 1e-300;
     };
     int sweeps = 0;
     for (int sweep = 0; sweep < EIG_MAX_SWEEPS; ++sweep) {
@@ -247,17 +249,23 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
             // round-robin pairing: position 0 fixed, positions 1..pp-1 rotate by r
             if (tid < half) {
                 const int qa = tid, qb = pp - 1 - tid;
-                const int a = qa == 0 ? 0 : ((qa - 1 + r) % (pp - 1)) + 1;
-                const int b = ((qb - 1 + r) % (pp - 1)) + 1;
+                // (q - 1 + r) modulo pp - 1 (both terms below pp - 1), plus 1
+                int a = qa - 1 + r, b = qb - 1 + r;
+                a -= a >= pp - 1 ? pp - 1 : 0;
+                b -= b >= pp - 1 ? pp - 1 : 0;
+                a = qa == 0 ? 0 : a + 1;
+                b += 1;
                 const int i = min(a, b), j = max(a, b);
                 pi[tid] = i;
                 pj[tid] = j;
                 const double hii = H[i * EIG_LDP + i], hjj = H[j * EIG_LDP + j], hij = H[i * EIG_LDP + j];
                 double c = 1.0, s = 0.0, t = 0.0;
                 if (passes(hij, hii, hjj)) {
-                    const double tau = (hjj - hii) / (2.0 * hij);
-                    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
+                    // the smaller root of t^2 + 2 tau t - 1 = 0, tau = (hjj - hii) / (2 hij),
+                    // written without forming tau: t = sign(d) 2hij / (|d| + sqrt(d^2 + 4 hij^2))
+                    const double d = hjj - hii, h2 = 2.0 * hij;
+                    t = (d >= 0.0 ? h2 : -h2) / (fabs(d) + sqrt(fma(d, d, h2 * h2)));
+                    c = rsqrt(fma(t, t, 1.0));
                     s = t * c;
                 }
                 cs[tid] = c;
