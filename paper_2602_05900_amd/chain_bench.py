@@ -54,6 +54,9 @@ def run_qchain(dmax: int, steps: int, temperature: float = 1.0) -> dict:
     h = workloads.heisenberg_bond()
     tau = (1.0 / temperature) / 2 ** steps
     s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=dmax, max_steps=steps)
+    s.coarse_grain(steps, exchange=False)      # untimed warm-up solve
+    s.log_z_chain()
+    s.reset(model="qchain", bond_h=h, tau=tau, dmax=dmax, max_steps=steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.coarse_grain(steps, exchange=False)

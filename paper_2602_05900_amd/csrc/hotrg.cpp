@@ -580,7 +580,10 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
     record(s, step_index, 2);
     // -- FP64 eigensolve(s) and isometry
     {
-        const int par = step_index & 1;
+        // Ritz block kept per fused axis: with the exchange the axes alternate,
+        // so the last block of this axis is the step two earlier; without it
+        // every step fuses the same legs and the previous step's block is used
+        const int par = exchange ? (step_index & 1) : 0;
         const int pblk = nE > kEigPMax ? eig_block(nE, Dp) : nE;
         const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)n;
         const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;

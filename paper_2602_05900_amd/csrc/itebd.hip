@@ -55,15 +55,8 @@ constexpr int kUpdThreads = kLanesPerPair * kMaxN / 2;   // update kernel: one l
 constexpr int kMaxColsPerLane = (kMaxN + 7) / 8;
 constexpr int kUpdatesPerLaunch = 32;
 constexpr int kMaxSweeps = 40;
-#ifndef ITEBD_TOL
-#define ITEBD_TOL 1e-14
-#endif
-#ifndef ITEBD_ABS
-#define ITEBD_ABS 0
-#endif
-// rotate a pair while |w_p.w_q| > kTol |w_p| |w_q| (relative test), or, with
-// the absolute test, while |w_p.w_q| > kTol |W|_F^2
-constexpr double kTol = ITEBD_TOL;
+// rotate a pair while |w_p.w_q| > kTol |w_p| |w_q| (relative test)
+constexpr double kTol = 1e-14;
 
 struct Gate {
     double g[16];   // exp(-tau h), row-major [(s' t'), (s t)]
@@ -90,6 +83,8 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
+// four waves per SIMD (at most 128 VGPRs): with 75 KB of LDS two workgroups
+// of eight waves then share a CU
 __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4))) void itebd_update_kernel(double* __restrict__ states,
                                                                 double* __restrict__ vprev,
                                                                 double* __restrict__ pair,
@@ -201,12 +196,6 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4))
         __syncthreads();
 
         // one-sided Jacobi
-        double fro2 = 0.0;
-        if (ITEBD_ABS) {
-            // |W|_F^2 (invariant under the rotations): every thread sums the same terms in the same order
-            for (int j = 0; j < n; ++j)
-                for (int i = 0; i < n; ++i) fro2 = fma(sW[j * ld + i], sW[j * ld + i], fro2);
-        }
         const int g = tid / kLanesPerPair, lane = tid % kLanesPerPair;
         const int npair = n >> 1;
         int sweeps = kMaxSweeps;
@@ -254,8 +243,8 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4))
                     al = sum16(al);
                     be = sum16(be);
                     ga = sum16(ga);
-                    // rotate while ga^2 > kTol^2 al be (relative test) or |ga| > kTol |W|_F^2
-                    if (ITEBD_ABS ? fabs(ga) > kTol * fro2 : ga * ga > (kTol * kTol) * (al * be)) {
+                    // rotate while ga^2 > kTol^2 al be (the relative test, squared)
+                    if (ga * ga > (kTol * kTol) * (al * be)) {
                         // the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga):
                         // t = sign(d) 2ga / (|d| + sqrt(d^2 + 4 ga^2)), d = be - al
                         const double d = be - al, g2 = 2.0 * ga;
