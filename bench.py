@@ -288,6 +288,15 @@ def run_qchain(binding, workloads):
     x = np.polyfit(np.log([r[0] for r in rows[1:]]), np.log([r[1] for r in rows[1:]]), 1)[0]
     out["ms_per_step"] = {str(d): t for d, t in rows}
     out["fit_exponent_d8_to_d48"] = float(x)
+    # where a step goes at D_b = 32: HIP events between the stages of every
+    # step (a separate timed solve, so the timing above is not perturbed)
+    s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=32, max_steps=k)
+    s.set_timing(True)
+    s.coarse_grain(k, exchange=False)
+    s.log_z_chain()
+    st, nst = s.stage_times()
+    s.close()
+    out["stage_ms_per_step_d32"] = {name: v / max(nst, 1) for name, v in st.items() if v > 0.0}
     fe = {}
     for temp in (2.0, 1.0, 0.5, 0.25):
         tau_t = (1.0 / temp) / 2 ** k
