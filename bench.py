@@ -412,7 +412,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+        print(json.dumps({"error": "the benchmark runs on one GPU: the path has no multi-GPU mode, so --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -41,8 +41,8 @@ written out here:
   same isometry and normalisation as T, so that after n steps
   Tr I_n / Tr T_n is the observable averaged over the torus.
 
-Readings where the paper is silent are listed in the design doc; each appears
-below at the point it is used.
+Where the paper is silent, the reading taken is stated below at the point
+where it is used.
 """
 from __future__ import annotations
 
