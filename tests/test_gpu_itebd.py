@@ -138,3 +138,16 @@ def test_benchmark_configuration_sampled_chains(gpu_lib):
         assert abs(e[i] - er) <= 1e-9 * abs(er), i
     one = gpu_run(h, states[511:512], chi, sched).states()
     assert np.array_equal(got[511], one[0])
+
+
+def test_zero_updates_leave_the_states_unchanged(gpu_lib):
+    """Degenerate call: nupdates = 0 launches nothing; the states read back
+    are the uploaded ones, bit for bit, and the counters stay at zero."""
+    from paper_2602_05900_amd import binding
+    chi = 7
+    states = workloads.random_chain_states(3, chi, seed=41)
+    c = binding.Chains(workloads.heisenberg_bond(), states, chi)
+    c.evolve(0.1, 0)
+    assert np.array_equal(c.states(), states)
+    assert c.info()[0] == 0 and c.work() == (0.0, 0.0)
+    c.close()
