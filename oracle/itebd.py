@@ -61,10 +61,6 @@ def unpack(row: np.ndarray, chi: int, d: int = 2) -> ChainState:
                       l1=row[2 * n:2 * n + chi].copy(), l2=row[2 * n + chi:2 * n + 2 * chi].copy())
 
 
-def pack(st: ChainState) -> np.ndarray:
-    return np.concatenate([st.B1.ravel(), st.B2.ravel(), st.l1, st.l2])
-
-
 def sign_gauge_rows(Yt: np.ndarray) -> np.ndarray:
     """Make the largest-magnitude entry of each row positive (lowest index on ties)."""
     out = Yt.copy()
@@ -136,12 +132,3 @@ def tfim_energy(g: float, J: float = 1.0, npts: int = 20001) -> float:
     hstep = k[1] - k[0]
     s = f[0] + f[-1] + 4.0 * np.sum(f[1:-1:2]) + 2.0 * np.sum(f[2:-1:2])
     return -(s * hstep / 3.0) / math.pi
-
-
-def update_flops(chi: int, d: int = 2) -> float:
-    """FLOPs of one bond update in the order above: the contraction of B1 and
-    B2 (2 d^2 chi^3), the gate (2 d^4 chi^2), psi' Y (2 d^2 chi^3) and one SVD
-    of the (d chi) x (d chi) matrix counted as 4 (d chi)^3 (the work of one
-    sweep of one-sided Jacobi over all column pairs, rows of M and of V)."""
-    n = d * chi
-    return 2.0 * d * d * chi ** 3 + 2.0 * d ** 4 * chi ** 2 + 2.0 * d * d * chi ** 3 + 4.0 * n ** 3

@@ -86,3 +86,14 @@ def test_heisenberg_high_temperature_series():
 def test_heisenberg_low_temperature_approaches_bethe():
     f = qchain.free_energy(workloads.heisenberg_bond(), 0.05, 16, 14)   # beta = 819
     assert 0.0 < f - itebd.BETHE_HEISENBERG < 2.5e-3
+
+
+def test_alternating_merges_approach_the_ground_state_energy():
+    """Merging along both axes (beta -> infinity) gives the ground-state
+    energy per site: for the transverse-field Ising chain at g = 1.5 it lies
+    above the free-fermion value and approaches it as D grows."""
+    h = workloads.ising_transverse_bond(1.5)
+    exact_e = itebd.tfim_energy(1.5)
+    e16 = qchain.ground_energy(h, 0.02, 16, 16) - exact_e
+    e24 = qchain.ground_energy(h, 0.02, 24, 16) - exact_e
+    assert 0.0 < e24 < e16 < 3e-3
