@@ -46,6 +46,7 @@ constexpr int kMaxN = 2 * kMaxChi;
 // column stride of W and V: the smallest ld >= n with ld = 8 (mod 32)
 __host__ __device__ constexpr int col_stride(int n) { return ((n + 23) / 32) * 32 + 8; }
 constexpr int kMaxLd = col_stride(kMaxN);
+static_assert(4 * kMaxChi * kMaxChi <= kMaxN * kMaxLd, "B1 and B2 are staged in the V buffer");
 constexpr int kLanesPerPair = 16;
 constexpr int kRowsPerLane = kMaxN / kLanesPerPair;
 constexpr int kThreads = 256;                       // energy kernel
@@ -53,6 +54,7 @@ constexpr int kUpdThreads = kLanesPerPair * kMaxN / 2;   // update kernel: one l
 // row-parallel products (W = P V, B1' = P V_kept): kUpdThreads / n >= 8 groups
 // of n lanes, each lane one row and at most this many columns
 constexpr int kMaxColsPerLane = (kMaxN + 7) / 8;
+static_assert(kUpdThreads / kMaxN >= 8, "row-parallel products assume at least 8 lane groups");
 constexpr int kUpdatesPerLaunch = 32;
 constexpr int kMaxSweeps = 40;
 // rotate a pair while |w_p.w_q| > kTol |w_p| |w_q| (relative test)
