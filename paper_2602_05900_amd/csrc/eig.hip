@@ -412,14 +412,6 @@ __global__ __launch_bounds__(256) void eig_rotate_kernel(double* __restrict__ V,
 
 // ---------------------------------------------------------------- Cholesky
 
-// sum_{m=j}^{i-1} L[i][m] M[m][j] with L in the lower triangle of A, the
-// strict lower part of M = L^{-1} stored transposed in A's upper triangle
-// (M[m][j] at A[j][m]) and its diagonal in d2.
-__device__ __forceinline__ double L_times_M(const double* A, int i, int j, const double* d2) {
-    double acc = A[i * EIG_LDP + j] * d2[j];
-    for (int m = j + 1; m < i; ++m) acc += A[i * EIG_LDP + m] * A[j * EIG_LDP + m];
-    return acc;
-}
 
 // One workgroup.  G (p x p) is the Gram matrix of the block X to be
 // orthonormalised.  check >= 0: first decide convergence from the reduced
@@ -492,13 +484,27 @@ __global__ __launch_bounds__(1024) void eig_chol_kernel(const double* __restrict
     __shared__ double d2[EIG_PMAX];
     for (int i = tid; i < p; i += 1024) d2[i] = 1.0 / A[i * EIG_LDP + i];
     __syncthreads();
-    for (int i = 1; i < p; ++i) {
-        for (int j = tid; j < i; j += 1024) {
-            double acc = L_times_M(A, i, j, d2);
-            A[j * EIG_LDP + i] = -acc * d2[i];
+    // one column of M per thread: column j is the forward substitution
+    // L m = e_j, which reads only L and the column's own earlier entries, so
+    // the columns need no barriers between them (four partial sums per dot
+    // product for instruction-level parallelism)
+    for (int j = tid; j < p; j += 1024) {
+        for (int i = j + 1; i < p; ++i) {
+            const double* Li = A + i * EIG_LDP;
+            const double* Mj = A + j * EIG_LDP;   // M[m][j] at A[j][m]
+            double a0 = Li[j] * d2[j], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int m = j + 1;
+            for (; m + 3 < i; m += 4) {
+                a0 = fma(Li[m], Mj[m], a0);
+                a1 = fma(Li[m + 1], Mj[m + 1], a1);
+                a2 = fma(Li[m + 2], Mj[m + 2], a2);
+                a3 = fma(Li[m + 3], Mj[m + 3], a3);
+            }
+            for (; m < i; ++m) a0 = fma(Li[m], Mj[m], a0);
+            A[j * EIG_LDP + i] = -((a0 + a1) + (a2 + a3)) * d2[i];
         }
-        __syncthreads();
     }
+    __syncthreads();
     // Q[r][c] = d_r * M[c][r] (X_new = X D L^{-T}); M[c][r] = 0 for r > c
     for (int e = tid; e < p * p; e += 1024) {
         const int r = e / p, c = e - (e / p) * p;
