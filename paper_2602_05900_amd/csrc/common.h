@@ -120,6 +120,8 @@ struct EigCtl {
     int sweeps;      // Jacobi sweeps of the last small eigenproblem
     double resid;    // max_j |E u_j - theta_j u_j| / theta_0 over the kept pairs
     double trace;    // Tr E
+    double best;     // smallest residual seen at a convergence check
+    int stall;       // consecutive checks that did not bring it below 0.9 best
 };
 
 constexpr int kEigPMax = 96;   // largest Ritz block / largest fully diagonalised E

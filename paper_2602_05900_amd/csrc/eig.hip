@@ -86,6 +86,8 @@ __global__ __launch_bounds__(256) void eig_init_kernel(const double* __restrict_
             ctl->iters = 0;
             ctl->converged = 0;
             ctl->resid = 0.0;
+            ctl->best = 1e300;
+            ctl->stall = 0;
         }
     }
     if (!warm) {
@@ -435,10 +437,22 @@ __global__ __launch_bounds__(1024) void eig_chol_kernel(const double* __restrict
             for (int j = 0; j < k; ++j) worst = fmax(worst, sqrt(fmax(G[p * p + j], 0.0)));
             const double scale = fmax(fabs(theta[0]), 1e-300);
             const int conv = worst <= tol * scale;
+            const double r = worst / scale;
             ctl->iters = check + 1;
-            ctl->resid = worst / scale;
+            ctl->resid = r;
             ctl->converged = conv;
-            stop = conv || check == last_iter;
+            // stagnation: three checks in a row without getting below 0.9x
+            // the best residual so far mean the block has reached its
+            // rounding floor (kept pairs in the noise of a nearly rank-
+            // deficient E); further passes would end at the same residual at
+            // the pass cap, so stop here (converged stays 0, as at the cap)
+            if (r < 0.9 * ctl->best) {
+                ctl->best = r;
+                ctl->stall = 0;
+            } else {
+                ctl->stall += 1;
+            }
+            stop = conv || check == last_iter || ctl->stall >= 3;
             if (stop) ctl->done = 1;
         }
         __syncthreads();
