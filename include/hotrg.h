@@ -32,8 +32,12 @@
  * (the 2x2-block rotation scheme of Sec. II.B, Eqs. (5)-(6)); larger ones by
  * a block subspace iteration with Rayleigh-Ritz projection (the small
  * projected problem again by that Jacobi method), warm-started from the
- * isometry of the step two earlier, until the kept Ritz pairs have relative
- * residual <= 1e-12 (at most 30 passes).
+ * isometry of the step two earlier (the previous step's for steps without
+ * the axis exchange), until the kept Ritz pairs have relative residual
+ * <= 1e-12, at most 30 passes, or until the residual stagnates (three
+ * convergence checks in a row without getting below 0.9x the best so far,
+ * as when kept pairs lie in the rounding noise of a nearly rank-deficient
+ * environment; hotrg_eig_info then reports the residual reached).
  *
  * Errors: every int-returning call returns HOTRG_OK (0) or a negative
  * status.  Errors detected on the device (non-finite or non-positive c_n, a
