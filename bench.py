@@ -223,7 +223,7 @@ def run_itebd(binding, workloads):
     kernel_s = ev0.elapsed_time(ev1) / 1e3
     sw1, rot1 = c.work()
     flops = chain_bench.itebd_flops(chi, batch * nup, sw1 - sw0, rot1 - rot0)
-    launches = -(-nup // 32)
+    launches = -(-nup // 32)          # itebd_evolve launches up to 32 updates at a time
     out["d30_batch512"] = {"chains": batch, "bond_updates_per_chain": nup, "seconds": dt,
                            "updates_per_s": batch * nup / dt, "us_per_update_per_chain": dt / nup * 1e6,
                            "energy_mean": float(np.mean(e)), "energy_minus_bethe_max": float(np.max(e) - bethe),
