@@ -471,26 +471,32 @@ __global__ __launch_bounds__(1024) void eig_chol_kernel(const double* __restrict
         A[i * EIG_LDP + j] = v;
     }
     __syncthreads();
-    // right-looking Cholesky of the lower triangle, two barriers per column:
-    // every thread takes the pivot sqrt(A_jj) itself (A_jj is final and is
-    // not overwritten until the end), scales its entries of column j, then
-    // the trailing update runs.
+    // right-looking Cholesky of the lower triangle, one barrier per column:
+    // every thread takes the pivot sqrt(A_jj) itself (A_jj is final at
+    // column j); the trailing update scales the column-j entries it needs on
+    // the fly (column j is only read in this phase), and the scaled column is
+    // written transposed into the free upper triangle (row j), then copied
+    // back into the lower triangle after the last column.
     __shared__ double ldiag[EIG_PMAX];
     const int ty = tid >> 5, tx = tid & 31;
     for (int j = 0; j < p; ++j) {
         const double a = A[j * EIG_LDP + j];
         const double ljj = a > 1e-300 ? sqrt(a) : 1.0;
+        const double inv = 1.0 / ljj;
         if (tid == 0) ldiag[j] = ljj;
-        for (int i = j + 1 + tid; i < p; i += 1024) A[i * EIG_LDP + j] /= ljj;
-        __syncthreads();
-        // trailing update of the lower triangle, thread (ty, tx) of a 32 x 32 grid
+        // thread (ty, tx) of a 32 x 32 grid: rows i = j + 1 + ty, ..., columns l = j + 1 + tx, ... <= i
         for (int i = j + 1 + ty; i < p; i += 32) {
-            const double lij = A[i * EIG_LDP + j];
-            for (int l = j + 1 + tx; l <= i; l += 32) A[i * EIG_LDP + l] -= lij * A[l * EIG_LDP + j];
+            const double lij = A[i * EIG_LDP + j] * inv;
+            if (tx == 0) A[j * EIG_LDP + i] = lij;
+            for (int l = j + 1 + tx; l <= i; l += 32) A[i * EIG_LDP + l] -= lij * (A[l * EIG_LDP + j] * inv);
         }
         __syncthreads();
     }
-    for (int j = tid; j < p; j += 1024) A[j * EIG_LDP + j] = ldiag[j];
+    for (int e = tid; e < p * p; e += 1024) {
+        const int i = e / p, c = e - (e / p) * p;
+        if (c < i) A[i * EIG_LDP + c] = A[c * EIG_LDP + i];
+        else if (c == i) A[i * EIG_LDP + i] = ldiag[i];
+    }
     __syncthreads();
     // M = L^{-1} (lower), row by row: M[i][j] = -(sum_{m=j}^{i-1} L[i][m] M[m][j]) / L[i][i]
     // kept in the strict upper triangle of A transposed (A[j][i] for j < i) and
