@@ -151,3 +151,33 @@ def test_zero_updates_leave_the_states_unchanged(gpu_lib):
     assert np.array_equal(c.states(), states)
     assert c.info()[0] == 0 and c.work() == (0.0, 0.0)
     c.close()
+
+
+def test_benchmark_launch_configuration_elementwise_tfim(gpu_lib):
+    """512 chains (two per CU) at D_b = 30, the benchmark's launch
+    configuration, on the transverse-field Ising chain (g = 1.5, distinct
+    Schmidt values): sampled chains element by element against the oracle,
+    weights to 1e-10 and tensors to 1e-9 after the shared sign gauge.  The
+    samples (two from each half of the batch) have kept Schmidt values at
+    least 3e-6 apart, so the oracle's LAPACK vectors, accurate to about
+    eps / gap, are good to ~1e-10; chains with gaps near 1e-8 (which the
+    one-sided Jacobi resolves better than LAPACK) are not used."""
+    chi, batch = 30, 512
+    h = workloads.ising_transverse_bond(1.5)
+    states = workloads.random_chain_states(batch, chi, seed=77)
+    sched = ((0.05, 64),)
+    c = gpu_run(h, states, chi, sched)
+    got = c.states()
+    e = c.energies()
+    c.close()
+    for i in (1, 100, 400, 510):
+        ref = oracle_run(h, states[i], chi, sched)
+        gaps = [np.min(np.abs(np.diff(np.sort(lam)))) for lam in (ref.l1, ref.l2)]
+        assert min(gaps) > 3e-6, (i, gaps)
+        g = oracle.unpack(got[i], chi)
+        np.testing.assert_allclose(g.l1, ref.l1, atol=1e-10)
+        np.testing.assert_allclose(g.l2, ref.l2, atol=1e-10)
+        np.testing.assert_allclose(g.B1, ref.B1, atol=1e-9)
+        np.testing.assert_allclose(g.B2, ref.B2, atol=1e-9)
+        er = oracle.energy_per_site(ref, h)
+        assert abs(e[i] - er) <= 1e-12 * abs(er)
