@@ -87,12 +87,10 @@ __device__ __forceinline__ double sum16(double v) {
 
 // four waves per SIMD (at most 128 VGPRs): with 75 KB of LDS two workgroups
 // of eight waves then share a CU
-__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4))) void itebd_update_kernel(double* __restrict__ states,
-                                                                double* __restrict__ vprev,
-                                                                double* __restrict__ pair,
-                                                                int* __restrict__ sweeps_out,
-                                                                unsigned long long* __restrict__ work, int chi,
-                                                                Gate G, long base, int nupd)
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev, double* __restrict__ pair,
+                         int* __restrict__ sweeps_out, unsigned long long* __restrict__ work, int chi, Gate G,
+                         long base, int nupd)
 {
     // 75 KB in all, so two chains share a CU
     __shared__ double sW[kMaxN * kMaxLd];   // column-major, stride ld
