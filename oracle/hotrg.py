@@ -237,6 +237,24 @@ def truncation(E: np.ndarray, dmax: int) -> Truncation:
     return Truncation(U=U, eigenvalues=lam, kept=kept, trunc_err=trunc_err, cut_gap=cut_gap)
 
 
+def project(T: np.ndarray, U: np.ndarray):
+    """The merged pair's fused legs projected with an isometry U (n x D',
+    n = Dx^2, rows (a1 a2) with a1 the bottom copy's leg), in the O(D^7) order:
+
+    X[l,a2,r1,d,k] = sum_{a1}     U[a1,a2,l] T[a1,r1,d,k]
+    Y[l,r1,d,r2,u] = sum_{a2,k}   X[l,a2,r1,d,k] T[a2,r2,k,u]
+    T'[l,r,d,u]    = sum_{r1,r2}  Y[l,r1,d,r2,u] U[r1,r2,r]
+
+    Returns (X, T'), T' unnormalised with legs [l, r, d, u] (no exchange).
+    """
+    Dx = T.shape[0]
+    U3 = U.reshape(Dx, Dx, U.shape[1])                           # U[a1, a2, l]
+    X = np.einsum("abl,ardk->lbrdk", U3, T, optimize=True)       # X[l,a2,r1,d,k]
+    Y = np.einsum("lbrdk,bsku->lrdsu", X, T, optimize=True)      # Y[l,r1,d,r2,u]
+    Tp = np.einsum("lrdsu,rsm->lmdu", Y, U3, optimize=True)      # T'[l,r,d,u]
+    return X, Tp
+
+
 @dataclass
 class StepResult:
     T_next: np.ndarray     # normalised, x/y exchanged: dims [Dy, Dy, D', D']
@@ -281,9 +299,7 @@ def coarse_grain_step(T: np.ndarray, dmax: int, two_sided: bool = False,
         if trr.trunc_err < tr.trunc_err:
             tr, side = trr, 1
     U3 = tr.U.reshape(Dx, Dx, tr.kept)                           # U[a1, a2, l]
-    X = np.einsum("abl,ardk->lbrdk", U3, T, optimize=True)       # X[l,a2,r1,d,k]
-    Y = np.einsum("lbrdk,bsku->lrdsu", X, T, optimize=True)      # Y[l,r1,d,r2,u]
-    Tp = np.einsum("lrdsu,rsm->lmdu", Y, U3, optimize=True)      # T'[l,r,d,u]
+    X, Tp = project(T, tr.U)
     c = float(np.max(np.abs(Tp)))
     Tp = Tp / c
     nxt = []
