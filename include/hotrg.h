@@ -37,13 +37,22 @@
  * <= 1e-12, at most 30 passes, or until the residual stagnates (three
  * convergence checks in a row without getting below 0.9x the best so far,
  * as when kept pairs lie in the rounding noise of a nearly rank-deficient
- * environment; hotrg_eig_info then reports the residual reached).
+ * environment; hotrg_eig_info then reports the residual reached and
+ * HOTRG_EIG_STAGNATED).  A solve that stops short of the 1e-12 bound with a
+ * residual above the failure bound (1e-6 of the largest eigenvalue by
+ * default, see hotrg_set_eig_limits), or whose eigenvalues are not finite,
+ * or a dense Jacobi diagonalisation that ends at its sweep cap, is a failed
+ * eigensolve: HOTRG_EEIG is latched on the device.
  *
  * Errors: every int-returning call returns HOTRG_OK (0) or a negative
- * status.  Errors detected on the device (non-finite or non-positive c_n, a
- * failed eigensolve) are latched in a device status word; the first one
- * sticks and is returned by the next synchronising call (hotrg_log_z,
- * hotrg_step_info, hotrg_copy_tensor).  No C++ exception crosses this ABI.
+ * status.  Errors detected on the device (HOTRG_ENONFINITE: a non-finite or
+ * non-positive c_n; HOTRG_EEIG: a failed eigensolve) are latched in a device
+ * status word; the first one sticks and is returned by the next
+ * synchronising call (hotrg_log_z, hotrg_log_z_chain, hotrg_step_info,
+ * hotrg_step_sides, hotrg_eig_info, hotrg_observables, hotrg_copy_tensor).
+ * The kernels of later steps still run (and exit normally) on whatever the
+ * failed step left; only the status is reported.  No C++ exception crosses
+ * this ABI.
  * Distinct handles are independent and may be driven from different host
  * threads; one handle must not be used from two threads at once.
  */
@@ -61,7 +70,7 @@ extern "C" {
 #define HOTRG_EINVAL     -1  /* invalid argument or parameter set           */
 #define HOTRG_ENOMEM     -2  /* workspace smaller than hotrg_workspace_bytes */
 #define HOTRG_EHIP       -3  /* a HIP runtime call failed                    */
-#define HOTRG_EEIG       -4  /* eigensolve not possible for these parameters  */
+#define HOTRG_EEIG       -4  /* eigensolve failed (latched on the device)     */
 #define HOTRG_ENONFINITE -5  /* c_n or the final trace not finite or <= 0    */
 #define HOTRG_ESTATE     -6  /* call not valid in the handle's state         */
 #define HOTRG_ENODEV     -7  /* no HIP device                                */
@@ -253,18 +262,58 @@ int hotrg_step_sides(hotrg_solve* s, int n, double* eps_left, double* eps_right,
  * ENONFINITE (Tr T = 0). */
 int hotrg_observables(hotrg_solve* s, double values[2]);
 
+/* How the eigensolve of a step ended (hotrg_eig_info's `stop`). */
+#define HOTRG_EIG_CONVERGED  0  /* every kept Ritz pair met the 1e-12 bound, or
+                                   E was diagonalised densely to the Jacobi
+                                   rotation threshold                         */
+#define HOTRG_EIG_STAGNATED  1  /* stopped when the residual stopped falling   */
+#define HOTRG_EIG_PASS_CAP   2  /* stopped at the pass cap (dense: sweep cap)   */
+
 /* Synchronises and reports the eigensolve of step n (1..steps taken):
  * iterations = subspace passes used (0 when E was diagonalised densely),
- * sweeps = Jacobi sweeps of the last projected problem, residual =
- * max_j |E u_j - theta_j u_j| / theta_0 over the kept pairs (0 when dense).
- * Any output pointer may be NULL.  Errors: EINVAL, latched. */
-int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual);
+ * sweeps = Jacobi sweeps of the last projected problem (of E itself when
+ * dense), residual = max_j |E u_j - theta_j u_j| / theta_0 over the kept
+ * pairs (0 when dense), stop = HOTRG_EIG_* above.  A step whose stop is not
+ * HOTRG_EIG_CONVERGED and whose residual exceeds the failure bound has
+ * latched HOTRG_EEIG, which this call then returns (the outputs are left
+ * unset).  Any output pointer may be NULL.  Errors: EINVAL, latched. */
+int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual, int* stop);
+
+/* Eigensolver limits for the steps enqueued after this call (the defaults
+ * are restored by hotrg_reset):
+ *   max_passes    subspace passes per eigensolve, 1..HOTRG_EIG_MAX_PASSES
+ *                 (default 30)
+ *   fail_residual a solve that stops short of convergence with a residual
+ *                 above fail_residual (relative to the largest eigenvalue)
+ *                 latches HOTRG_EEIG; > 0, default 1e-6.
+ * A small pass cap makes the failure reachable on purpose without any
+ * invalid input (tests of the error path): every kernel still exits
+ * normally.  Errors: EINVAL. */
+#define HOTRG_EIG_MAX_PASSES 60
+int hotrg_set_eig_limits(hotrg_solve* s, int max_passes, double fail_residual);
 
 /* Synchronises and copies the current normalised tensor (FP64) to host
  * memory `host` of `capacity` doubles; dims receives {Dx, Dy} (the tensor
  * has Dx*Dx*Dy*Dy entries, layout as above).  Errors: EINVAL (capacity too
  * small: dims are still filled in), latched errors. */
 int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]);
+
+/* Synchronises and copies the environment of the last step taken (left
+ * environment E = M M^T, symmetrised, FP64 as the eigensolver received it;
+ * Sec. II.A) to host memory `host` of `capacity` doubles, row-major n x n
+ * with rows and columns the fused leg (a1 a2), a1 the bottom copy's; *n
+ * receives n = Dx^2 of that step.  For tests and diagnostics: the buffer is
+ * overwritten by the next step.  Errors: EINVAL (no step taken, capacity
+ * too small: *n is still filled in), latched errors. */
+int hotrg_copy_environment(hotrg_solve* s, double* host, size_t capacity, int* n);
+
+/* Synchronises and copies the isometry the last step applied to host memory
+ * `host` of `capacity` doubles, row-major n x D' (column l = kept vector l,
+ * rows the fused leg (a1 a2)), as the contractions used it: FP64 values
+ * for HOTRG_FP64, the FP32 value or the sum of the BF16 planes otherwise.
+ * dims receives {n, D'}.  For tests and diagnostics.  Errors: as
+ * hotrg_copy_environment. */
+int hotrg_copy_isometry(hotrg_solve* s, double* host, size_t capacity, int dims[2]);
 
 /* Per-stage timing with HIP events recorded on the solve's stream.
  * hotrg_set_timing(s, 1) starts recording for the steps enqueued afterwards
@@ -274,6 +323,11 @@ int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]
  * recorded since timing was enabled, and the number of such steps. */
 int hotrg_set_timing(hotrg_solve* s, int enable);
 int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed);
+/* The same for one recorded step: ms[HOTRG_NUM_STAGES] of the k-th step
+ * enqueued since timing was enabled (0-based), and that step's input dims
+ * {Dx, Dy, D'} in dims (may be NULL).  Synchronises.  Errors: EINVAL (timing
+ * off or k out of range). */
+int hotrg_step_stage_times(hotrg_solve* s, int k, double* ms, int dims[3]);
 
 /* Per-kernel timing of the Y contraction (the D^7 GEMM): summed GPU ms and
  * launch count over the recorded steps, from events around that launch. */
@@ -313,6 +367,28 @@ int hotrg_gemm_nt(int precision, int M, int N, int K,
                   double* C, double alpha,
                   long sm, long rs_hi, long rs_lo, long sn, long cs_hi, long cs_lo,
                   void* scratch, void* stream);
+
+/* hotrg_gemm_nt with the tile choice of one contraction of a step, so that a
+ * test reaches the very kernel a solve launches for it:
+ *   role   HOTRG_ROLE_GENERIC (half environments and E), HOTRG_ROLE_X,
+ *          HOTRG_ROLE_Y (the D^7 product) or HOTRG_ROLE_TP
+ *   panel  1: both converted operands are stored in the 32 x 16 panel layout
+ *          a solve's producers write for the environment and Y products
+ *          (split precisions only; M and N multiples of 32, K of 16)
+ * The output is FP64 through the map, as for hotrg_gemm_nt (a solve's Y
+ * writes FP32 in the split modes; the products themselves are the same).
+ * Errors: EINVAL (as hotrg_gemm_nt, role out of range, panel with FP64 or
+ * with shapes the layout cannot hold), EHIP (also when the role's kernel
+ * does not accept the shape). */
+#define HOTRG_ROLE_GENERIC 0
+#define HOTRG_ROLE_X       1
+#define HOTRG_ROLE_Y       2
+#define HOTRG_ROLE_TP      3
+int hotrg_gemm_nt_role(int precision, int role, int panel, int M, int N, int K,
+                       const double* A, long lda, const double* B, long ldb,
+                       double* C, double alpha,
+                       long sm, long rs_hi, long rs_lo, long sn, long cs_hi, long cs_lo,
+                       void* scratch, void* stream);
 
 #ifdef __cplusplus
 }

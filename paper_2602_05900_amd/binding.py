@@ -23,6 +23,9 @@ FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 MODELS = {"ising": ISING, "potts": POTTS, "custom": CUSTOM, "qchain": QCHAIN}
 MAX_STEPS = 60
+# how a step's eigensolve ended (hotrg_eig_info)
+EIG_CONVERGED, EIG_STAGNATED, EIG_PASS_CAP = 0, 1, 2
+EIG_MAX_PASSES = 60
 STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm", "obs"]
 # observable slots (hotrg_observables): order parameter per site, energy of one y bond
 OBS_MAGNETIZATION, OBS_BOND_ENERGY = 1, 2
@@ -31,9 +34,10 @@ OBSERVABLES = {"m": OBS_MAGNETIZATION, "e": OBS_BOND_ENERGY}
 EXPORTS = [
     "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain",
     "hotrg_coarse_grain_batch", "hotrg_coarse_grain_axis", "hotrg_log_z", "hotrg_log_z_chain",
-    "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_copy_tensor", "hotrg_set_timing", "hotrg_stage_times",
+    "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_set_eig_limits",
+    "hotrg_copy_tensor", "hotrg_copy_environment", "hotrg_copy_isometry", "hotrg_set_timing", "hotrg_stage_times", "hotrg_step_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
-    "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt",
+    "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt", "hotrg_gemm_nt_role",
     "itebd_state_len", "itebd_workspace_bytes", "itebd_init", "itebd_evolve", "itebd_energy",
     "itebd_copy_states", "itebd_info", "itebd_work", "itebd_destroy",
 ]
@@ -91,12 +95,16 @@ def load() -> ctypes.CDLL:
     lib.hotrg_log_z_chain.argtypes = [c_void_p, P(c_double)]
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
-    lib.hotrg_eig_info.argtypes = [c_void_p, c_int, P(c_int), P(c_int), P(c_double)]
+    lib.hotrg_eig_info.argtypes = [c_void_p, c_int, P(c_int), P(c_int), P(c_double), P(c_int)]
+    lib.hotrg_set_eig_limits.argtypes = [c_void_p, c_int, c_double]
     lib.hotrg_step_sides.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_int)]
     lib.hotrg_observables.argtypes = [c_void_p, P(c_double)]
     lib.hotrg_copy_tensor.argtypes = [c_void_p, P(c_double), c_size_t, P(c_int)]
+    lib.hotrg_copy_environment.argtypes = [c_void_p, P(c_double), c_size_t, P(c_int)]
+    lib.hotrg_copy_isometry.argtypes = [c_void_p, P(c_double), c_size_t, P(c_int)]
     lib.hotrg_set_timing.argtypes = [c_void_p, c_int]
     lib.hotrg_stage_times.argtypes = [c_void_p, P(c_double), P(c_int)]
+    lib.hotrg_step_stage_times.argtypes = [c_void_p, c_int, P(c_double), P(c_int)]
     lib.hotrg_gemm_y_time.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_destroy.argtypes = [c_void_p]
     lib.hotrg_destroy.restype = None
@@ -109,6 +117,9 @@ def load() -> ctypes.CDLL:
     lib.hotrg_gemm_nt.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long,
                                   c_void_p, c_double, c_long, c_long, c_long, c_long, c_long, c_long,
                                   c_void_p, c_void_p]
+    lib.hotrg_gemm_nt_role.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long,
+                                       c_void_p, c_double, c_long, c_long, c_long, c_long, c_long, c_long,
+                                       c_void_p, c_void_p]
     lib.itebd_state_len.argtypes = [c_int]
     lib.itebd_state_len.restype = c_size_t
     lib.itebd_workspace_bytes.argtypes = [c_int, c_int]
@@ -285,12 +296,25 @@ class Solve:
         _check(self._lib.hotrg_observables(self._h, v), "hotrg_observables")
         return {"m": v[0], "e": v[1]}
 
+    def _eig_info(self, n: int):
+        it, sw, r, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+        _check(self._lib.hotrg_eig_info(self._h, int(n), ctypes.byref(it), ctypes.byref(sw), ctypes.byref(r),
+                                        ctypes.byref(st)), "hotrg_eig_info")
+        return it.value, sw.value, r.value, st.value
+
     def eig_info(self, n: int):
         """(subspace passes, Jacobi sweeps, relative residual) of step n's eigensolve."""
-        it, sw, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
-        _check(self._lib.hotrg_eig_info(self._h, int(n), ctypes.byref(it), ctypes.byref(sw), ctypes.byref(r)),
-               "hotrg_eig_info")
-        return it.value, sw.value, r.value
+        return self._eig_info(n)[:3]
+
+    def eig_stop(self, n: int) -> int:
+        """How step n's eigensolve ended: EIG_CONVERGED, EIG_STAGNATED or EIG_PASS_CAP."""
+        return self._eig_info(n)[3]
+
+    def set_eig_limits(self, max_passes: int = 30, fail_residual: float = 1e-6) -> "Solve":
+        """Pass cap and failure bound of the eigensolves enqueued from now on."""
+        _check(self._lib.hotrg_set_eig_limits(self._h, int(max_passes), float(fail_residual)),
+               "hotrg_set_eig_limits")
+        return self
 
     def tensor(self):
         import numpy as np
@@ -302,6 +326,26 @@ class Solve:
                                            out.size, dims), "hotrg_copy_tensor")
         return out
 
+    def environment(self):
+        """The last step's symmetrised left environment E (n x n, FP64)."""
+        import numpy as np
+        n = ctypes.c_int()
+        self._lib.hotrg_copy_environment(self._h, None, 0, ctypes.byref(n))
+        out = np.empty((n.value, n.value), dtype=np.float64)
+        _check(self._lib.hotrg_copy_environment(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                out.size, ctypes.byref(n)), "hotrg_copy_environment")
+        return out
+
+    def isometry(self):
+        """The isometry the last step applied (n x D', as the products used it)."""
+        import numpy as np
+        dims = (ctypes.c_int * 2)()
+        self._lib.hotrg_copy_isometry(self._h, None, 0, dims)
+        out = np.empty((dims[0], dims[1]), dtype=np.float64)
+        _check(self._lib.hotrg_copy_isometry(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             out.size, dims), "hotrg_copy_isometry")
+        return out
+
     def set_timing(self, enable: bool = True):
         _check(self._lib.hotrg_set_timing(self._h, 1 if enable else 0), "hotrg_set_timing")
 
@@ -310,6 +354,17 @@ class Solve:
         n = ctypes.c_int()
         _check(self._lib.hotrg_stage_times(self._h, ms, ctypes.byref(n)), "hotrg_stage_times")
         return dict(zip(STAGES, list(ms))), n.value
+
+    def step_stage_times(self):
+        """Per recorded step: ((Dx, Dy, D'), {stage: ms})."""
+        _, n = self.stage_times()
+        out = []
+        for k in range(n):
+            ms = (ctypes.c_double * len(STAGES))()
+            dims = (ctypes.c_int * 3)()
+            _check(self._lib.hotrg_step_stage_times(self._h, k, ms, dims), "hotrg_step_stage_times")
+            out.append(((dims[0], dims[1], dims[2]), dict(zip(STAGES, list(ms)))))
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
@@ -398,18 +453,29 @@ def coarse_grain_batch(solves, nsteps: int) -> None:
     _check(lib.hotrg_coarse_grain_batch(handles, len(solves), int(nsteps)), "hotrg_coarse_grain_batch")
 
 
-def gemm_nt(A, B, C, M, N, K, lda, ldb, out_map, precision: str = "fp64", alpha: float = 1.0, stream=None):
+ROLES = {"generic": 0, "x": 1, "y": 2, "tp": 3}
+
+
+def gemm_nt(A, B, C, M, N, K, lda, ldb, out_map, precision: str = "fp64", alpha: float = 1.0, stream=None,
+            role: str | None = None, panel: bool = False):
     """Index-mapped product on the device (torch float64 CUDA tensors):
     C[map(m,n)] = alpha * sum_k A[m*lda+k] B[n*ldb+k],
-    out_map = (sm, rs_hi, rs_lo, sn, cs_hi, cs_lo)."""
+    out_map = (sm, rs_hi, rs_lo, sn, cs_hi, cs_lo).  role / panel select the
+    tile choice of one contraction of a step (hotrg_gemm_nt_role)."""
     lib = load()
     prec = PRECISIONS[precision]
     st = stream if stream is not None else torch.cuda.current_stream(C.device)
     nbytes = lib.hotrg_gemm_scratch_bytes(prec, M, N, K)
     scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=C.device) if nbytes else None
     sm, rs_hi, rs_lo, sn, cs_hi, cs_lo = out_map
-    _check(lib.hotrg_gemm_nt(prec, M, N, K, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(B.data_ptr()), ldb,
-                             ctypes.c_void_p(C.data_ptr()), alpha, sm, rs_hi, rs_lo, sn, cs_hi, cs_lo,
-                             ctypes.c_void_p(scratch.data_ptr() if scratch is not None else 0),
-                             ctypes.c_void_p(st.cuda_stream)), "hotrg_gemm_nt")
+    sp = ctypes.c_void_p(scratch.data_ptr() if scratch is not None else 0)
+    if role is None and not panel:
+        _check(lib.hotrg_gemm_nt(prec, M, N, K, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(B.data_ptr()),
+                                 ldb, ctypes.c_void_p(C.data_ptr()), alpha, sm, rs_hi, rs_lo, sn, cs_hi, cs_lo,
+                                 sp, ctypes.c_void_p(st.cuda_stream)), "hotrg_gemm_nt")
+    else:
+        _check(lib.hotrg_gemm_nt_role(prec, ROLES[role or "generic"], 1 if panel else 0, M, N, K,
+                                      ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(B.data_ptr()), ldb,
+                                      ctypes.c_void_p(C.data_ptr()), alpha, sm, rs_hi, rs_lo, sn, cs_hi, cs_lo,
+                                      sp, ctypes.c_void_p(st.cuda_stream)), "hotrg_gemm_nt_role")
     return scratch

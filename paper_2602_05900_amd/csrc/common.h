@@ -106,6 +106,8 @@ struct DevState {
     int r_info[64];
     int r_sweeps[64];
     double r_resid[64];
+    int eig_stop[64];     // how each step's eigensolve ended (HOTRG_EIG_*)
+    int r_eig_stop[64];   // the same for the right environment
     double imp_trace[2];  // sum_{x,y} I[x,x,y,y] of the impurity tensors
     double chain_lnz;     // ln lambda_max of the y-traced tensor (hotrg_log_z_chain)
     int chain_ok;         // 1 if the last normalised square had a positive trace
@@ -122,6 +124,7 @@ struct EigCtl {
     double trace;    // Tr E
     double best;     // smallest residual seen at a convergence check
     int stall;       // consecutive checks that did not bring it below 0.9 best
+    int jac_capped;  // the last Jacobi diagonalisation ended at its sweep cap
 };
 
 constexpr int kEigPMax = 96;   // largest Ritz block / largest fully diagonalised E
@@ -160,9 +163,12 @@ inline int eig_block(int n, int k) {
 // step two earlier with the same (n, p).
 // slot 0 records the diagnostics as the step's own (and eps_left), slot 1 as
 // the right environment's (eps_right, r_*).
+// A solve that stops unconverged with a residual above fail_tol (relative to
+// theta_0), with non-finite eigenvalues, or a dense Jacobi at its sweep cap,
+// latches HOTRG_EEIG in st->status (first error sticks).
 hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
-                           unsigned long long seed, int maxit, double tol, const Buf& Ut, const Buf& Ux,
-                           DevState* st, int step, hipStream_t stream, int slot = 0);
+                           unsigned long long seed, int maxit, double tol, double fail_tol, const Buf& Ut,
+                           const Buf& Ux, DevState* st, int step, hipStream_t stream, int slot = 0);
 
 // Two-sided truncation: when eps_right[step] < eps_left[step], copies the
 // right isometry (UtR, UxR: `bytes` bytes each, 16-byte multiple) over the

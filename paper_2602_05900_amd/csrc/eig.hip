@@ -31,6 +31,7 @@
 // reproducible.
 #include <math.h>
 #include "common.h"
+#include "../../include/hotrg.h"
 
 namespace hotrg {
 
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(256) void eig_init_kernel(const double* __restrict_
             ctl->resid = 0.0;
             ctl->best = 1e300;
             ctl->stall = 0;
+            ctl->jac_capped = 0;
         }
     }
     if (!warm) {
@@ -232,8 +234,8 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
     auto passes = [&](double hij, double hii, double hjj) {
         return hij * hij > 1e-28 * fabs(hii * hjj) && fabs(hij) > 1e-300;
     };
-    int sweeps = 0;
-    for (int sweep = 0; sweep < EIG_MAX_SWEEPS; ++sweep) {
+    int sweeps = 0, capped = 0;
+    for (int sweep = 0;; ++sweep) {
         // A sweep in which no off-diagonal element passes the rotation test
         // below changes nothing; find that out directly (one pass over the
         // upper triangle) instead of by running the sweep's pp - 1 rounds.
@@ -247,6 +249,10 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
         }
         __syncthreads();
         if (!any_rot) break;
+        if (sweep == EIG_MAX_SWEEPS) {   // rotations still pending after the cap
+            capped = 1;
+            break;
+        }
         for (int r = 0; r < pp - 1; ++r) {
             // round-robin pairing: position 0 fixed, positions 1..pp-1 rotate by r
             if (tid < half) {
@@ -340,7 +346,10 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
         const int row = e / p, col = e - (e / p) * p;
         S[(long)row * p + rank[col]] = V[row * EIG_LDP + col];
     }
-    if (tid == 0) ctl->sweeps = sweeps;
+    if (tid == 0) {
+        ctl->sweeps = sweeps;
+        ctl->jac_capped = capped;
+    }
 }
 
 // ---------------------------------------------------------------- Ritz rotation
@@ -636,8 +645,24 @@ __global__ __launch_bounds__(256) void eig_select_kernel(const double* __restric
 }
 
 __global__ __launch_bounds__(64) void eig_stats_kernel(const double* __restrict__ theta, int p, int n, int k,
-                                                       const EigCtl* ctl, DevState* st, int step, int slot) {
+                                                       const EigCtl* ctl, DevState* st, int step, int slot,
+                                                       double fail_tol) {
     if (threadIdx.x != 0 || step >= 64) return;
+    // how the solve ended, and whether it failed: a dense diagonalisation
+    // (p == n) fails only at its sweep cap; a subspace solve that stopped
+    // short of the convergence bound fails when its residual is above
+    // fail_tol (NaN included); non-finite eigenvalues fail either way
+    int stop;
+    bool failed;
+    if (p == n) {
+        stop = ctl->jac_capped ? HOTRG_EIG_PASS_CAP : HOTRG_EIG_CONVERGED;
+        failed = ctl->jac_capped != 0;
+    } else {
+        stop = ctl->converged ? HOTRG_EIG_CONVERGED : (ctl->stall >= 3 ? HOTRG_EIG_STAGNATED : HOTRG_EIG_PASS_CAP);
+        failed = !ctl->converged && !(ctl->resid <= fail_tol);
+    }
+    if (!isfinite(theta[0])) failed = true;
+    if (failed && st->status == 0) st->status = HOTRG_EEIG;
     double err;
     if (p == n) {   // every eigenvalue known: discarded weight summed directly
         double tot = 0.0, dis = 0.0;
@@ -660,6 +685,7 @@ __global__ __launch_bounds__(64) void eig_stats_kernel(const double* __restrict_
         st->info[step] = ctl->iters;
         st->eig_resid[step] = ctl->resid;
         st->eig_sweeps[step] = ctl->sweeps;
+        st->eig_stop[step] = stop;
         st->side[step] = 0;
     } else {
         st->eps_right[step] = err;
@@ -667,6 +693,7 @@ __global__ __launch_bounds__(64) void eig_stats_kernel(const double* __restrict_
         st->r_info[step] = ctl->iters;
         st->r_resid[step] = ctl->resid;
         st->r_sweeps[step] = ctl->sweeps;
+        st->r_eig_stop[step] = stop;
     }
 }
 
@@ -692,6 +719,7 @@ __global__ __launch_bounds__(256) void choose_side_kernel(DevState* st, int step
             st->info[step] = st->r_info[step];
             st->eig_resid[step] = st->r_resid[step];
             st->eig_sweeps[step] = st->r_sweeps[step];
+            st->eig_stop[step] = st->r_eig_stop[step];
         }
     }
 }
@@ -713,14 +741,15 @@ hipError_t launch_choose_side(DevState* st, int step, void* Ut, void* Ux, const 
 }
 
 hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
-                           unsigned long long seed, int maxit, double tol, const Buf& Ut, const Buf& Ux,
-                           DevState* st, int step, hipStream_t stream, int slot) {
-    if (n < 1 || k < 1 || k > n) return hipErrorInvalidValue;
+                           unsigned long long seed, int maxit, double tol, double fail_tol, const Buf& Ut,
+                           const Buf& Ux, DevState* st, int step, hipStream_t stream, int slot) {
+    if (n < 1 || k < 1 || k > n || maxit < 1) return hipErrorInvalidValue;
     if (n <= EIG_PMAX) {
         hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(256), 0, stream, E, n, (double*)nullptr, 0, 1, seed, w.ctl);
         hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(EIG_JT), 0, stream, E, n, n, w.theta, w.S, w.ctl, 0);
         hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, w.S, n, n, dx, k, Ut, Ux);
-        hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, n, n, k, w.ctl, st, step, slot);
+        hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, n, n, k, w.ctl, st, step, slot,
+                           fail_tol);
         return hipGetLastError();
     }
     const int p = eig_block(n, k);
@@ -782,7 +811,8 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
                            seed * 131 + it, w.ctl);
     }
     hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, V, p, n, dx, k, Ut, Ux);
-    hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, p, n, k, w.ctl, st, step, slot);
+    hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, p, n, k, w.ctl, st, step, slot,
+                       fail_tol);
     return hipGetLastError();
 }
 

@@ -99,6 +99,7 @@ struct Layout {
 
 constexpr double kEigTol = 1e-12;
 constexpr int kEigMaxIt = 30;
+constexpr double kEigFailTol = 1e-6;   // unconverged solves above this residual latch HOTRG_EEIG
 
 int step_cap(const hotrg_params* p) { return p->max_steps > 0 ? p->max_steps : HOTRG_MAX_STEPS; }
 
@@ -430,9 +431,13 @@ struct hotrg_solve {
     int warm_nr[2] = {0, 0};  // the same for the right environment (two-sided)
     int warm_pr[2] = {0, 0};
     int imp_slot[2] = {0, 0}; // observable slot of each carried impurity tensor
+    int last_n = 0, last_dp = 0;    // fused-leg size and kept count of the last step
+    int eig_maxit = kEigMaxIt;      // subspace passes per eigensolve
+    double eig_fail = kEigFailTol;  // residual above which an unconverged solve fails
     bool timing = false;
     int timed_from = 0;  // first step recorded with events
     std::vector<hipEvent_t> ev;
+    std::vector<StepDims> timed_dims;  // input dims of each recorded step
 
     DevState* state() const { return reinterpret_cast<DevState*>(ws + L.oState); }
     EigWork eig() const {
@@ -531,6 +536,7 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
     const int dims[4] = {Dx, Dx, Dy, Dy};
     const int step_index = s->steps;
     int rc;
+    if (s->timing && step_index >= s->timed_from) s->timed_dims.push_back({Dx, Dy, Dp});
 
     // -- half environments and E
     // With the split formats and whole 32-row panels, the half-environment
@@ -587,13 +593,13 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
         const int pblk = nE > kEigPMax ? eig_block(nE, Dp) : nE;
         const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)n;
         const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;
-        HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, kEigMaxIt, kEigTol, Ut, Ux,
-                                   s->state(), n, s->stream, 0));
+        HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, s->eig_maxit, kEigTol, s->eig_fail,
+                                   Ut, Ux, s->state(), n, s->stream, 0));
         if (two) {
             const Buf UtR = make_buf(w, L.oUtR, f, L.nU), UxR = make_buf(w, L.oUxR, f, L.nU);
             const bool warm_r = nE > kEigPMax && s->warm_nr[par] == nE && s->warm_pr[par] == pblk;
-            HIP_TRY(s, launch_eig_topk(ER, nE, Dp, Dx, s->eig_right(), par, warm_r, seed, kEigMaxIt,
-                                       kEigTol, UtR, UxR, s->state(), n, s->stream, 1));
+            HIP_TRY(s, launch_eig_topk(ER, nE, Dp, Dx, s->eig_right(), par, warm_r, seed, s->eig_maxit,
+                                       kEigTol, s->eig_fail, UtR, UxR, s->state(), n, s->stream, 1));
             HIP_TRY(s, launch_choose_side(s->state(), n, Ut.ptr, Ux.ptr, UtR.ptr, UxR.ptr, buf_bytes(f, L.nU),
                                           s->stream));
         }
@@ -685,6 +691,8 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
         }
     }
     record(s, step_index, 10);
+    s->last_n = nE;
+    s->last_dp = Dp;
     if (exchange) {
         s->dx = Dy;
         s->dy = Dp;
@@ -702,6 +710,7 @@ int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     initial_dims(p, &s->dx, &s->dy);
     s->steps = 0;
     s->timed_from = 0;
+    s->timed_dims.clear();
     for (int i = 0; i < 2; ++i) s->warm_n[i] = s->warm_p[i] = s->warm_nr[i] = s->warm_pr[i] = 0;
     const size_t count = (size_t)s->dx * s->dx * s->dy * s->dy;
     ModelTensors mt;
@@ -800,6 +809,8 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
     s->fmt = fmt_of(p->precision);
     s->products = products_of(p->precision);
     s->host_status = HOTRG_OK;
+    s->eig_maxit = kEigMaxIt;
+    s->eig_fail = kEigFailTol;
     return upload_initial(s, p);
 }
 
@@ -887,7 +898,7 @@ int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err, doubl
     return HOTRG_OK;
 }
 
-int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual) {
+int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual, int* stop) {
     if (!s || n < 1 || n > s->steps) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     DevState d;
@@ -897,6 +908,15 @@ int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* 
     if (iterations) *iterations = d.info[n];
     if (sweeps) *sweeps = d.eig_sweeps[n];
     if (residual) *residual = d.eig_resid[n];
+    if (stop) *stop = d.eig_stop[n];
+    return HOTRG_OK;
+}
+
+int hotrg_set_eig_limits(hotrg_solve* s, int max_passes, double fail_residual) {
+    if (!s || max_passes < 1 || max_passes > HOTRG_EIG_MAX_PASSES) return HOTRG_EINVAL;
+    if (!(fail_residual > 0.0) || !isfinite(fail_residual)) return HOTRG_EINVAL;
+    s->eig_maxit = max_passes;
+    s->eig_fail = fail_residual;
     return HOTRG_OK;
 }
 
@@ -945,11 +965,71 @@ int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]
     return HOTRG_OK;
 }
 
+int hotrg_copy_environment(hotrg_solve* s, double* host, size_t capacity, int* n) {
+    if (!s || !n) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    *n = s->last_n;
+    const size_t count = (size_t)s->last_n * s->last_n;
+    if (s->steps < 1 || !host || capacity < count) return HOTRG_EINVAL;
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    HIP_TRY(s, hipMemcpyAsync(host, s->ws + s->L.oE, count * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return HOTRG_OK;
+}
+
+int hotrg_copy_isometry(hotrg_solve* s, double* host, size_t capacity, int dims[2]) {
+    if (!s || !dims) return HOTRG_EINVAL;
+    if (s->host_status) return s->host_status;
+    const int n = s->last_n, dp = s->last_dp;
+    dims[0] = n;
+    dims[1] = dp;
+    const size_t count = (size_t)n * dp;
+    if (s->steps < 1 || !host || capacity < count) return HOTRG_EINVAL;
+    DevState d;
+    int rc = read_state(s, &d);
+    if (rc) return rc;
+    if (latched(d)) return latched(d);
+    // Ut[l, i] = u_l[i] in the contraction format: planes of round_up(nU, 64)
+    // elements one after the other
+    const Fmt f = s->fmt;
+    const size_t plane = round_up(std::max<size_t>(s->L.nU, 1), 64);
+    const int planes = fmt_planes(f);
+    const size_t eb = fmt_plane_elem_bytes(f);
+    std::vector<char> raw((size_t)planes * plane * eb);
+    HIP_TRY(s, hipMemcpyAsync(raw.data(), s->ws + s->L.oUt, raw.size(), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    for (int l = 0; l < dp; ++l)
+        for (int i = 0; i < n; ++i) {
+            const size_t e = (size_t)l * n + i;
+            double v = 0.0;
+            if (f == Fmt::F64) {
+                v = reinterpret_cast<const double*>(raw.data())[e];
+            } else if (f == Fmt::F32) {
+                v = reinterpret_cast<const float*>(raw.data())[e];
+            } else {
+                for (int pl = 0; pl < planes; ++pl) {
+                    uint16_t b;
+                    memcpy(&b, raw.data() + ((size_t)pl * plane + e) * 2, 2);
+                    const uint32_t bits = (uint32_t)b << 16;
+                    float x;
+                    memcpy(&x, &bits, 4);
+                    v += x;
+                }
+            }
+            host[(size_t)i * dp + l] = v;
+        }
+    return HOTRG_OK;
+}
+
 int hotrg_set_timing(hotrg_solve* s, int enable) {
     if (!s) return HOTRG_EINVAL;
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     s->ev.clear();
+    s->timed_dims.clear();
     s->timing = enable != 0;
     s->timed_from = s->steps;
     if (s->timing) {
@@ -982,6 +1062,27 @@ int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed) {
         ms[HOTRG_STAGE_TP] += elapsed(s, i, 7, 8);
         ms[HOTRG_STAGE_NORM] += elapsed(s, i, 8, 9);
         ms[HOTRG_STAGE_OBS] += elapsed(s, i, 9, 10);
+    }
+    return HOTRG_OK;
+}
+
+int hotrg_step_stage_times(hotrg_solve* s, int k, double* ms, int dims[3]) {
+    if (!s || !ms || !s->timing || k < 0 || k >= s->steps - s->timed_from || (size_t)k >= s->timed_dims.size())
+        return HOTRG_EINVAL;
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    for (int i = 0; i < HOTRG_NUM_STAGES; ++i) ms[i] = 0.0;
+    ms[HOTRG_STAGE_PERMUTE] = elapsed(s, k, 0, 1) + elapsed(s, k, 3, 4) + elapsed(s, k, 5, 6);
+    ms[HOTRG_STAGE_ENV] = elapsed(s, k, 1, 2);
+    ms[HOTRG_STAGE_EIG] = elapsed(s, k, 2, 3);
+    ms[HOTRG_STAGE_X] = elapsed(s, k, 4, 5);
+    ms[HOTRG_STAGE_Y] = elapsed(s, k, 6, 7);
+    ms[HOTRG_STAGE_TP] = elapsed(s, k, 7, 8);
+    ms[HOTRG_STAGE_NORM] = elapsed(s, k, 8, 9);
+    ms[HOTRG_STAGE_OBS] = elapsed(s, k, 9, 10);
+    if (dims) {
+        dims[0] = s->timed_dims[(size_t)k].dx;
+        dims[1] = s->timed_dims[(size_t)k].dy;
+        dims[2] = s->timed_dims[(size_t)k].dp;
     }
     return HOTRG_OK;
 }
@@ -1038,32 +1139,45 @@ size_t hotrg_gemm_scratch_bytes(int precision, int M, int N, int K) {
     return round_up(buf_bytes(f, (size_t)M * K), 256) + buf_bytes(f, (size_t)N * K);
 }
 
-int hotrg_gemm_nt(int precision, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
-                  double* C, double alpha, long sm, long rs_hi, long rs_lo, long sn, long cs_hi, long cs_lo,
-                  void* scratch, void* stream) {
+int hotrg_gemm_nt_role(int precision, int role, int panel, int M, int N, int K, const double* A, long lda,
+                       const double* B, long ldb, double* C, double alpha, long sm, long rs_hi, long rs_lo, long sn,
+                       long cs_hi, long cs_lo, void* scratch, void* stream) {
     if (M < 0 || N < 0 || K < 0 || sm < 1 || sn < 1 || !C) return HOTRG_EINVAL;
     if (precision < HOTRG_FP64 || precision > HOTRG_BF16X6) return HOTRG_EINVAL;
+    if (role < HOTRG_ROLE_GENERIC || role > HOTRG_ROLE_TP || (panel != 0 && panel != 1)) return HOTRG_EINVAL;
     if (K > 0 && (!A || !B || lda < K || ldb < K)) return HOTRG_EINVAL;
+    const bool split = precision == HOTRG_BF16X3 || precision == HOTRG_BF16X6;
+    if (panel && (!split || M % 32 || N % 32 || K % 16 || K == 0)) return HOTRG_EINVAL;
+    const GemmRole gr = static_cast<GemmRole>(role);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const OutMap mp{sm, rs_hi, rs_lo, sn, cs_hi, cs_lo};
     const Buf Cb{C, Fmt::F64, 0};
     if (precision == HOTRG_FP64) {
         const Buf Ab{const_cast<double*>(A), Fmt::F64, 0}, Bb{const_cast<double*>(B), Fmt::F64, 0};
-        return launch_gemm_nt(Ab, lda, Bb, ldb, Cb, M, N, K, alpha, mp, 1, GemmRole::Generic, st) == hipSuccess
-                   ? HOTRG_OK
-                   : HOTRG_EHIP;
+        return launch_gemm_nt(Ab, lda, Bb, ldb, Cb, M, N, K, alpha, mp, 1, gr, st) == hipSuccess ? HOTRG_OK
+                                                                                              : HOTRG_EHIP;
     }
     if (!scratch || ((uintptr_t)scratch & 255u)) return HOTRG_EINVAL;
     const Fmt f = fmt_of(precision);
     char* base = static_cast<char*>(scratch);
-    const Buf Ab = make_buf(base, 0, f, (size_t)M * K);
-    const Buf Bb = make_buf(base, round_up(buf_bytes(f, (size_t)M * K), 256), f, (size_t)N * K);
+    Buf Ab = make_buf(base, 0, f, (size_t)M * K);
+    Buf Bb = make_buf(base, round_up(buf_bytes(f, (size_t)M * K), 256), f, (size_t)N * K);
+    if (panel) {
+        Ab.panel_k = K;
+        Bb.panel_k = K;
+    }
     if (launch_convert2d(A, lda, M, K, Ab, st) != hipSuccess) return HOTRG_EHIP;
     if (launch_convert2d(B, ldb, N, K, Bb, st) != hipSuccess) return HOTRG_EHIP;
-    return launch_gemm_nt(Ab, K, Bb, K, Cb, M, N, K, alpha, mp, products_of(precision), GemmRole::Generic, st) ==
-                   hipSuccess
+    return launch_gemm_nt(Ab, K, Bb, K, Cb, M, N, K, alpha, mp, products_of(precision), gr, st) == hipSuccess
                ? HOTRG_OK
                : HOTRG_EHIP;
+}
+
+int hotrg_gemm_nt(int precision, int M, int N, int K, const double* A, long lda, const double* B, long ldb,
+                  double* C, double alpha, long sm, long rs_hi, long rs_lo, long sn, long cs_hi, long cs_lo,
+                  void* scratch, void* stream) {
+    return hotrg_gemm_nt_role(precision, HOTRG_ROLE_GENERIC, 0, M, N, K, A, lda, B, ldb, C, alpha, sm, rs_hi, rs_lo,
+                              sn, cs_hi, cs_lo, scratch, stream);
 }
 
 }  // extern "C"
