@@ -17,11 +17,15 @@ terms, 6 products, FP32 accumulation; eigensolve, normalisation and ln Z in
 FP64).  Also reported: the same batch in FP64, per-solve service time
 p50/p99, per-stage GPU times from HIP events, |delta f| against the FP64
 oracle's stored values for these temperatures, the roofline of the dominant
-kernel (the Y product, measured on one solve running alone) and the FP64
-CPU oracle on a bounded sample.  Two further workloads are measured and
-reported beside the headline (not in `value`): a D = 24 FP64 scan of 64
+kernel (the steady-state Y product, 2 D^7 algorithmic FLOPs a launch,
+measured on one solve running alone) and the FP64 CPU oracle on a bounded
+sample.  Further workloads are measured and reported beside the headline
+(not in `value`), each under its own key, where a failure is recorded as
+{"error": ...} without dropping the line: a D = 24 FP64 scan of 64
 temperatures with the finite-difference internal energy against Onsager
-("c2"), and one D = 64, 40-step solve at Tc in BF16x6 and in FP64 ("c5").
+("c2"), served solves under Poisson arrivals ("c4"), one D = 64, 40-step
+solve at Tc in BF16x6 and in FP64 ("c5"), two-sided truncation with
+impurity observables, iTEBD chains and the quantum chain.
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6] [--concurrency C]
 """
@@ -30,9 +34,11 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -48,22 +54,22 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6"
 
 
 def measured_traffic(precision: str, dmax: int, nsteps: int):
-    """HBM bytes per Y launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary of this workload, or None when there is none or when the product
-    kernel's source has changed since the counters were taken."""
+    """HBM bytes per steady-state Y launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary of this workload, or None when there is none or when
+    the product kernel's source has changed since the counters were taken."""
     path = TRAFFIC_PROFILE.get(precision)
     if path is None or dmax != 48 or nsteps != 30 or not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         key, sep, val = line.strip().partition(":")
-        if sep and key in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+        if sep and key in ("traffic_bytes_per_steady_launch", "kernel_source_sha256"):
             fields[key] = val.strip()
     src = os.path.join(ROOT, "paper_2602_05900_amd", "csrc", "gemm.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_steady_launch" not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields["traffic_bytes_per_steady_launch"])
 
 
 def fd_energy(temps, lnz):
@@ -389,7 +395,115 @@ def cpu_baseline(dmax: int, nsteps_sample: int, temperature: float):
     }
 
 
-def main():
+def run_roofline(binding, accounting, precision, dmax, nsteps, temperature):
+    """The dominant kernel, the Y product at steady state (dims D x D x D,
+    2 D^7 algorithmic FLOPs a launch), measured alone: one solve on its own
+    stream with HIP events around every Y launch, averaged over the
+    steady-state launches only (the early, growing steps use other tiles)."""
+    s = binding.Solve(model="ising", q=2, temperature=temperature, dmax=dmax, precision=precision,
+                      max_steps=nsteps)
+    s.set_timing(True)
+    s.coarse_grain(nsteps)
+    s.log_z()
+    per_step = s.step_stage_times()
+    s.close()
+    steady = [ms["y"] for dims, ms in per_step if dims == (dmax, dmax, dmax)]
+    if not steady:
+        return {"error": "no steady-state Y launch in this configuration"}
+    avg = sum(steady) / len(steady)
+    flops = accounting.stage_flops(dmax, dmax, dmax)["y"]
+    achieved = flops / (avg * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    traffic = measured_traffic(precision, dmax, nsteps)
+    return {
+        "kernel": "gemm_nt Y = X . T (the D^7 product), steady-state launch",
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per steady launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_flops_per_launch": flops,
+        "algorithmic_bytes_per_launch": accounting.y_bytes(dmax, dmax, dmax, ELEM_BYTES[precision],
+                                                           Y_OUT_BYTES[precision]),
+        "issued_mfma_products": PRODUCTS[precision],
+        "issued_achieved": achieved * PRODUCTS[precision],
+        "issued_frac": achieved * PRODUCTS[precision] / peak,
+        "launches": len(steady),
+        "avg_launch_ms": avg,
+        "min_launch_ms": min(steady),
+        "max_launch_ms": max(steady),
+        "measured": "HIP events on the solve's stream around each steady-state Y launch of one solve run alone",
+    }
+
+
+def run_c4(serve, accounting, workloads, precision, slots, budget):
+    """Served solves under Poisson arrivals (the serving workload's request
+    mix), time-bounded: a rate below the knee and the overloaded 50 req/s.
+    Requests without a result when the horizon ends are counted and enter
+    the latency percentiles with the time they had waited by then (so those
+    percentiles are lower bounds under overload)."""
+    srv = serve.Server(slots=slots, budget=budget, precision=precision)
+    out = {"workload": "Poisson arrivals; Ising/Potts(q=3) uniform, T ~ U[0.5, 1.5] Tc, D in {16,24,32,48}, "
+                       "20-40 steps, seeded; served with continuous batching",
+           "precision": precision, "slots": slots, "runs": []}
+    for rate, seconds, horizon in ((10.0, 15.0, 30.0), (50.0, 10.0, 20.0)):
+        reqs = workloads.request_stream(rate_hz=rate, duration_s=seconds)
+        offered = sum(accounting.solve_flops(r.q, r.dmax, r.nsteps) for r in reqs) / seconds / 1e12
+
+        def progress(now, done, total, active, queued, rate=rate):
+            print(f"# C4 {rate:g} req/s {now:6.1f} s: {done}/{total} done, {active} active, {queued} queued",
+                  file=sys.stderr, flush=True)
+
+        t0 = time.perf_counter()
+        done = srv.run(reqs, realtime=True, progress=progress, horizon=horizon)
+        wall = time.perf_counter() - t0
+        lat = [c.latency for c in done]
+        waited = lat + [max(horizon - a, 0.0) for _, a in srv.unfinished]
+        service = [c.finished - c.admitted for c in done]
+        out["runs"].append({
+            "rate_hz": rate, "arrival_window_s": seconds, "horizon_s": horizon, "requests": len(reqs),
+            "finished": len(done), "unfinished": len(srv.unfinished), "wall_s": wall,
+            "offered_tflops": offered,
+            "served_tflops": sum(c.flops for c in done) / wall / 1e12,
+            "solves_per_s": len(done) / wall,
+            "p50_latency_s": serve.percentile(lat, 50), "p99_latency_s": serve.percentile(lat, 99),
+            "p50_latency_s_all_requests_lower_bound": serve.percentile(waited, 50),
+            "p99_latency_s_all_requests_lower_bound": serve.percentile(waited, 99),
+            "p50_service_s": serve.percentile(service, 50), "p99_service_s": serve.percentile(service, 99),
+            "peak_footprint_gb": srv.peak_in_use / 2 ** 30,
+        })
+        srv.peak_in_use = srv.in_use
+    return out
+
+
+def run_leg(line, name, fn, *args):
+    """One side measurement: its result, or its error, under its own key, so
+    that a failing leg never drops the benchmark line."""
+    print(f"# {name} ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    try:
+        line[name] = fn(*args)
+    except Exception as e:  # noqa: BLE001 - recorded in the line
+        traceback.print_exc(file=sys.stderr)
+        line[name] = {"error": f"{type(e).__name__}: {e}"}
+    if isinstance(line[name], dict):
+        line[name]["leg_wall_s"] = time.perf_counter() - t0
+
+
+def finite(obj):
+    """The line with every non-finite float replaced by null (strict JSON)."""
+    if isinstance(obj, float):
+        return obj if math.isfinite(obj) else None
+    if isinstance(obj, dict):
+        return {k: finite(v) for k, v in obj.items()}
+    if isinstance(obj, (list, tuple)):
+        return [finite(v) for v in obj]
+    return obj
+
+
+def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16, help="timed solves")
@@ -404,12 +518,13 @@ def main():
     ap.add_argument("--concurrency", type=int, default=4, help="solves in flight (streams)")
     ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
     ap.add_argument("--no-c2", dest="c2", action="store_false", help="skip the D=24 temperature scan")
+    ap.add_argument("--no-c4", dest="c4", action="store_false", help="skip the served Poisson stream")
     ap.add_argument("--no-c5", dest="c5", action="store_false", help="skip the D=64 solve")
     ap.add_argument("--no-observables", dest="observables", action="store_false",
                     help="skip the two-sided / impurity-observable runs")
     ap.add_argument("--no-itebd", dest="itebd", action="store_false", help="skip the iTEBD runs")
     ap.add_argument("--no-qchain", dest="qchain", action="store_false", help="skip the quantum-chain HOTRG runs")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
 
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU: the path has no multi-GPU mode, so --gpus must be 1",
@@ -423,9 +538,6 @@ def main():
     torch.cuda.set_device(dev)
     temps = workloads.temperature_grid(2.0, 2.5, 16)
     flops_solve = accounting.solve_flops(2, args.dmax, args.nsteps)
-    dims = accounting.step_dims(2, 2, args.dmax, args.nsteps)
-    y_flops = sum(accounting.stage_flops(*d)["y"] for d in dims)
-    y_bytes = sum(accounting.y_bytes(*d, ELEM_BYTES[args.precision], Y_OUT_BYTES[args.precision]) for d in dims)
 
     def batch(first, count):
         return [workloads.Request(rid=first + i, arrival=0.0, model="ising", q=2,
@@ -435,45 +547,30 @@ def main():
     def progress(now, done, total, active, queued):
         print(f"# {now:6.1f} s: {done}/{total} solves done, {active} active", file=sys.stderr, flush=True)
 
-    def run_batch(precision, concurrency, first, count, warmup):
+    def run_batch(precision, concurrency, warm_reqs, reqs):
         server = serve.Server(slots=concurrency, budget=args.budget_gb << 30, precision=precision,
                               device="cuda:0", timing=True)
-        if warmup:
-            server.run(batch(first, warmup), realtime=False)
+        if warm_reqs:
+            server.run(warm_reqs, realtime=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        done = server.run(batch(first + warmup, count), realtime=False, progress=progress)
+        done = server.run(reqs, realtime=False, progress=progress)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         stage = {k: 0.0 for k in binding.STAGES}
         for c in done:
-            for k, v in c.stage_ms.items():
+            for k, v in (c.stage_ms or {}).items():
                 stage[k] += v
-        print(f"# {precision}: {count} solves, {concurrency} in flight, {wall:.2f} s", file=sys.stderr, flush=True)
+        print(f"# {precision}: {len(reqs)} solves, {concurrency} in flight, {wall:.2f} s", file=sys.stderr,
+              flush=True)
         return done, wall, stage
 
-    done, wall, stage_sum = run_batch(args.precision, args.concurrency, 0, args.steps, args.warmup)
+    # the timed batch: solves warmup .. warmup + steps - 1 of the temperature cycle
+    warm_reqs, timed_reqs = batch(0, args.warmup), batch(args.warmup, args.steps)
+    done, wall, stage_sum = run_batch(args.precision, args.concurrency, warm_reqs, timed_reqs)
     for c in done:
-        print(f"# solve T={c.temperature:.4f} lnZ/N={c.lnz_per_site:.15f} service {1e3 * (c.finished - c.admitted):.1f} ms",
-              file=sys.stderr, flush=True)
-
-    # the dominant kernel measured alone: one solve on one stream, events around each Y launch
-    iso, iso_wall, iso_stage = run_batch(args.precision, 1, 0, 1, 0)
-    y_ms = iso_stage["y"]
-    achieved = y_flops / (y_ms * 1e-3) / 1e12 if y_ms > 0 else None
-    peak = PEAK_TFLOPS[args.precision]
-    hw_achieved = achieved * PRODUCTS[args.precision] if achieved else None
-
-    cmp = None
-    if args.compare_fp64 and args.precision != "fp64":
-        fdone, fwall, _ = run_batch("fp64", args.concurrency, 0, args.steps, 1)
-        fl = {c.rid: c.lnz_per_site for c in fdone}
-        cmp = {
-            "fp64_value": flops_solve * args.steps / fwall / 1e12,
-            "fp64_ms_per_step": fwall / args.steps * 1e3,
-            "speedup_vs_fp64": fwall / wall,
-            "max_rel_df_vs_gpu_fp64": max(abs(c.lnz_per_site - fl[c.rid]) / abs(fl[c.rid]) for c in done),
-        }
+        print(f"# solve T={c.temperature:.4f} lnZ/N={c.lnz_per_site:.15f} service "
+              f"{1e3 * (c.finished - c.admitted):.1f} ms", file=sys.stderr, flush=True)
 
     total_flops = flops_solve * args.steps
     value = total_flops / wall / 1e12
@@ -518,54 +615,53 @@ def main():
         "p50_solve_ms": serve.percentile(service, 50) * 1e3,
         "p99_solve_ms": serve.percentile(service, 99) * 1e3,
         "p50_batch_latency_ms": serve.percentile(latency, 50) * 1e3,
+        "p99_batch_latency_ms": serve.percentile(latency, 99) * 1e3,
         "solves_per_s": args.steps / wall,
         "stage_ms_per_solve": {k: v / args.steps for k, v in stage_sum.items()},
-        "isolated_solve_stage_ms": iso_stage,
-        "isolated_solve_ms": iso_wall * 1e3,
         "contraction_kernel_tflops": total_flops / (contraction_ms * 1e-3) / 1e12 if contraction_ms else None,
-        "roofline": {
-            "kernel": "gemm_nt (Y = X . T, the D^7 product)",
-            "bound": "mfma",
-            "achieved": hw_achieved,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": hw_achieved / peak if hw_achieved else None,
-            "traffic": measured_traffic(args.precision, args.dmax, args.nsteps),
-            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": y_bytes / args.nsteps,
-            "algorithmic_flops_per_solve": y_flops,
-            "hardware_flops_factor": PRODUCTS[args.precision],
-            "measured": "HIP events around each Y launch of one solve run alone on its stream",
-            "launches": args.nsteps,
-            "avg_launch_ms": y_ms / args.nsteps,
-            "timed_region_avg_launch_ms": stage_sum["y"] / (args.nsteps * args.steps),
-        },
         "lnz_per_site": {f"{c.temperature:.6f}": c.lnz_per_site for c in done},
         "rel_err_vs_fp64_oracle": errs or None,
-        "fp64_comparison": cmp,
+        "max_rel_err_vs_fp64_oracle": max(errs.values()) if errs else None,
     }
+    run_leg(line, "roofline", run_roofline, binding, accounting, args.precision, args.dmax, args.nsteps,
+            float(temps[0]))
+
+    if args.compare_fp64 and args.precision != "fp64":
+        def fp64_comparison():
+            # the same requests (same temperatures) as the timed batch, one warm-up solve first
+            fdone, fwall, _ = run_batch("fp64", args.concurrency, batch(0, 1), timed_reqs)
+            fl = {c.rid: c.lnz_per_site for c in fdone}
+            out = {
+                "fp64_value": flops_solve * args.steps / fwall / 1e12,
+                "fp64_ms_per_step": fwall / args.steps * 1e3,
+                "speedup_vs_fp64": fwall / wall,
+                "max_rel_df_vs_gpu_fp64": max(abs(c.lnz_per_site - fl[c.rid]) / abs(fl[c.rid]) for c in done),
+            }
+            ferr = [abs(c.lnz_per_site - ref[round(c.temperature, 9)]) / abs(ref[round(c.temperature, 9)])
+                    for c in fdone if round(c.temperature, 9) in ref]
+            if ferr:
+                out["fp64_max_rel_err_vs_fp64_oracle"] = max(ferr)
+            return out
+        run_leg(line, "fp64_comparison", fp64_comparison)
     if args.c2:
-        print("# C2: D=24 scan ...", file=sys.stderr, flush=True)
-        line["c2"] = run_c2(serve, accounting, workloads, args.budget_gb << 30)
+        run_leg(line, "c2", run_c2, serve, accounting, workloads, args.budget_gb << 30)
+    if args.c4:
+        run_leg(line, "c4", run_c4, serve, accounting, workloads, args.precision, 8, 160 << 30)
     if args.c5:
-        print("# C5: D=64 ...", file=sys.stderr, flush=True)
-        line["c5"] = run_c5(binding, accounting)
+        run_leg(line, "c5", run_c5, binding, accounting)
     if args.observables:
-        print("# observables: two-sided, m and e impurities ...", file=sys.stderr, flush=True)
-        line["observables"] = run_observables(binding, accounting)
+        run_leg(line, "observables", run_observables, binding, accounting)
     if args.itebd:
-        print("# iTEBD: Heisenberg chains ...", file=sys.stderr, flush=True)
-        from paper_2602_05900_amd import workloads as wl
-        line["itebd"] = run_itebd(binding, wl)
+        run_leg(line, "itebd", run_itebd, binding, workloads)
     if args.qchain:
-        print("# quantum chain HOTRG ...", file=sys.stderr, flush=True)
-        from paper_2602_05900_amd import workloads as wl
-        line["qchain"] = run_qchain(binding, wl)
+        run_leg(line, "qchain", run_qchain, binding, workloads)
     if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))
-        line["cpu_baseline"]["chains"] = cpu_baseline_chains()
-    print(json.dumps(line), flush=True)
+        def cpu():
+            out = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))
+            out["chains"] = cpu_baseline_chains()
+            return out
+        run_leg(line, "cpu_baseline", cpu)
+    print(json.dumps(finite(line)), flush=True)
 
 
 if __name__ == "__main__":

@@ -169,18 +169,26 @@ class Server:
                 still.append(a)
         self.active = still
 
-    def run(self, requests, realtime: bool = True, progress=None) -> list[Completed]:
+    def run(self, requests, realtime: bool = True, progress=None, horizon: float | None = None) -> list[Completed]:
         """Serve `requests` (objects with rid, arrival, model, q, temperature,
         dmax, nsteps).  realtime: requests become visible at their arrival
-        time; otherwise all are queued at once (a closed batch)."""
+        time; otherwise all are queued at once (a closed batch).  horizon:
+        stop serving that many seconds after the start; solves still in
+        flight are then drained and released without a result, and
+        `self.unfinished` holds the (rid, arrival) of every request without
+        one (in flight, queued or not yet arrived)."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         self.t0 = time.perf_counter()
+        self.unfinished = []
         i = 0
         n_total = len(reqs)
         n_before = len(self.done)
         last_report = 0.0
         while len(self.done) - n_before < n_total:
             now = self._now()
+            if horizon is not None and now >= horizon:
+                self._abandon(reqs[i:])
+                break
             while i < n_total and (not realtime or reqs[i].arrival <= now):
                 self.queue.append(reqs[i])
                 i += 1
@@ -194,6 +202,21 @@ class Server:
                 time.sleep(0.0002)
         torch.cuda.synchronize(self.device)
         return sorted(self.done[n_before:], key=lambda c: c.rid)
+
+    def _abandon(self, not_arrived):
+        """End of a horizon: wait for the enqueued work of the solves in
+        flight, release them and forget the queue."""
+        torch.cuda.synchronize(self.device)
+        for a in self.active:
+            self.unfinished.append((a.req.rid, a.req.arrival))
+            a.solve.close()
+            self.in_use -= a.footprint
+            self.free_streams.append(a.slot)
+            del a.workspace
+        self.active = []
+        self.unfinished += [(r.rid, r.arrival) for r in self.queue]
+        self.queue.clear()
+        self.unfinished += [(r.rid, r.arrival) for r in not_arrived]
 
 
 def percentile(xs, p):
