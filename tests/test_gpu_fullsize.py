@@ -1,0 +1,215 @@
+"""GPU parity at the benchmark's full sizes (D = 48, and D = 64 for the
+large-bond workload) against the FP64 oracle.
+
+* Whole solves: D = 48, 30 steps, at all 16 benchmark temperatures, against
+  the oracle's ln Z/N stored in tests/golden/oracle_ising_d48.json (written by
+  tests/golden/make_golden_d48.py from oracle/ only): FP64 to 1e-12 relative,
+  BF16x6 to its 1e-6 claim; FP32 and BF16x3 at four of them to their claims.
+  D = 64: the first 10 steps (full-size steps from step 7) against
+  tests/golden/oracle_ising_d64.json (ln Z/N and every c_n to 1e-12).
+* One full-size step, element by element, from the GPU's own input tensor
+  (Ising T = 2.25, step 9, dims 48 x 48 -> 48): the environment E against the
+  oracle's; the kept projector U U^T against the oracle's, within the
+  Davis-Kahan bound set by the GPU eigensolver's residual and the oracle's
+  gap at the cut (every entry of the difference of two rank-k projectors is
+  at most sqrt(2) |sin Theta|_2 <= sqrt(2) |R|_F / gap, with the residual
+  matrix |R|_F <= sqrt(k) max_j |E u_j - theta_j u_j|); and the next tensor
+  against the oracle's projection of the same input with the GPU's own
+  isometry, which makes the comparison of the X, Y and T' products
+  independent of any eigenvalue gap.
+* The Y product kernel the benchmark times (BF16x6, 256 x 256 tiles, panel
+  operands) at the D = 48 shape M = 110592, N = K = 2304, and at a ragged
+  shape, on sampled rows against NumPy.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact, hotrg as oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CLAIM = {"fp64": 1e-12, "bf16x6": 1e-6, "fp32": 1e-6, "bf16x3": 1e-5}
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def golden_d48():
+    return json.load(open(os.path.join(GOLDEN, "oracle_ising_d48.json")))["rows"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
+def test_d48_30_steps_all_benchmark_temperatures(gpu_lib, precision):
+    """The benchmark's workload, solve by solve, against the stored oracle."""
+    from paper_2602_05900_amd import binding
+    rows = golden_d48()
+    assert len(rows) == 16
+    s = None
+    worst = 0.0
+    for r in rows:
+        T = r["temperature"]
+        kw = dict(model="ising", q=2, temperature=T, dmax=48, precision=precision, max_steps=30)
+        s = binding.Solve(**kw) if s is None else s.reset(**kw)
+        s.coarse_grain(30)
+        e = rel(-T * s.log_z(), r["free_energy"])
+        print(f"{precision} T={T:.6f} |df|/|f| = {e:.2e}")
+        worst = max(worst, e)
+        assert e <= CLAIM[precision], (T, e)
+    s.close()
+    print(f"{precision}: max |df|/|f| over 16 temperatures = {worst:.2e}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_d48_30_steps_other_precisions(gpu_lib, precision):
+    from paper_2602_05900_amd import binding
+    rows = golden_d48()
+    s = None
+    for r in rows[::5]:
+        T = r["temperature"]
+        kw = dict(model="ising", q=2, temperature=T, dmax=48, precision=precision, max_steps=30)
+        s = binding.Solve(**kw) if s is None else s.reset(**kw)
+        s.coarse_grain(30)
+        e = rel(-T * s.log_z(), r["free_energy"])
+        print(f"{precision} T={T:.6f} |df|/|f| = {e:.2e}")
+        assert e <= CLAIM[precision], (T, e)
+    s.close()
+
+
+def test_d64_first_10_steps_against_oracle(gpu_lib):
+    """Ising at Tc, D = 64 (environments n = 4096 from step 7 on): ln Z/N of
+    the 2^10-site torus and every c_n against the stored oracle run."""
+    from paper_2602_05900_amd import binding
+    g = json.load(open(os.path.join(GOLDEN, "oracle_ising_d64.json")))
+    n = g["nsteps"]
+    s = binding.Solve(model="ising", q=2, temperature=g["temperature"], dmax=64, precision="fp64", max_steps=n)
+    s.coarse_grain(n)
+    lnz = s.log_z()
+    print(f"D=64 {n} steps: gpu {lnz:.16f} oracle {g['lnz_per_site']:.16f} rel {rel(lnz, g['lnz_per_site']):.2e}")
+    assert rel(lnz, g["lnz_per_site"]) <= 1e-12
+    for k in range(n + 1):
+        c, err, _ = s.step_info(k)
+        assert rel(c, g["c"][k]) <= 1e-12, k
+        if k:
+            assert abs(err - g["trunc_err"][k - 1]) <= 1e-8 * g["trunc_err"][k - 1] + 1e-14, k
+    for k in range(5, n + 1):   # n = 256, 1024, 4096, ...: subspace iteration
+        it, _, res = s.eig_info(k)
+        assert res <= 1e-12 and it > 0, (k, it, res)
+    s.close()
+
+
+# ------------------------------------------------------------------ one full-size step
+
+T_STEP, N_BEFORE = 2.25, 8       # step 9 at T = 2.25: the oracle's cut gap is 5.1e-6 there
+
+
+@pytest.fixture(scope="module")
+def d48_input(gpu_lib):
+    """The GPU's own FP64 tensor after 8 steps (dims 48 x 48)."""
+    from paper_2602_05900_amd import binding
+    s = binding.Solve(model="ising", q=2, temperature=T_STEP, dmax=48, max_steps=N_BEFORE)
+    s.coarse_grain(N_BEFORE)
+    Tin = s.tensor()
+    s.close()
+    assert Tin.shape == (48, 48, 48, 48)
+    E_ref = oracle.environment(Tin)
+    tr = oracle.truncation(E_ref, 48)
+    return Tin, E_ref, tr
+
+
+def step_from(Tin, precision):
+    from paper_2602_05900_amd import binding
+    s = binding.Solve(model="custom", tensor=Tin, dmax=48, temperature=1.0, precision=precision, max_steps=1)
+    s.coarse_grain(1)
+    out = dict(E=s.environment(), U=s.isometry(), T=s.tensor(), info=s.eig_info(1), c=s.step_info(1)[0])
+    s.close()
+    return out
+
+
+def projected_next(Tin, U):
+    """The oracle's next tensor for the input Tin and a given isometry U."""
+    _, Tp = oracle.project(Tin, U)
+    c = float(np.max(np.abs(Tp)))
+    return np.ascontiguousarray((Tp / c).transpose(2, 3, 0, 1)), c
+
+
+def test_d48_step_fp64_elementwise(d48_input):
+    Tin, E_ref, tr = d48_input
+    assert tr.cut_gap > 1e-6, tr.cut_gap          # the premise of the projector bound below
+    g = step_from(Tin, "fp64")
+    # S1, S2: the environment, every entry
+    scale = np.max(np.abs(E_ref))
+    dE = np.max(np.abs(g["E"] - E_ref)) / scale
+    print(f"E: max |dE| / max |E| = {dE:.2e}")
+    assert dE <= 1e-12
+    # S3: the kept subspace, within the Davis-Kahan bound
+    it, _, res = g["info"]
+    U, Ur = g["U"], tr.U
+    assert U.shape == Ur.shape == (2304, 48)
+    assert np.max(np.abs(U.T @ U - np.eye(48))) <= 1e-12
+    dP = np.max(np.abs(U @ U.T - Ur @ Ur.T))
+    bound = math.sqrt(2.0) * math.sqrt(48) * (res + 1e-15) / tr.cut_gap + 1e-13
+    print(f"projector: max |dP| = {dP:.2e}, bound {bound:.2e} (residual {res:.1e}, {it} passes, gap {tr.cut_gap:.1e})")
+    assert dP <= bound
+    # kept eigenvalue weight: the truncation error of the step
+    # S4-S7: X, Y, T' and c_n with the GPU's own isometry
+    Tn_ref, c_ref = projected_next(Tin, U)
+    assert rel(g["c"], c_ref) <= 1e-12
+    dT = np.max(np.abs(g["T"] - Tn_ref))
+    print(f"T': max |dT| = {dT:.2e} (max |T'| = 1)")
+    assert dT <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol_e,tol_t", [("bf16x6", 2e-6, 2e-5), ("fp32", 2e-6, 2e-5),
+                                                   ("bf16x3", 2e-4, 5e-4)])
+def test_d48_step_reduced_precision_elementwise(d48_input, precision, tol_e, tol_t):
+    """The same step with the contractions in a reduced precision: E and the
+    next tensor (with the GPU's own isometry, as the products used it) to the
+    precision's level, relative to their largest entries."""
+    Tin, E_ref, _ = d48_input
+    g = step_from(Tin, precision)
+    dE = np.max(np.abs(g["E"] - E_ref)) / np.max(np.abs(E_ref))
+    Tn_ref, c_ref = projected_next(Tin, g["U"])
+    dT = np.max(np.abs(g["T"] - Tn_ref))
+    print(f"{precision}: max |dE|/max|E| = {dE:.2e}, max |dT'| = {dT:.2e}, c rel {rel(g['c'], c_ref):.2e}")
+    assert dE <= tol_e
+    assert rel(g["c"], c_ref) <= tol_t
+    assert dT <= tol_t
+
+
+# ------------------------------------------------------------------ the timed Y kernel
+
+@pytest.mark.parametrize("M,N,K", [(110592, 2304, 2304), (110560, 2272, 2288)])
+def test_y_kernel_at_benchmark_shape_sampled_rows(gpu_lib, M, N, K):
+    """BF16x6 Y product, panel operands, 256 x 256 tiles (the benchmark's
+    timed kernel), against NumPy on sampled rows: every tile row band, the
+    first and last rows, and random rows; bound as for the unit tests of the
+    product (3-term BF16 split, FP32 accumulation: 24 significant bits)."""
+    import torch
+    from paper_2602_05900_amd import binding
+    rng = np.random.default_rng(M + N + K)
+    A = torch.empty((M, K), dtype=torch.float64, device="cuda").normal_(generator=torch.Generator("cuda").manual_seed(1))
+    B = torch.from_numpy(rng.standard_normal((N, K))).cuda()
+    C = torch.full((M * N,), float("nan"), dtype=torch.float64, device="cuda")
+    binding.gemm_nt(A, B, C, M, N, K, K, K, (1, N, 0, 1, 1, 0), precision="bf16x6", role="y", panel=True)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([np.arange(0, M, 256), np.arange(255, M, 256)[:8], [M - 1],
+                                     rng.integers(0, M, 256)]))
+    idx = torch.from_numpy(rows).cuda()
+    Ar = A[idx].cpu().numpy()
+    Cr = C.view(M, N)[idx].cpu().numpy()
+    Bn = B.cpu().numpy()
+    ref = Ar @ Bn.T
+    absdot = np.abs(Ar) @ np.abs(Bn).T
+    bound = (2.0 + 8.0 * math.sqrt(K)) * 2.0 ** -24 * absdot
+    assert np.all(np.isfinite(Cr))
+    worst = float(np.max(np.abs(Cr - ref) / bound))
+    print(f"Y kernel {M}x{N}x{K}: {len(rows)} rows, worst error / bound = {worst:.3f}")
+    assert worst <= 1.0
+    del A, B, C
+    torch.cuda.empty_cache()
