@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(PKG, "libhotrg.so")
 OK, EINVAL, ENOMEM, EHIP, EEIG, ENONFINITE, ESTATE, ENODEV = 0, -1, -2, -3, -4, -5, -6, -7
 # models and precisions
 ISING, POTTS, CUSTOM, QCHAIN = 0, 1, 2, 3
-FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+FP64, FP32, BF16X3, BF16X6, FP16X3 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6, "fp16x3": FP16X3}
 MODELS = {"ising": ISING, "potts": POTTS, "custom": CUSTOM, "qchain": QCHAIN}
 MAX_STEPS = 60
 # how a step's eigensolve ended (hotrg_eig_info)
@@ -310,7 +310,7 @@ class Solve:
         """How step n's eigensolve ended: EIG_CONVERGED, EIG_STAGNATED or EIG_PASS_CAP."""
         return self._eig_info(n)[3]
 
-    def set_eig_limits(self, max_passes: int = 30, fail_residual: float = 1e-6) -> "Solve":
+    def set_eig_limits(self, max_passes: int = 30, fail_residual: float = 5e-2) -> "Solve":
         """Pass cap and failure bound of the eigensolves enqueued from now on."""
         _check(self._lib.hotrg_set_eig_limits(self._h, int(max_passes), float(fail_residual)),
                "hotrg_set_eig_limits")

@@ -11,6 +11,7 @@ namespace hotrg {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Storage format of contraction operands and intermediates.
 enum class Fmt : int {
@@ -18,9 +19,12 @@ enum class Fmt : int {
     F32 = 1,      // float
     BF16x2 = 2,   // two bf16 planes: hi, lo (value ~ hi + lo)
     BF16x3 = 3,   // three bf16 planes: hi, mid, lo
+    F16x2 = 4,    // two fp16 planes: hi, lo of the value times a power-of-two scale
 };
 
-inline int fmt_planes(Fmt f) { return f == Fmt::BF16x2 ? 2 : (f == Fmt::BF16x3 ? 3 : 1); }
+inline int fmt_planes(Fmt f) {
+    return f == Fmt::BF16x2 || f == Fmt::F16x2 ? 2 : (f == Fmt::BF16x3 ? 3 : 1);
+}
 inline size_t fmt_plane_elem_bytes(Fmt f) { return f == Fmt::F64 ? 8 : (f == Fmt::F32 ? 4 : 2); }
 inline size_t fmt_elem_bytes(Fmt f) { return fmt_plane_elem_bytes(f) * fmt_planes(f); }
 
@@ -46,7 +50,16 @@ struct Buf {
     long panel_k = 0;  // 0: row-major; else the row length of the panel layout
     long cols = 0;     // 0: dense; else the column count of a sub-block
     long ld = 0;       // row stride of a row-major sub-block (cols != 0, panel_k == 0)
+    float scale = 1.f; // F16x2 writers store the planes of value * scale (a power of two)
 };
+
+// FP16 two-plane split of f (already scaled): hi = fp16(f), lo = fp16(f - hi),
+// both by round-to-nearest-even; f - hi is exact in FP32.
+__device__ __forceinline__ void f16_split(float f, _Float16* hi, _Float16* lo) {
+    const _Float16 h = (_Float16)f;
+    *hi = h;
+    *lo = (_Float16)(f - (float)h);
+}
 
 __host__ __device__ inline long panel_index(long r, long c, long panel_k) {
     return ((r >> 5) * (panel_k >> 4) + (c >> 4)) * 512 + (r & 31) * 16 + (c & 15);
@@ -194,6 +207,14 @@ hipError_t launch_symmetrize(double* E, int n, hipStream_t stream);
 }  // namespace hotrg
 
 namespace hotrg {
+// The stand-alone product of the C ABI (hotrg_gemm_nt_role) with its operand
+// conversion into `scratch` (scratch_bytes available; ENOMEM when the
+// conversion needs more), and the bytes that conversion needs.
+size_t gemm_scratch_bytes(int precision, int M, int N, int K);
+int gemm_nt_with_scratch(int precision, int role, int panel, int M, int N, int K, const double* A, long lda,
+                         const double* B, long ldb, double* C, double alpha, long sm, long rs_hi, long rs_lo, long sn,
+                         long cs_hi, long cs_lo, void* scratch, size_t scratch_bytes, void* stream);
+
 // out[r, c] = in[r * ld + c] for r < rows, c < cols, converted to out's format
 // (dense, row length cols).
 hipError_t launch_convert2d(const double* in, long ld, int rows, int cols, const Buf& out,

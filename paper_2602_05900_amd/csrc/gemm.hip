@@ -130,6 +130,11 @@ struct Store {
             case (int)Fmt::F64: static_cast<double*>(ptr)[off] = alpha * (double)v; break;
             case (int)Fmt::F32: static_cast<float*>(ptr)[off] = (float)(alpha * (double)v); break;
             case (int)Fmt::BF16x2: split_store(static_cast<__bf16*>(ptr), plane, 2, off, (float)(alpha * (double)v)); break;
+            case (int)Fmt::F16x2: {
+                _Float16* p = static_cast<_Float16*>(ptr);
+                f16_split((float)(alpha * (double)v), p + off, p + off + plane);
+                break;
+            }
             default: split_store(static_cast<__bf16*>(ptr), plane, 3, off, (float)(alpha * (double)v)); break;
         }
     }
@@ -612,7 +617,22 @@ __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA, bool PB, int NST, int MINW>
+// One 32x32x16 product on the matrix cores, BF16 or FP16 operands (the
+// operand vectors are 8 two-byte values either way; F16 reinterprets them).
+template <bool F16>
+__device__ __forceinline__ void mfma_32x32x16(const bf16x8& a, const bf16x8& b,
+                                              float __attribute__((ext_vector_type(16)))& acc) {
+    if constexpr (F16)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), acc,
+                                                     0, 0, 0);
+    else
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+}
+
+// F16: the operand planes are FP16 (hi, lo of the value times a power of two;
+// NPROD 3: hi*hi + hi*lo + lo*hi) instead of BF16.
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA, bool PB, int NST, int MINW,
+          bool F16 = false>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, MINW)
 void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
                             const __bf16* __restrict__ B, long ldb, long b_plane,
@@ -746,9 +766,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[SP::a(pr)][i], b[SP::b(pr)][j], acc[i][j],
-                                                                        0, 0, 0);
+                for (int j = 0; j < FN; ++j) mfma_32x32x16<F16>(a[SP::a(pr)][i], b[SP::b(pr)][j], acc[i][j]);
     };
 
     // K steps padded to a multiple of NST (the padding steps load zeros), so
@@ -850,6 +868,67 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             return;
         }
     }
+    // FP16-plane outputs (F16x2: hi, lo of alpha * acc, the scale being part
+    // of alpha), from BF16 operands: the same 16-row slab staging as above
+    // with two 2-byte planes.
+    constexpr int REG3 = 2 * SLAB;
+    constexpr int PER_ARRAY3 = STAGE / REG3;
+    if constexpr (PER_ARRAY3 > 0 && NW <= PER_ARRAY3 * NST) {
+        if (vec_out == 3) {
+            typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+            constexpr int CPR = WN / 8;
+            constexpr int NCH = 16 * CPR;
+            static_assert(NCH % 64 == 0, "whole chunks per lane");
+            constexpr int CPL = NCH / 64;
+            __syncthreads();   // every wave is done reading the stages
+            const int ar = wave / PER_ARRAY3;
+            _Float16* reg = reinterpret_cast<_Float16*>(ar == 0 ? S0 : (ar == 1 ? S1 : S2)) +
+                            (wave - ar * PER_ARRAY3) * REG3;
+            _Float16* outp = static_cast<_Float16*>(store.ptr);
+            const long pstride = (long)store.plane;
+            MapPart ccol[CPL];
+            bool cok[CPL];
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = lane + 64 * t;
+                const int n = ncol(wn * WN + (c % CPR) * 8);
+                cok[t] = n < N;
+                ccol[t] = cok[t] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+#pragma unroll
+                        for (int rr = 0; rr < 8; ++rr) {
+                            const int r = 8 * h + rr;
+                            const int row = 8 * (rr >> 2) + 4 * fk + (rr & 3);
+                            _Float16* dst = reg + row * RW + j * 32 + frow;
+                            f16_split((float)(store.alpha * (double)acc[i][j][r]), dst, dst + SLAB);
+                        }
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's staging writes are done
+#pragma unroll
+                    for (int t = 0; t < CPL; ++t) {
+                        const int c = lane + 64 * t;
+                        const int row = c / CPR;
+                        const int m = m0 + wm * WM + i * 32 + 16 * h + row;
+                        if (cok[t] && m < M) {
+                            const long off = map_off(mp, map_row(mp, (unsigned)m), ccol[t]);
+                            const _Float16* src = reg + row * RW + (c % CPR) * 8;
+#pragma unroll
+                            for (int pl = 0; pl < 2; ++pl)
+                                *reinterpret_cast<u4*>(outp + pl * pstride + off) =
+                                    *reinterpret_cast<const u4*>(src + pl * SLAB);
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // staging reads are done before the region is rewritten
+                }
+            }
+            return;
+        }
+    }
     // FP32 outputs (a product whose consumer splits its operand on load):
     // the same 16-row slab staging with one 4-byte plane, 16-byte stores of
     // 4 columns.  The value stored is the one the plane split above starts
@@ -931,7 +1010,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
 }
 
 template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int ROLE, bool PA = false, bool PB = false, int NST = 3,
-          int MINW = 1>
+          int MINW = 1, bool F16 = false>
 static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
                                const Store& st, const OutMap& mp, hipStream_t stream, int ngrp = 0)
 {
@@ -950,13 +1029,18 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
     if (HOTRG_F32_STAGED && !vec_out && st.fmt == (int)Fmt::F32 && mp.panel_k == 0 && mp.cs_lo == 1 && mp.rs_hi % 4 == 0 &&
         mp.rs_lo % 4 == 0 && mp.cs_hi % 4 == 0 && mp.sn % 4 == 0 && N % 4 == 0 && ((uintptr_t)st.ptr & 15) == 0)
         vec_out = 2;
+    // FP16 planes from BF16 operands (the X product feeding an FP16 Y)
+    if (!vec_out && !F16 && st.fmt == (int)Fmt::F16x2 && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 &&
+        st.plane % 8 == 0 && ((uintptr_t)st.ptr & 15) == 0)
+        vec_out = 3;
+    if (F16 && vec_out == 1) vec_out = 0;   // the BF16-plane staging does not apply to FP16 operands
     const int tiles_m = (M + BM - 1) / BM;
     const int tiles_n = (N + BN - 1) / BN;
     const long tiles = (long)tiles_m * tiles_n;
     const int per_xcd = (int)((tiles + 7) / 8);
     const long grid = 8L * per_xcd;
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE, PA, PB, NST, MINW>),
+    hipLaunchKernelGGL((gemm_nt_bf16dma_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, ROLE, PA, PB, NST, MINW, F16>),
                        dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
@@ -987,6 +1071,22 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                            const Store& st, const OutMap& map, int products, hipStream_t stream)
 {
     (void)products;
+    if (A.fmt == Fmt::F16x2 || B.fmt == Fmt::F16x2) {
+        // FP16 two-plane operands: the Y product at full size only (panel
+        // operands, 256 x 256 tiles), hi*hi + hi*lo + lo*hi
+        if constexpr (ROLE == 2) {
+            const bool ok = A.fmt == Fmt::F16x2 && B.fmt == Fmt::F16x2 && A.panel_k && B.panel_k && K >= 16 &&
+                            K % 16 == 0 && A.panel_k == lda && B.panel_k == ldb && K <= lda && K <= ldb &&
+                            lda % 16 == 0 && ldb % 16 == 0 && M % 32 == 0 && N % 32 == 0 && N > 64 &&
+                            (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 &&
+                            ((uintptr_t)B.ptr & 15) == 0 && (long)((M + 255) / 256) * ((N + 255) / 256) >= 512;
+            if (!ok) return hipErrorInvalidValue;
+            return run_gemm_dma<3, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true, HOTRG_Y_NST,
+                                HOTRG_Y_MINW, true>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
     const bool split = A.fmt == Fmt::BF16x2 || A.fmt == Fmt::BF16x3;
     if (A.fmt == Fmt::F32 && (B.fmt == Fmt::BF16x2 || B.fmt == Fmt::BF16x3)) {
         // T' = Y . U with Y kept in FP32 by its producer: the A tile is split

@@ -20,6 +20,11 @@ __device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
     switch (o.fmt) {
         case Fmt::F64: static_cast<double*>(o.ptr)[idx] = v; break;
         case Fmt::F32: static_cast<float*>(o.ptr)[idx] = (float)v; break;
+        case Fmt::F16x2: {
+            _Float16* p = static_cast<_Float16*>(o.ptr);
+            f16_split((float)(v * (double)o.scale), p + idx, p + idx + o.plane);
+            break;
+        }
         default: {
             __bf16* p = static_cast<__bf16*>(o.ptr);
             const float f = (float)v;
