@@ -12,9 +12,11 @@ one HIP stream and workspace each) through the continuous-batching server.
 
 value = algorithmic contraction FLOPs of the timed solves (O(D^7) order,
 eigensolve excluded from the count but not from the time) / wall time of
-the timed region, in the headline precision (default: BF16 split into 3
-terms, 6 products, FP32 accumulation; eigensolve, normalisation and ln Z in
-FP64).  Also reported: the same batch in FP64, per-solve service time
+the timed region, in the headline precision (default FP16X3: the D^7
+product Y with its operands split into two FP16 terms of the value times a
+fixed power of two, 3 products, the other products split into three BF16
+terms, 6 products, all with FP32 accumulation; eigensolve, normalisation
+and ln Z in FP64).  Also reported: the same batch in BF16x6 and in FP64, per-solve service time
 p50/p99, per-stage GPU times from HIP events, |delta f| against the FP64
 oracle's stored values for these temperatures, the roofline of the dominant
 kernel (the steady-state Y product, 2 D^7 algorithmic FLOPs a launch,
@@ -27,7 +29,7 @@ temperatures with the finite-difference internal energy against Onsager
 solve at Tc in BF16x6 and in FP64 ("c5"), two-sided truncation with
 impurity observables, iTEBD chains and the quantum chain.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6] [--concurrency C]
+    python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6|fp16x3] [--concurrency C]
 """
 from __future__ import annotations
 
@@ -44,13 +46,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
-TRAFFIC_PROFILE = {"bf16x6": os.path.join(ROOT, "profiles", "gemm_y_bf16x6_ising_d48_traffic.md")}
-ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 6}
+# dense MFMA peaks of the Y product's operand type (BF16 and FP16: 2.5 PFLOP/s)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0, "fp16x3": 2500.0}
+TRAFFIC_PROFILE = {p: os.path.join(ROOT, "profiles", f"gemm_y_{p}_ising_d48_traffic.md") for p in ("bf16x6", "fp16x3")}
+# bytes per element of Y's operands (X and the re-laid-out T)
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 6, "fp16x3": 4}
 # Y's output: FP32 in the split modes (its consumer splits it on load)
-Y_OUT_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4}
-PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc"}
+Y_OUT_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4, "fp16x3": 4}
+# MFMA products per algorithmic product in Y
+PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc",
+         "fp16x3": "fp16x3-split/f32acc (Y), bf16x6-split/f32acc (other products)"}
 
 
 def measured_traffic(precision: str, dmax: int, nsteps: int):
@@ -320,15 +326,16 @@ def run_qchain(binding, workloads):
 
 
 def run_c5(binding, accounting):
-    """Ising at Tc, D = 64, 40 steps, one solve in BF16x6 and one in FP64 on
-    the same GPU: throughput and |delta f| between them and against Onsager."""
+    """Ising at Tc, D = 64, 40 steps, one solve in FP16X3, one in BF16x6 and
+    one in FP64 on the same GPU: throughput and |delta f| between them and
+    against Onsager."""
     import torch
     ref = onsager_reference()
     tc = ref["critical"]["temperature"] if ref else 2.269185314213022
     flops = accounting.solve_flops(2, 64, 40)
     out = {"workload": "Ising J=1 at Tc, D=64, 40 steps, one solve per precision"}
     lnz = {}
-    for prec in ("bf16x6", "fp64"):
+    for prec in ("fp16x3", "bf16x6", "fp64"):
         s = binding.Solve(model="ising", q=2, temperature=tc, dmax=64, precision=prec, max_steps=40)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -342,8 +349,9 @@ def run_c5(binding, accounting):
                 ref["critical"]["lnz_per_site"]
         del s
         torch.cuda.empty_cache()
-    out["rel_df_bf16x6_vs_fp64"] = abs(lnz["bf16x6"] - lnz["fp64"]) / abs(lnz["fp64"])
-    out["speedup_bf16x6_vs_fp64"] = out["fp64"]["seconds"] / out["bf16x6"]["seconds"]
+    for prec in ("fp16x3", "bf16x6"):
+        out[f"rel_df_{prec}_vs_fp64"] = abs(lnz[prec] - lnz["fp64"]) / abs(lnz["fp64"])
+        out[f"speedup_{prec}_vs_fp64"] = out["fp64"]["seconds"] / out[prec]["seconds"]
     return out
 
 
@@ -508,9 +516,11 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
-    ap.add_argument("--precision", default="bf16x6", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--precision", default="fp16x3", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
                     help="skip the FP64 run of the same batch")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="skip the BF16x6 and FP64 runs of the same batch")
     ap.add_argument("--dmax", type=int, default=48)
     ap.add_argument("--nsteps", type=int, default=30, help="coarse-graining steps per solve")
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
@@ -626,23 +636,26 @@ def main(argv=None):
     run_leg(line, "roofline", run_roofline, binding, accounting, args.precision, args.dmax, args.nsteps,
             float(temps[0]))
 
-    if args.compare_fp64 and args.precision != "fp64":
-        def fp64_comparison():
-            # the same requests (same temperatures) as the timed batch, one warm-up solve first
-            fdone, fwall, _ = run_batch("fp64", args.concurrency, batch(0, 1), timed_reqs)
-            fl = {c.rid: c.lnz_per_site for c in fdone}
-            out = {
-                "fp64_value": flops_solve * args.steps / fwall / 1e12,
-                "fp64_ms_per_step": fwall / args.steps * 1e3,
-                "speedup_vs_fp64": fwall / wall,
-                "max_rel_df_vs_gpu_fp64": max(abs(c.lnz_per_site - fl[c.rid]) / abs(fl[c.rid]) for c in done),
-            }
-            ferr = [abs(c.lnz_per_site - ref[round(c.temperature, 9)]) / abs(ref[round(c.temperature, 9)])
-                    for c in fdone if round(c.temperature, 9) in ref]
-            if ferr:
-                out["fp64_max_rel_err_vs_fp64_oracle"] = max(ferr)
-            return out
-        run_leg(line, "fp64_comparison", fp64_comparison)
+    def comparison(prec):
+        # the same requests (same temperatures) as the timed batch, one warm-up solve first
+        fdone, fwall, _ = run_batch(prec, args.concurrency, batch(0, 1), timed_reqs)
+        fl = {c.rid: c.lnz_per_site for c in fdone}
+        out = {
+            "precision": prec,
+            "value": flops_solve * args.steps / fwall / 1e12,
+            "ms_per_step": fwall / args.steps * 1e3,
+            "headline_speedup": fwall / wall,
+            "max_rel_df_headline_vs_this": max(abs(c.lnz_per_site - fl[c.rid]) / abs(fl[c.rid]) for c in done),
+        }
+        ferr = [abs(c.lnz_per_site - ref[round(c.temperature, 9)]) / abs(ref[round(c.temperature, 9)])
+                for c in fdone if round(c.temperature, 9) in ref]
+        if ferr:
+            out["max_rel_err_vs_fp64_oracle"] = max(ferr)
+        return out
+
+    for prec in ("bf16x6", "fp64"):
+        if prec != args.precision and args.compare and (prec != "fp64" or args.compare_fp64):
+            run_leg(line, f"{prec}_comparison", comparison, prec)
     if args.c2:
         run_leg(line, "c2", run_c2, serve, accounting, workloads, args.budget_gb << 30)
     if args.c4:

@@ -102,11 +102,13 @@ def test_bench_line_with_the_drivers_flags_and_a_failing_leg(monkeypatch, capsys
     assert line["steps"] == 20 and line["warmup"] == 5 and line["n_gpus"] == 1
     assert line["value"] > 0 and math.isfinite(line["ms_per_step"])
     # the timed batch and the FP64 comparison cover the same requests
-    timed = [c for c in calls if c[0] == "bf16x6" and len(c[1]) == 20]
+    timed = [c for c in calls if c[0] == "fp16x3" and len(c[1]) == 20]
+    bf = [c for c in calls if c[0] == "bf16x6" and len(c[1]) == 20]
     fp64 = [c for c in calls if c[0] == "fp64" and len(c[1]) == 20]
-    assert timed and fp64 and timed[0][1] == fp64[0][1] == list(range(5, 25))
+    assert timed and bf and fp64 and timed[0][1] == bf[0][1] == fp64[0][1] == list(range(5, 25))
     cmp = line["fp64_comparison"]
-    assert "error" not in cmp and abs(cmp["max_rel_df_vs_gpu_fp64"] - 1e-9 / 0.5) < 1e-9
+    assert "error" not in cmp and abs(cmp["max_rel_df_headline_vs_this"] - 1e-9 / 0.5) < 1e-9
+    assert "error" not in line["bf16x6_comparison"]
     # the roofline: steady launches only, algorithmic FLOPs over their mean time
     rf = line["roofline"]
     assert rf["bound"] == "mfma" and rf["unit"] == "TFLOP/s" and rf["peak"] == 2500.0

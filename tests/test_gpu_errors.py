@@ -20,13 +20,13 @@ pytestmark = pytest.mark.gpu
 
 
 def test_pass_cap_one_latches_eeig_and_it_sticks(gpu_lib):
-    """Ising D = 48 with one subspace pass per eigensolve: step 5 (n = 256,
-    the first subspace solve) stops far from convergence, HOTRG_EEIG is
-    latched, and it is what every later synchronising call returns, also
-    after more steps have run."""
+    """Ising D = 48 with one subspace pass per eigensolve and a failure bound
+    of 1e-6: step 5 (n = 256, the first subspace solve) stops far from
+    convergence, HOTRG_EEIG is latched, and it is what every later
+    synchronising call returns, also after more steps have run."""
     from paper_2602_05900_amd import binding
     s = binding.Solve(model="ising", q=2, temperature=2.25, dmax=48, max_steps=12)
-    s.set_eig_limits(max_passes=1)
+    s.set_eig_limits(max_passes=1, fail_residual=1e-6)
     s.coarse_grain(6)
     with pytest.raises(binding.HotrgError) as e:
         s.log_z()
@@ -45,17 +45,19 @@ def test_pass_cap_one_latches_eeig_and_it_sticks(gpu_lib):
 
 
 def test_pass_cap_below_failure_bound_is_reported_not_latched(gpu_lib):
-    """The same cap with a failure bound above the residual reached: no
-    error, and the stop reason says the pass cap ended the solve."""
+    """The same cap with a failure bound above any finite residual: no
+    error, and the stop reason says the pass cap ended the solve, with the
+    residual of an unconverged block (above the 1e-6 of the test above)."""
     from paper_2602_05900_amd import binding
     s = binding.Solve(model="ising", q=2, temperature=2.25, dmax=48, max_steps=6)
-    s.set_eig_limits(max_passes=1, fail_residual=1.0)
+    s.set_eig_limits(max_passes=1, fail_residual=1e300)
     s.coarse_grain(6)
     assert np.isfinite(s.log_z())
     assert [s.eig_stop(n) for n in range(1, 5)] == [binding.EIG_CONVERGED] * 4     # dense Jacobi
     assert s.eig_stop(5) == binding.EIG_PASS_CAP
     it, _, res = s.eig_info(5)
-    assert it == 1 and res > 1e-12
+    print(f"one pass: residual {res:.2e}")
+    assert it == 1 and res > 1e-6
     s.close()
 
 

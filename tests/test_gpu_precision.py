@@ -10,7 +10,7 @@ from oracle import exact, hotrg as oracle
 
 pytestmark = pytest.mark.gpu
 
-CLAIM = {"fp32": 1e-6, "bf16x6": 1e-6, "bf16x3": 1e-5}
+CLAIM = {"fp32": 1e-6, "bf16x6": 1e-6, "fp16x3": 1e-6, "bf16x3": 1e-5}
 
 
 def rel(a, b):
@@ -68,7 +68,7 @@ def test_c5_d64_bf16x6_against_fp64_and_onsager(gpu_lib):
     from paper_2602_05900_amd import binding
     Tc = exact.ISING_TC
     lnz = {}
-    for prec in ("fp64", "bf16x6"):
+    for prec in ("fp64", "bf16x6", "fp16x3"):
         s = binding.Solve(model="ising", q=2, temperature=Tc, dmax=64, precision=prec, max_steps=40)
         s.coarse_grain(40)
         lnz[prec] = s.log_z()
@@ -79,5 +79,26 @@ def test_c5_d64_bf16x6_against_fp64_and_onsager(gpu_lib):
         torch.cuda.empty_cache()
     exact_tc = exact.onsager_lnz_tc()
     print(f"D=64 Tc: fp64 {lnz['fp64']:.15f} bf16x6 {lnz['bf16x6']:.15f} onsager {exact_tc:.15f}")
+    print(f"D=64 Tc: fp16x3 {lnz['fp16x3']:.15f}")
     assert rel(lnz["bf16x6"], lnz["fp64"]) <= CLAIM["bf16x6"]
+    assert rel(lnz["fp16x3"], lnz["fp64"]) <= CLAIM["fp16x3"]
     assert rel(lnz["fp64"], exact_tc) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6"])
+def test_d32_against_oracle_golden(gpu_lib, precision):
+    """D = 32, 30 steps (the smallest bond dimension whose steady Y product
+    takes the full-size tiles, and with them FP16X3's FP16 planes) against
+    the oracle's values in tests/golden/oracle_ising_d32.json."""
+    import json
+    import os
+    from paper_2602_05900_amd import binding
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_ising_d32.json")
+    for r in json.load(open(path))["rows"]:
+        T = r["temperature"]
+        s = binding.Solve(model="ising", q=2, temperature=T, dmax=32, precision=precision, max_steps=30)
+        s.coarse_grain(30)
+        e = rel(-T * s.log_z(), r["free_energy"])
+        print(f"D=32 {precision} T={T:.4f} |df|/|f| = {e:.2e}")
+        assert e <= CLAIM[precision]
+        s.close()
