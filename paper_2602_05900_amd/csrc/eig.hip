@@ -45,13 +45,8 @@ constexpr int EIG_MAX_SWEEPS = 40;
 // Rayleigh quotient dominates a pass: measured at D = 48, 0.66-0.76x the
 // eigensolve time at the same residual bound (every third pass misses the
 // bound in 30 passes).
-#ifndef HOTRG_RR_EVERY
-#define HOTRG_RR_EVERY 2
-#endif
-#ifndef HOTRG_JAC_THREADS
-#define HOTRG_JAC_THREADS 1024
-#endif
-constexpr int EIG_JT = HOTRG_JAC_THREADS;   // threads of the one-workgroup Jacobi kernel
+constexpr int EIG_RR_EVERY = 2;
+constexpr int EIG_JT = 1024;   // threads of the one-workgroup Jacobi kernel
 
 // ---------------------------------------------------------------- helpers
 
@@ -781,8 +776,7 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
     orth(V, shift, seed * 31 + 7);
     for (int it = 0; it < maxit; ++it) {
         hipLaunchKernelGGL(eig_ev_kernel, dim3(grid_for(n, 16)), dim3(256), 0, stream, E, n, V, w.W, p, w.ctl);
-#if HOTRG_RR_EVERY > 1
-        if (it % HOTRG_RR_EVERY != HOTRG_RR_EVERY - 1 && it != maxit - 1) {
+        if (it % EIG_RR_EVERY != EIG_RR_EVERY - 1 && it != maxit - 1) {
             // power step without Rayleigh-Ritz: V <- orth(E V)
             hipLaunchKernelGGL(eig_gram_kernel, dim3(nb), dim3(256), 0, stream, w.W, w.W, n, p, w.part, pstride,
                                w.ctl);
@@ -794,7 +788,6 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
                                seed * 131 + it, w.ctl);
             continue;
         }
-#endif
         hipLaunchKernelGGL(eig_gram_kernel, dim3(nb), dim3(256), 0, stream, V, w.W, n, p, w.part, pstride, w.ctl);
         hipLaunchKernelGGL(eig_reduce_kernel, dim3(grid_for(p * p, 256)), dim3(256), 0, stream, w.part, nb, pstride,
                            p * p, w.G, w.ctl);

@@ -26,58 +26,32 @@
 
 #include "common.h"
 
-// Tile of the BF16-split product: workgroup BM x BN over WM x WN waves, PF
-// K stages of global loads in flight.  256 x 256 on 8 waves measured fastest
-// for the D = 48 Y product (6.9 ms vs 8.5 ms for 256 x 128, 11.5 ms for
-// 128 x 128): the split operands make the product L2-bandwidth-bound, and
-// the larger tile reads each operand byte fewer times.
-#ifndef HOTRG_BF16_BM
-#define HOTRG_BF16_BM 256
-#define HOTRG_BF16_BN 256
-#define HOTRG_BF16_WM 4
-#define HOTRG_BF16_WN 2
-#define HOTRG_BF16_PF 1
-#endif
-#ifndef HOTRG_BF16_DMA
-#define HOTRG_BF16_DMA 1
-#endif
-#ifndef HOTRG_DMA_WM
-#define HOTRG_DMA_WM 4
-#define HOTRG_DMA_WN 2
-#endif
-// narrow outputs (T', N = D') and mid-size products (half environments, E)
-#ifndef HOTRG_NARROW_NST
-#define HOTRG_NARROW_NST 3    // two stages measured slower for T' (12.1 -> 16.1 ms per D = 48 solve)
-#define HOTRG_NARROW_MINW 1
-#endif
-#ifndef HOTRG_F32_STAGED
-#define HOTRG_F32_STAGED 1
-#endif
+namespace hotrg {
+
+// ---------------------------------------------------------------- tile choices
+
+// Register-staged BF16-split product (K not a multiple of 16): workgroup
+// BM x BN over WM x WN waves, PF K stages of global loads in flight.
+// 256 x 256 on 8 waves measured fastest for the D = 48 Y product in this
+// form (6.9 ms vs 8.5 ms for 256 x 128, 11.5 ms for 128 x 128): the split
+// operands make the product L2-bandwidth-bound, and the larger tile reads
+// each operand byte fewer times.
+constexpr int kP32BM = 256, kP32BN = 256, kP32WM = 4, kP32WN = 2, kP32PF = 1;
+// direct-to-LDS 256 x 256 tiles on row-major operands: waves
+constexpr int kDmaWM = 4, kDmaWN = 2;
+// narrow outputs (T', N = D'): three stages (two measured slower for T':
+// 12.1 -> 16.1 ms per D = 48 solve), one workgroup per CU
+constexpr int kNarrowNst = 3, kNarrowMinw = 1;
 // T' reading Y in FP32 (split on load): register-staged 64 x 64 tiles, two
 // waves, one prefetch stage (per D = 48 solve: 13.1 ms, against 13.5 with two
 // stages, 16-17 ms with 128 or 256 rows, 17-20 ms with one wave)
-#ifndef HOTRG_TP_BM
-#define HOTRG_TP_BM 64
-#define HOTRG_TP_WM 2
-#endif
-#ifndef HOTRG_TP_PF
-#define HOTRG_TP_PF 1
-#endif
-#ifndef HOTRG_MID_NST
-#define HOTRG_MID_NST 2    // two stages, up to three workgroups per CU (env 19.2 -> 18.3 ms per D = 48 solve)
-#define HOTRG_MID_MINW 2
-#endif
-// Y product (panel operands) at full size
-#ifndef HOTRG_Y_BM
-#define HOTRG_Y_BM 256
-#define HOTRG_Y_BN 256
-#define HOTRG_Y_WM 4
-#define HOTRG_Y_WN 2
-#define HOTRG_Y_NST 3
-#define HOTRG_Y_MINW 1
-#endif
+constexpr int kTpBM = 64, kTpWM = 2, kTpPF = 1;
+// mid-size products (half environments, E): two stages, up to three
+// workgroups per CU (env 19.2 -> 18.3 ms per D = 48 solve)
+constexpr int kMidNst = 2, kMidMinw = 2;
+// the Y product (panel operands) at full size
+constexpr int kYBM = 256, kYBN = 256, kYWM = 4, kYWN = 2, kYNst = 3, kYMinw = 1;
 
-namespace hotrg {
 
 // ---------------------------------------------------------------- MFMA ops
 
@@ -1026,7 +1000,7 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
     int vec_out = same_planes && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 && st.plane % 8 == 0 &&
                   ((uintptr_t)st.ptr & 15) == 0;
     // FP32 output: runs of 4 columns contiguous and 16-byte aligned (row-major maps)
-    if (HOTRG_F32_STAGED && !vec_out && st.fmt == (int)Fmt::F32 && mp.panel_k == 0 && mp.cs_lo == 1 && mp.rs_hi % 4 == 0 &&
+    if (!vec_out && st.fmt == (int)Fmt::F32 && mp.panel_k == 0 && mp.cs_lo == 1 && mp.rs_hi % 4 == 0 &&
         mp.rs_lo % 4 == 0 && mp.cs_hi % 4 == 0 && mp.sn % 4 == 0 && N % 4 == 0 && ((uintptr_t)st.ptr & 15) == 0)
         vec_out = 2;
     // FP16 planes from BF16 operands (the X product feeding an FP16 Y)
@@ -1081,8 +1055,8 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                             (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 &&
                             ((uintptr_t)B.ptr & 15) == 0 && (long)((M + 255) / 256) * ((N + 255) / 256) >= 512;
             if (!ok) return hipErrorInvalidValue;
-            return run_gemm_dma<3, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true, HOTRG_Y_NST,
-                                HOTRG_Y_MINW, true>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
+            return run_gemm_dma<3, kYBM, kYBN, kYWM, kYWN, ROLE, true, true, kYNst,
+                                kYMinw, true>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
         } else {
             return hipErrorInvalidValue;
         }
@@ -1093,9 +1067,9 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
         // into the planes of B's format as it is written to LDS
         if (A.panel_k || B.panel_k) return hipErrorInvalidValue;
         return B.fmt == Fmt::BF16x2
-                   ? run_gemm_p32<3, HOTRG_TP_BM, 64, HOTRG_TP_WM, 1, HOTRG_TP_PF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
+                   ? run_gemm_p32<3, kTpBM, 64, kTpWM, 1, kTpPF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
                                                                                      stream)
-                   : run_gemm_p32<6, HOTRG_TP_BM, 64, HOTRG_TP_WM, 1, HOTRG_TP_PF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
+                   : run_gemm_p32<6, kTpBM, 64, kTpWM, 1, kTpPF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
                                                                                      stream);
     }
     if (A.panel_k || B.panel_k) {
@@ -1111,9 +1085,9 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
             // half environments and E (N = K = D^2): mid-size tiles
             if (!both) return hipErrorInvalidValue;
             return A.fmt == Fmt::BF16x2
-                       ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                       ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true, kMidNst, kMidMinw>(
                              A, lda, B, ldb, M, N, K, st, map, stream)
-                       : run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                       : run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true, kMidNst, kMidMinw>(
                              A, lda, B, ldb, M, N, K, st, map, stream);
         } else if constexpr (ROLE == 2) {
             if (!both) return hipErrorInvalidValue;
@@ -1121,20 +1095,20 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
             if (A.fmt == Fmt::BF16x2)
                 return big_tiles < 512
                            ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
-                           : run_gemm_dma<3, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true,
-                                          HOTRG_Y_NST, HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream,
+                           : run_gemm_dma<3, kYBM, kYBN, kYWM, kYWN, ROLE, true, true,
+                                          kYNst, kYMinw>(A, lda, B, ldb, M, N, K, st, map, stream,
                                                                      (int)map.ngroup);
             return big_tiles < 512
                        ? run_gemm_dma<6, 128, 128, 2, 2, ROLE, true, true>(A, lda, B, ldb, M, N, K, st, map, stream)
-                       : run_gemm_dma<6, HOTRG_Y_BM, HOTRG_Y_BN, HOTRG_Y_WM, HOTRG_Y_WN, ROLE, true, true, HOTRG_Y_NST,
-                                      HOTRG_Y_MINW>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
+                       : run_gemm_dma<6, kYBM, kYBN, kYWM, kYWN, ROLE, true, true, kYNst,
+                                      kYMinw>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
         } else if constexpr (ROLE == 3) {
             // T' = Y . U: Y in panels, U row-major, narrow output
             if (!(base && A.panel_k && !B.panel_k && N <= 64 && ldb % 8 == 0)) return hipErrorInvalidValue;
             return A.fmt == Fmt::BF16x2
-                       ? run_gemm_dma<3, 128, 64, 2, 1, ROLE, true, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                       ? run_gemm_dma<3, 128, 64, 2, 1, ROLE, true, false, kNarrowNst, kNarrowMinw>(
                              A, lda, B, ldb, M, N, K, st, map, stream)
-                       : run_gemm_dma<6, 128, 64, 2, 1, ROLE, true, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                       : run_gemm_dma<6, 128, 64, 2, 1, ROLE, true, false, kNarrowNst, kNarrowMinw>(
                              A, lda, B, ldb, M, N, K, st, map, stream);
         } else {
             (void)both;
@@ -1144,7 +1118,6 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
     if (split) {
         // narrow outputs (T' has N = D') take a 64-wide tile
         const bool narrow = N <= 64;
-#if HOTRG_BF16_DMA
         const bool dma = K >= 16 && K % 16 == 0 && lda % 8 == 0 && ldb % 8 == 0 && (long)A.plane % 8 == 0 &&
                          (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
         if (dma) {
@@ -1168,30 +1141,29 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
             const long big_tiles = (long)((M + 255) / 256) * ((N + 255) / 256);
             if (A.fmt == Fmt::BF16x2) {
                 if (narrow)
-                    return run_gemm_dma<3, 128, 64, 2, 1, ROLE, false, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                    return run_gemm_dma<3, 128, 64, 2, 1, ROLE, false, false, kNarrowNst, kNarrowMinw>(
                         A, lda, B, ldb, M, N, K, st, map, stream);
                 if (big_tiles < 512)
-                    return run_gemm_dma<3, 128, 128, 2, 2, ROLE, false, false, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                    return run_gemm_dma<3, 128, 128, 2, 2, ROLE, false, false, kMidNst, kMidMinw>(
                         A, lda, B, ldb, M, N, K, st, map, stream);
-                return run_gemm_dma<3, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
+                return run_gemm_dma<3, 256, 256, kDmaWM, kDmaWN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
                                                                                   stream, (int)map.ngroup);
             }
             if (narrow)
-                return run_gemm_dma<6, 128, 64, 2, 1, ROLE, false, false, HOTRG_NARROW_NST, HOTRG_NARROW_MINW>(
+                return run_gemm_dma<6, 128, 64, 2, 1, ROLE, false, false, kNarrowNst, kNarrowMinw>(
                     A, lda, B, ldb, M, N, K, st, map, stream);
             if (big_tiles < 512)
-                return run_gemm_dma<6, 128, 128, 2, 2, ROLE, false, false, HOTRG_MID_NST, HOTRG_MID_MINW>(
+                return run_gemm_dma<6, 128, 128, 2, 2, ROLE, false, false, kMidNst, kMidMinw>(
                     A, lda, B, ldb, M, N, K, st, map, stream);
-            return run_gemm_dma<6, 256, 256, HOTRG_DMA_WM, HOTRG_DMA_WN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
+            return run_gemm_dma<6, 256, 256, kDmaWM, kDmaWN, ROLE>(A, lda, B, ldb, M, N, K, st, map,
                                                                               stream, (int)map.ngroup);
         }
-#endif
         if (A.fmt == Fmt::BF16x2)
             return narrow ? run_gemm_p32<3, 256, 64, 4, 1, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
-                          : run_gemm_p32<3, HOTRG_BF16_BM, HOTRG_BF16_BN, HOTRG_BF16_WM, HOTRG_BF16_WN, HOTRG_BF16_PF,
+                          : run_gemm_p32<3, kP32BM, kP32BN, kP32WM, kP32WN, kP32PF,
                                          ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
         return narrow ? run_gemm_p32<6, 256, 64, 4, 1, 1, ROLE>(A, lda, B, ldb, M, N, K, st, map, stream)
-                      : run_gemm_p32<6, HOTRG_BF16_BM, HOTRG_BF16_BN, HOTRG_BF16_WM, HOTRG_BF16_WN, HOTRG_BF16_PF,
+                      : run_gemm_p32<6, kP32BM, kP32BN, kP32WM, kP32WN, kP32PF,
                                      ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
     }
     switch (A.fmt) {

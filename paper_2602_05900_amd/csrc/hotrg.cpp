@@ -96,10 +96,7 @@ int popcount2(int m) { return (m & 1) + ((m >> 1) & 1); }
 // Y is kept in FP32 in the split modes: T' splits it into planes as it loads
 // its tiles, so Y is written and read at 4 bytes an element instead of 6
 // (BF16x3 planes), with the same planes reaching the products.
-#ifndef HOTRG_Y_F32
-#define HOTRG_Y_F32 1
-#endif
-Fmt y_fmt(Fmt f) { return HOTRG_Y_F32 && (f == Fmt::BF16x2 || f == Fmt::BF16x3) ? Fmt::F32 : f; }
+Fmt y_fmt(Fmt f) { return f == Fmt::BF16x2 || f == Fmt::BF16x3 ? Fmt::F32 : f; }
 
 struct Layout {
     size_t nT = 0, nP = 0, nAB = 0, nE = 0, nU = 0, nX = 0, nEig = 0;
