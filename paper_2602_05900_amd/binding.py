@@ -38,6 +38,7 @@ EXPORTS = [
     "hotrg_copy_tensor", "hotrg_copy_environment", "hotrg_copy_isometry", "hotrg_set_timing", "hotrg_stage_times", "hotrg_step_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt", "hotrg_gemm_nt_role",
+    "hotrg_gemm_nt_noalloc",
     "itebd_state_len", "itebd_workspace_bytes", "itebd_init", "itebd_evolve", "itebd_energy",
     "itebd_copy_states", "itebd_info", "itebd_work", "itebd_destroy",
 ]
@@ -117,6 +118,9 @@ def load() -> ctypes.CDLL:
     lib.hotrg_gemm_nt.argtypes = [c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long,
                                   c_void_p, c_double, c_long, c_long, c_long, c_long, c_long, c_long,
                                   c_void_p, c_void_p]
+    lib.hotrg_gemm_nt_noalloc.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p,
+                                          c_long, c_void_p, c_double, c_long, c_long, c_long, c_long, c_long,
+                                          c_long, c_void_p]
     lib.hotrg_gemm_nt_role.argtypes = [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_long, c_void_p, c_long,
                                        c_void_p, c_double, c_long, c_long, c_long, c_long, c_long, c_long,
                                        c_void_p, c_void_p]
@@ -454,6 +458,20 @@ def coarse_grain_batch(solves, nsteps: int) -> None:
 
 
 ROLES = {"generic": 0, "x": 1, "y": 2, "tp": 3}
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def gemm_nt_noalloc(A, B, C, M, N, K, lda, ldb, out_map, precision: str = "fp64", alpha: float = 1.0,
+                    stream=None, role: str = "generic", panel: bool = False) -> int:
+    """hotrg_gemm_nt_noalloc: the stand-alone product with the library's own
+    device scratch array (no allocation).  Returns the status code."""
+    lib = load()
+    st = stream if stream is not None else torch.cuda.current_stream(C.device)
+    sm, rs_hi, rs_lo, sn, cs_hi, cs_lo = out_map
+    return lib.hotrg_gemm_nt_noalloc(PRECISIONS[precision], ROLES[role], 1 if panel else 0, M, N, K,
+                                     ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(B.data_ptr()), ldb,
+                                     ctypes.c_void_p(C.data_ptr()), alpha, sm, rs_hi, rs_lo, sn, cs_hi, cs_lo,
+                                     ctypes.c_void_p(st.cuda_stream))
 
 
 def gemm_nt(A, B, C, M, N, K, lda, ldb, out_map, precision: str = "fp64", alpha: float = 1.0, stream=None,

@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libhotrg.so")
 PEAK = os.path.join(PKG, "peak_bench")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["gemm.hip", "tensor_ops.hip", "eig.hip", "hotrg.cpp", "itebd.hip"]
+SOURCES = ["gemm.hip", "tensor_ops.hip", "eig.hip", "hotrg.cpp", "itebd.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
