@@ -15,21 +15,30 @@
  *   M[(a s),(t b)] = lambda_2[a] psi'[a,s,t,b];  M = X S Y^T
  *   B2' = rows of Y^T kept, B1' = psi' Y / |S_kept|, lambda_1' = S_kept / |S_kept|
  * after which the two sites exchange roles, so the next update acts on the
- * other bond.  The SVD is a one-sided (column) Jacobi method in FP64 with a
- * round-robin pair ordering, warm-started from the right singular vectors
- * of the same bond's previous update; the kept right vectors have their
- * largest-magnitude entry made positive.
+ * other bond.  The SVD, in FP64, is a Householder QR with column pivoting,
+ * M Pi = Q R, followed by a one-sided (column) Jacobi method with a
+ * round-robin pair ordering on R^T: its converged columns, normalised and
+ * permuted back by Pi, are the right singular vectors of M and their norms
+ * the singular values (Q and the left vectors are never formed).  The kept
+ * right vectors have their largest-magnitude entry made positive.
  *
- * Device mapping: one workgroup per chain keeps the Jacobi matrices (W, V)
- * in LDS (chi <= 32); the unit cell and the evolved pair go through the
- * chain's slice of the workspace, which stays in L2, and a launch runs many
- * updates of a chain.  Two chains share a CU, so a batch of twice the CU
- * count fills the chip.
+ * Device mapping: one workgroup per chain keeps the decomposition's work
+ * matrix in LDS (chi <= 32, 37 KB); the unit cell and the evolved pair go
+ * through the chain's slice of the workspace, which stays in L2, and a
+ * launch runs many updates of a chain.  Up to four chains share a CU.
  *
  * Status codes are those of hotrg.h.  The caller owns the device workspace
- * (itebd_workspace_bytes: state rows, the evolved pair and two bonds' right
- * vectors per chain, counters) and the stream; nothing is allocated on the
- * device by the library.  All arithmetic is FP64.
+ * (itebd_workspace_bytes: state rows, the evolved pair per chain, status
+ * words, counters) and the stream; nothing is allocated on the device by
+ * the library.  All arithmetic is FP64.
+ *
+ * Failures are recorded per chain in a device status word (bits below) and
+ * reported by the synchronising calls itebd_energy and itebd_info:
+ * HOTRG_ENONFINITE when a chain's kept singular values had a zero or
+ * non-finite norm (that update is not applied and the chain is not updated
+ * again: its state row keeps the last good update), else HOTRG_EEIG when a
+ * decomposition was still rotating at the sweep limit (that update is
+ * applied as it stands).  The other chains of the batch are unaffected.
  */
 #ifndef ITEBD_H
 #define ITEBD_H
@@ -44,6 +53,12 @@ extern "C" {
 
 #define ITEBD_MAX_CHI 32  /* largest bond dimension (the state lives in LDS) */
 #define ITEBD_PHYS    2   /* physical dimension (spin 1/2)                   */
+#define ITEBD_MAX_SWEEPS 40  /* default and largest Jacobi sweep limit       */
+
+/* Bits of a chain's status word (itebd_status). */
+#define ITEBD_CHAIN_SWEEP_CAP 1  /* a decomposition reached the sweep limit    */
+#define ITEBD_CHAIN_NONFINITE 2  /* kept singular values' norm zero or not
+                                    finite: the chain is frozen                 */
 
 typedef struct itebd_batch itebd_batch;  /* opaque host handle */
 
@@ -74,23 +89,37 @@ int itebd_evolve(itebd_batch* b, double tau, int nupdates);
 
 /* Synchronises and writes each chain's energy per site, the mean of <h>
  * on its two bonds, <h> = theta.(h theta) / theta.theta with theta the
- * weighted two-site wave function of the bond.  energies: batch doubles.
- * Errors: EINVAL, EHIP. */
+ * weighted two-site wave function of the bond.  energies: batch doubles,
+ * written for every chain (a frozen chain's from its last good state).
+ * Errors: EINVAL, EHIP; ENONFINITE or EEIG when a chain's status word is
+ * set (see above; itebd_status tells which chains). */
 int itebd_energy(itebd_batch* b, double* energies);
 
 /* Synchronises and copies the states (batch rows, layout as for init; B1 is
  * the left site of the bond the next update acts on).  Errors: EINVAL, EHIP. */
 int itebd_copy_states(itebd_batch* b, double* host, size_t capacity);
 
-/* Bond updates applied so far and the largest Jacobi sweep count any chain
- * needed in the last launch (synchronises).  Either pointer may be NULL. */
+/* Bond updates enqueued so far (a frozen chain applied fewer) and the
+ * largest Jacobi sweep count any chain needed in the last launch
+ * (synchronises).  Either pointer may be NULL.  Returns ENONFINITE or EEIG
+ * as itebd_energy does, after writing the outputs. */
 int itebd_info(itebd_batch* b, long* updates, int* max_sweeps);
+
+/* Synchronises and copies every chain's status word (ITEBD_CHAIN_* bits,
+ * 0 = no failure) to status (batch ints, host).  Errors: EINVAL, EHIP. */
+int itebd_status(itebd_batch* b, int* status);
+
+/* Sets the Jacobi sweep limit of later updates, 1..ITEBD_MAX_SWEEPS
+ * (default ITEBD_MAX_SWEEPS).  A converged decomposition takes one sweep
+ * without rotations to be recognised, so a limit of 1 marks every update
+ * with a rotation as ITEBD_CHAIN_SWEEP_CAP.  Errors: EINVAL. */
+int itebd_set_max_sweeps(itebd_batch* b, int max_sweeps);
 
 /* Work done so far, summed over the chains (synchronises): Jacobi sweeps
  * and pair rotations applied.  One sweep over n = 2 chi columns forms the
  * three dot products of every pair (n (n - 1) / 2 pairs, 6 n FLOPs each);
- * a rotation updates two columns of M and of V (12 n FLOPs).  Either
- * pointer may be NULL. */
+ * a rotation updates two columns of R^T (6 n FLOPs).  Either pointer may
+ * be NULL. */
 int itebd_work(itebd_batch* b, double* sweeps, double* rotations);
 
 /* Releases the host handle (waits for the stream first).  NULL is a no-op. */

@@ -40,9 +40,12 @@ EXPORTS = [
     "hotrg_runtime_version", "hotrg_gemm_scratch_bytes", "hotrg_gemm_nt", "hotrg_gemm_nt_role",
     "hotrg_gemm_nt_noalloc",
     "itebd_state_len", "itebd_workspace_bytes", "itebd_init", "itebd_evolve", "itebd_energy",
-    "itebd_copy_states", "itebd_info", "itebd_work", "itebd_destroy",
+    "itebd_copy_states", "itebd_info", "itebd_work", "itebd_status", "itebd_set_max_sweeps", "itebd_destroy",
 ]
 ITEBD_MAX_CHI = 32
+ITEBD_MAX_SWEEPS = 40
+# bits of an iTEBD chain's status word (itebd_status)
+ITEBD_CHAIN_SWEEP_CAP, ITEBD_CHAIN_NONFINITE = 1, 2
 
 
 class HotrgError(RuntimeError):
@@ -134,6 +137,8 @@ def load() -> ctypes.CDLL:
     lib.itebd_copy_states.argtypes = [c_void_p, P(c_double), c_size_t]
     lib.itebd_info.argtypes = [c_void_p, P(ctypes.c_long), P(c_int)]
     lib.itebd_work.argtypes = [c_void_p, P(c_double), P(c_double)]
+    lib.itebd_status.argtypes = [c_void_p, P(c_int)]
+    lib.itebd_set_max_sweeps.argtypes = [c_void_p, c_int]
     lib.itebd_destroy.argtypes = [c_void_p]
     lib.itebd_destroy.restype = None
     for name in EXPORTS:
@@ -430,6 +435,17 @@ class Chains:
         u, m = ctypes.c_long(), ctypes.c_int()
         _check(self._lib.itebd_info(self._h, ctypes.byref(u), ctypes.byref(m)), "itebd_info")
         return u.value, m.value
+
+    def status(self):
+        """Per-chain status words (ITEBD_CHAIN_* bits; 0 = no failure)."""
+        import numpy as np
+        out = np.zeros(self.batch, dtype=np.int32)
+        _check(self._lib.itebd_status(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), "itebd_status")
+        return out
+
+    def set_max_sweeps(self, max_sweeps: int) -> "Chains":
+        _check(self._lib.itebd_set_max_sweeps(self._h, int(max_sweeps)), "itebd_set_max_sweeps")
+        return self
 
     def work(self):
         """(Jacobi sweeps, pair rotations) summed over the chains so far."""

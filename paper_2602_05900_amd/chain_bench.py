@@ -20,14 +20,28 @@ import torch
 from . import binding, workloads
 
 
+def qr_flops(n: int) -> int:
+    """Householder QR with column pivoting of an n x n matrix as the update
+    kernel performs it: the first column norms (2 n^2), then per step k the
+    reflector's norm over the r = n - k remaining rows (2 r) and, for each
+    of the n - 1 - k trailing columns, its product with the reflector, the
+    update and its new norm below row k (2 r + 2 r + 2 (r - 1))."""
+    total = 2 * n * n
+    for k in range(n - 1):
+        r = n - k
+        total += 2 * r + (n - 1 - k) * (6 * r - 2)
+    return total
+
+
 def itebd_flops(chi: int, updates: float, sweeps: float, rotations: float) -> float:
-    """FLOPs the device performs (see itebd_work): per update the contraction
-    (2 n^2 chi), the gate (32 chi^2), the warm-start product (2 n^3), the
-    singular values (2 n^2) and B1' (4 n chi^2); per sweep the pair dot
-    products (3 n^2 (n - 1)); per rotation 12 n; n = 2 chi."""
+    """Algorithmic FLOPs of the device's work (see itebd_work): per update
+    the contraction (2 n^2 chi), the gate (32 chi^2), the pivoted QR
+    (qr_flops), the singular values (2 n^2) and B1' (4 n chi^2); per sweep
+    the pair dot products (3 n^2 (n - 1)); per rotation 6 n (two columns of
+    R^T); n = 2 chi."""
     n = 2 * chi
-    per_update = 2 * n * n * chi + 32 * chi * chi + 2 * n ** 3 + 2 * n * n + 4 * n * chi * chi
-    return updates * per_update + sweeps * 3 * n * n * (n - 1) + rotations * 12 * n
+    per_update = 2 * n * n * chi + 32 * chi * chi + qr_flops(n) + 2 * n * n + 4 * n * chi * chi
+    return updates * per_update + sweeps * 3 * n * n * (n - 1) + rotations * 6 * n
 
 
 def run_itebd(chains: int, chi: int, updates: int, tau: float = 0.01) -> dict:

@@ -1,34 +1,45 @@
 // iTEBD on the device: many independent infinite chains, one workgroup per
-// chain, all FP64.  The SVD work matrices (W, V) live in LDS (75 KB, so two
-// chains share a CU); B1 and B2 are staged into LDS from the chain's state
-// row at the start of each update and written back at its end, and the
-// evolved pair P goes to the chain's workspace slice (column-major, read
-// row-parallel by the products W = P V and B1' = P V_kept, and small enough
-// to stay in L2).  The C ABI is declared in include/itebd.h.
+// chain, all FP64.  The decomposition's work matrix lives in LDS (37 KB, so
+// up to four chains share a CU); B1 and B2 are staged into it from the
+// chain's state row at the start of each update and written back at its
+// end, and the evolved pair P goes to the chain's workspace slice
+// (column-major, read row-parallel by the product B1' = P Y_kept, and small
+// enough to stay in L2).  The C ABI is declared in include/itebd.h.
 //
 // One bond update (Sec. II.A, Eq. (1); the inverse-free form of the iTEBD
 // update), n = 2 chi:
 //   P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b]          (contraction)
 //   P <- G P on the physical pair (s, t) of every (a, b)     (gate)
-//   W = diag(lambda_2 (x) 1) P V0                             (V0: warm start or 1)
-//   one-sided Jacobi on the columns of W, rotations also applied to V
-//     -> W = X S, V = right singular vectors (unordered)
-//   keep the chi largest; sign gauge on the kept columns of V
-//   B2' = V_kept^T, B1' = P V_kept / |S_kept|, lambda_1' = S_kept / |S_kept|
+//   W = diag(lambda_2 (x) 1) P
+//   W Pi = Q R: Householder QR with column pivoting (Pi the permutation)
+//   one-sided Jacobi on the columns of A = R^T:  A J = U S
+//     then W = Q J S U^T Pi^T, so the right singular vectors of W are
+//     Y = Pi U: the normalised final columns of A, rows permuted back; no
+//     rotation is accumulated and the left vectors are never formed
+//   keep the chi largest; sign gauge on the kept columns of Y
+//   B2' = Y_kept^T, B1' = P Y_kept / |S_kept|, lambda_1' = S_kept / |S_kept|
 //   exchange the sites' roles
-// The Jacobi sweep visits all column pairs in n - 1 rounds of n/2 disjoint
-// pairs (round-robin ordering, the systolic schedule of Sec. II.B used for
-// one-sided rotations); sixteen lanes own a pair: they hold the pair's two
-// columns of W and of V in registers (rows l, l + 16, ...), form the three
-// dot products, reduce them over the sixteen lanes with DPP moves (every
-// lane gets the same bits: each stage adds two equal partial sums in either
-// order), and rotate their rows of W and V.  With 512 threads two waves share
-// each SIMD, so one wave's dependent FP64 chain (square roots, division)
-// overlaps the other's.  W and V are kept column-major with a column stride
-// ld = 8 (mod 32) doubles: the four pairs of a wave (consecutive column
-// indices) read 16 consecutive doubles each, starting 8 doubles apart in the
-// 32 double-wide banks, which covers every bank exactly twice (the least a
-// 64-lane 8-byte read can take).
+// Pivoting makes R graded, with columns of A = R^T close to orthogonal, so
+// the Jacobi method needs about half the sweeps of a cold start on W (the
+// preconditioning of Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29
+// (2008)), and each sweep rotates one matrix instead of two.
+//
+// Lanes: groups of eight lanes, one group per column pair in a Jacobi round
+// and per trailing column (two of them) in a QR step; a lane holds rows
+// l, l + 8, ..., l + 56 of its columns in registers.  A pair's three dot
+// products and a column's reflector product are reduced over the eight lanes
+// with DPP moves (every lane gets the same bits: each stage adds two equal
+// partial sums in either order).  The Jacobi sweep visits all column pairs
+// in n - 1 rounds of n/2 disjoint pairs (round-robin ordering, the systolic
+// schedule of Sec. II.B used for one-sided rotations).  A QR step is one
+// barrier: every wave finds the pivot (the largest remaining column norm,
+// lowest index on ties) and the reflector itself from the norms the previous
+// step left in LDS, keeps the column permutation in registers (lane j holds
+// the storage column of logical column j), and the groups then update the
+// trailing columns and write their new norms for the next step.  The work
+// matrix is column-major with a column stride ld = 8 (mod 32) doubles: the
+// eight groups of a wave read eight consecutive doubles each from columns
+// ld apart, which spreads a wave's read evenly over the banks.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -43,21 +54,29 @@ namespace {
 
 constexpr int kMaxChi = ITEBD_MAX_CHI;
 constexpr int kMaxN = 2 * kMaxChi;
-// column stride of W and V: the smallest ld >= n with ld = 8 (mod 32)
-__host__ __device__ constexpr int col_stride(int n) { return ((n + 23) / 32) * 32 + 8; }
-constexpr int kMaxLd = col_stride(kMaxN);
-static_assert(4 * kMaxChi * kMaxChi <= kMaxN * kMaxLd, "B1 and B2 are staged in the V buffer");
-constexpr int kLanesPerPair = 16;
-constexpr int kRowsPerLane = kMaxN / kLanesPerPair;
-constexpr int kThreads = 256;                       // energy kernel
-constexpr int kUpdThreads = kLanesPerPair * kMaxN / 2;   // update kernel: one lane group per pair
-// row-parallel products (W = P V, B1' = P V_kept): kUpdThreads / n >= 8 groups
-// of n lanes, each lane one row and at most this many columns
-constexpr int kMaxColsPerLane = (kMaxN + 7) / 8;
-static_assert(kUpdThreads / kMaxN >= 8, "row-parallel products assume at least 8 lane groups");
+// column stride of the work matrix, 8 (mod 32) doubles; every column has
+// kMaxN rows, those at and beyond n held at zero, so the row loops need no
+// bounds
+constexpr int kLd = 72;
+static_assert(kLd >= kMaxN && kLd % 32 == 8, "column stride");
+static_assert(4 * kMaxChi * kMaxChi <= kMaxN * kLd, "B1 and B2 are staged in the work matrix");
+constexpr int kLanes = 8;                       // lanes per Jacobi pair / QR column
+constexpr int kRows = kMaxN / kLanes;           // rows per lane
+constexpr int kGroups = kMaxN / 2;              // lane groups (one per pair of a round)
+constexpr int kUpdThreads = kLanes * kGroups;   // update kernel
+constexpr int kThreads = 256;                   // energy kernel
+static_assert(kMaxN <= 64, "a QR step holds one remaining row or column per lane of a wave");
+static_assert(2 * kGroups >= kMaxN - 1, "two trailing columns per group cover a QR step");
+// the contraction: one 2 x 2 block of (a, b) per thread
+static_assert(((kMaxChi + 1) / 2) * ((kMaxChi + 1) / 2) <= kUpdThreads, "contraction blocks");
+// the transposition R -> A through registers
+constexpr int kPerThread = (kMaxN * kMaxN + kUpdThreads - 1) / kUpdThreads;
+// the product B1' = P Y_kept: kUpdThreads / n >= 4 groups of n lanes, each
+// lane one row and at most this many kept columns
+constexpr int kMaxColsPerLane = (kMaxChi + 3) / 4;
+static_assert(kUpdThreads / kMaxN >= 4, "row-parallel product assumes at least 4 lane groups");
 constexpr int kUpdatesPerLaunch = 32;
-constexpr int kMaxSweeps = 40;
-// rotate a pair while |w_p.w_q| > kTol |w_p| |w_q| (relative test)
+// rotate a pair while |a_p.a_q| > kTol |a_p| |a_q| (relative test)
 constexpr double kTol = 1e-14;
 
 struct Gate {
@@ -73,133 +92,266 @@ __device__ __forceinline__ double dpp_d(double v) {
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// sum over an aligned row of sixteen lanes: partner lane ^1 (quad_perm
-// [1,0,3,2]), ^2 (quad_perm [2,3,0,1]), the mirror lane 7 - l inside the
-// half-row (the other quad), then the mirror lane 15 - l inside the row (the
-// other half-row)
-__device__ __forceinline__ double sum16(double v) {
+// sum over an aligned group of eight lanes: partner lane ^1 (quad_perm
+// [1,0,3,2]), ^2 (quad_perm [2,3,0,1]), then the mirror lane 7 - l inside
+// the half-row (the other quad)
+__device__ __forceinline__ double sum8(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x141>(v);
-    v += dpp_d<0x140>(v);
     return v;
 }
 
-// four waves per SIMD (at most 128 VGPRs): with 75 KB of LDS two workgroups
-// of eight waves then share a CU
-__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev, double* __restrict__ pair,
+// butterfly sum over the 64 lanes of a wave (identical bits in every lane)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void itebd_update_kernel(double* __restrict__ states, double* __restrict__ pair, int* __restrict__ status,
                          int* __restrict__ sweeps_out, unsigned long long* __restrict__ work, int chi, Gate G,
-                         long base, int nupd)
+                         int nupd, int max_sweeps)
 {
-    // 75 KB in all, so two chains share a CU
-    __shared__ double sW[kMaxN * kMaxLd];   // column-major, stride ld
-    __shared__ double sV[kMaxN * kMaxLd];   // also stages B1 and B2 at the start of an update
+    __shared__ double sA[kMaxN * kLd];      // work matrix, column-major, stride kLd; stages B1 and B2
     __shared__ double sl1[kMaxChi], sl2[kMaxChi];
-    __shared__ double ssig[kMaxN], ssgn[kMaxChi];
-    __shared__ int sord[kMaxChi];
+    __shared__ double sG[16];                // the gate (read from LDS: no long-lived scalar copies)
+    __shared__ double scn[2][kMaxN];         // squared norms of the remaining columns, by QR step parity
+    __shared__ double sdiag[kMaxN];          // diagonal of R
+    __shared__ double ssig[kMaxN], ssgn[kMaxChi], sscale[kMaxChi];
+    __shared__ int scol[kMaxN], sinv[kMaxN], sord[kMaxChi];
     __shared__ int srot;
-    __shared__ unsigned int srotc;   // rotations applied in this update
+    __shared__ unsigned long long srotc;
     __shared__ double snrm;
 
     const int tid = threadIdx.x;
+    if (status[blockIdx.x] & ITEBD_CHAIN_NONFINITE) return;   // a failed chain stays as it was
     const int n = 2 * chi;
-    const int ld = col_stride(n);
+    constexpr int ld = kLd;
     const int nb = 2 * chi * chi;
     const long len = 2L * nb + 2 * chi;
     double* st = states + (long)blockIdx.x * len;        // B1 and B2 are rewritten every update
-    double* vp = vprev + (long)blockIdx.x * 2 * n * n;
     double* gP = pair + (long)blockIdx.x * n * n;        // P, column-major: P[(a s),(t b)] at (t b) n + (a s)
-    const int ng = kUpdThreads / n;                      // lane groups of the row-parallel products (>= 8)
+    const int lane = tid & 63;
+    const int g = tid / kLanes, r = tid % kLanes;
+    const int ng = kUpdThreads / n;                      // lane groups of the row-parallel product (>= 4)
     const int prow = tid % n, pgrp = tid / n;
 
     for (int i = tid; i < chi; i += kUpdThreads) {
         sl1[i] = st[2 * nb + i];
         sl2[i] = st[2 * nb + chi + i];
     }
+    if (tid < 16) sG[tid] = G.g[tid];
+    if (tid == 0) srotc = 0;
     __syncthreads();
 
-    int max_sweeps = 0;
-    unsigned long long tot_sweeps = 0, tot_rot = 0;
+    int max_sw = 0, fail = 0;
+    unsigned long long tot_sweeps = 0;
+    unsigned nrot = 0;   // rotations of this lane's group (counted by its lane 0)
     for (int u = 0; u < nupd; ++u) {
-        if (tid == 0) srotc = 0;
-        const long count = base + u;
-        const int par = (int)(count & 1);
-        const bool warm = count >= 2;
-
-        // stage B1 and B2 in the V buffer
-        double* sB1 = sV;
-        double* sB2 = sV + nb;
+        // stage B1 and B2 in the work matrix
+        double* sB1 = sA;
+        double* sB2 = sA + nb;
         for (int i = tid; i < nb; i += kUpdThreads) {
             sB1[i] = st[i];
             sB2[i] = st[nb + i];
         }
         __syncthreads();
-        // contraction P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b] and the gate on the
-        // physical pair: one (a, b) per thread, its four (s, t)
-        for (int idx = tid; idx < chi * chi; idx += kUpdThreads) {
-            const int a = idx / chi, b = idx - (idx / chi) * chi;
-            double v[4];
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) {
-                    const double* x = sB1 + (s * chi + a) * chi;
-                    const double* y = sB2 + t * chi * chi + b;
-                    double acc = 0.0;
-                    for (int c = 0; c < chi; ++c) acc = fma(x[c], y[c * chi], acc);
-                    v[2 * s + t] = acc;
-                }
-            for (int s = 0; s < 2; ++s)
-                for (int t = 0; t < 2; ++t) {
-                    const int o = 2 * s + t;
-                    double acc = 0.0;
-                    for (int i = 0; i < 4; ++i) acc = fma(G.g[4 * o + i], v[i], acc);
-                    gP[(t * chi + b) * n + 2 * a + s] = acc;
-                }
-        }
-        __syncthreads();   // P complete; the staged B1, B2 are no longer needed
-        // starting right basis: the same bond's vectors of two updates ago, or 1
-        // (stored column-major, n x n)
-        double* vpar = vp + (long)par * n * n;
-        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
-            const int j = idx / n, i = idx - (idx / n) * n;
-            sV[j * ld + i] = warm ? vpar[idx] : (i == j ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        // W = diag(lambda_2 (x) 1) P V: thread (row r, group g) forms columns g, g + ng, ...
-        if (pgrp < ng) {
-            double acc[kMaxColsPerLane];
+        // contraction P[(a s),(t b)] = sum_c B1[s][a][c] B2[t][c][b] and the gate on
+        // the physical pair: a 2 x 2 block of (a, b) per thread, its sixteen (s, t)
+        const int nbk = (chi + 1) / 2;
+        double pw[16];
+        const bool blk = tid < nbk * nbk;
+        const int a0 = 2 * (tid / nbk), b0 = 2 * (tid % nbk);
+        if (blk) {
+            double acc[16];
 #pragma unroll
-            for (int q = 0; q < kMaxColsPerLane; ++q) acc[q] = 0.0;
-            if (warm) {
-                for (int k = 0; k < n; ++k) {
-                    const double pk = gP[k * n + prow];
+            for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+            const bool a1 = a0 + 1 < chi, b1 = b0 + 1 < chi;
+            for (int c = 0; c < chi; ++c) {
+                double x[2][2], y[2][2];   // x[a'][s], y[t][b']
 #pragma unroll
-                    for (int q = 0; q < kMaxColsPerLane; ++q) {
-                        const int j = pgrp + q * ng;
-                        if (j < n) acc[q] = fma(pk, sV[j * ld + k], acc[q]);
+                for (int s = 0; s < 2; ++s) {
+                    x[0][s] = sB1[(s * chi + a0) * chi + c];
+                    x[1][s] = a1 ? sB1[(s * chi + a0 + 1) * chi + c] : 0.0;
+                    y[s][0] = sB2[(s * chi + c) * chi + b0];
+                    y[s][1] = b1 ? sB2[(s * chi + c) * chi + b0 + 1] : 0.0;
+                }
+#pragma unroll
+                for (int ap = 0; ap < 2; ++ap)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+#pragma unroll
+                            for (int bp = 0; bp < 2; ++bp) {
+                                const int e = ((ap * 2 + s) * 2 + t) * 2 + bp;
+                                acc[e] = fma(x[ap][s], y[t][bp], acc[e]);
+                            }
+            }
+#pragma unroll
+            for (int ap = 0; ap < 2; ++ap)
+#pragma unroll
+                for (int bp = 0; bp < 2; ++bp) {
+                    double v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = acc[((ap * 2 + (i >> 1)) * 2 + (i & 1)) * 2 + bp];
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        double q = 0.0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) q = fma(sG[4 * o + i], v[i], q);
+                        pw[(ap * 2 + bp) * 4 + o] = q;
+                        const int a = a0 + ap, b = b0 + bp;
+                        if (a < chi && b < chi) gP[((o & 1) * chi + b) * n + 2 * a + (o >> 1)] = q;
                     }
                 }
-            } else {
+        }
+        __syncthreads();   // the staged B1, B2 are no longer needed
+        // W = diag(lambda_2 (x) 1) P into the work matrix, rows n.. of its
+        // columns zero
+        for (int idx = tid; idx < n * (kMaxN - n); idx += kUpdThreads) {
+            const int j = idx / (kMaxN - n), i = n + idx - j * (kMaxN - n);
+            sA[j * ld + i] = 0.0;
+        }
+        if (blk) {
 #pragma unroll
-                for (int q = 0; q < kMaxColsPerLane; ++q) {
-                    const int j = pgrp + q * ng;
-                    if (j < n) acc[q] = gP[j * n + prow];
+            for (int ap = 0; ap < 2; ++ap)
+#pragma unroll
+                for (int bp = 0; bp < 2; ++bp) {
+                    const int a = a0 + ap, b = b0 + bp;
+                    if (a < chi && b < chi) {
+                        const double lam = sl2[a];
+#pragma unroll
+                        for (int o = 0; o < 4; ++o)
+                            sA[((o & 1) * chi + b) * ld + 2 * a + (o >> 1)] = lam * pw[(ap * 2 + bp) * 4 + o];
+                    }
                 }
-            }
-            const double lam = sl2[prow >> 1];
+        }
+        __syncthreads();
+        // squared column norms for the first pivot (column j stored at j)
+        for (int h = 0; h < 2; ++h) {
+            const int l = g + kGroups * h;
+            if (l < n) {
+                double s2 = 0.0;
 #pragma unroll
-            for (int q = 0; q < kMaxColsPerLane; ++q) {
-                const int j = pgrp + q * ng;
-                if (j < n) sW[j * ld + prow] = lam * acc[q];
+                for (int m = 0; m < kRows; ++m) {
+                    const double a = sA[l * ld + r + kLanes * m];
+                    s2 = fma(a, a, s2);
+                }
+                s2 = sum8(s2);
+                if (r == 0) scn[0][l] = s2;
             }
         }
         __syncthreads();
 
-        // one-sided Jacobi
-        const int g = tid / kLanesPerPair, lane = tid % kLanesPerPair;
+        // Householder QR with column pivoting, one barrier per step
+        int col = lane;   // storage column of logical column `lane` (the same in every wave)
+        for (int k = 0; k < n - 1; ++k) {
+            const int cur = k & 1, nxt = cur ^ 1;
+            // pivot: the largest remaining norm, lowest logical index on ties
+            double cv = (lane >= k && lane < n) ? scn[cur][lane] : -1.0;
+            int ci = lane;
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+                const double ov = __shfl_xor(cv, m, 64);
+                const int oi = __shfl_xor(ci, m, 64);
+                if (ov > cv || (ov == cv && oi < ci)) {
+                    cv = ov;
+                    ci = oi;
+                }
+            }
+            int jm = __builtin_amdgcn_readfirstlane(ci);
+            if (jm < k || jm >= n) jm = k;   // only with non-finite norms
+            const int colk = __shfl(col, k, 64), coljm = __shfl(col, jm, 64);
+            col = lane == k ? coljm : (lane == jm ? colk : col);
+            // the reflector H = I - beta v v^T mapping rows k.. of the pivot column to (alpha, 0, ...)
+            const double* Wc = sA + coljm * ld;
+            const double x = k + lane < kMaxN ? Wc[k + lane] : 0.0;
+            const double sig = wave_sum(x * x);
+            const double x0 = __shfl(x, 0, 64);
+            // a remaining column below 1e-140 in norm (zero, in practice) is
+            // left as it is: R[k][k] = x0 and the entries below it, which the
+            // transposition never reads, are dropped; beta then stays finite
+            double al = x0, be = 0.0;
+            if (sig > 1e-280) {
+                al = -copysign(sqrt(sig), x0);
+                be = 1.0 / (sig - x0 * al);
+            }
+            const double v0 = x0 - al;
+            if (tid == 0) sdiag[k] = al;
+            if (k == n - 2 && tid < n) scol[tid] = col;   // the final order (wave 0)
+            // trailing logical columns k + 1 + g and k + 1 + g + kGroups
+            const int l0 = k + 1 + g, l1 = l0 + kGroups;
+            const int c0 = __shfl(col, min(l0, n - 1), 64), c1 = __shfl(col, min(l1, n - 1), 64);
+            double vv[kRows];
+#pragma unroll
+            for (int m = 0; m < kRows; ++m) {
+                const int i = r + kLanes * m;
+                const double wi = Wc[i];
+                vv[m] = i > k ? wi : (i == k ? v0 : 0.0);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int l = h ? l1 : l0;
+                if (l < n) {
+                    double* Wp = sA + (h ? c1 : c0) * ld;
+                    double xr[kRows];
+                    double w = 0.0;
+#pragma unroll
+                    for (int m = 0; m < kRows; ++m) {
+                        xr[m] = Wp[r + kLanes * m];
+                        w = fma(vv[m], xr[m], w);   // v is zero above row k
+                    }
+                    w = sum8(w);
+                    const double bw = be * w;
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int m = 0; m < kRows; ++m) {
+                        const int i = r + kLanes * m;
+                        xr[m] = fma(-bw, vv[m], xr[m]);   // rows above k unchanged
+                        Wp[i] = xr[m];
+                        s2 = fma(i > k ? xr[m] : 0.0, xr[m], s2);
+                    }
+                    s2 = sum8(s2);
+                    if (r == 0) scn[nxt][l] = s2;
+                }
+            }
+            __syncthreads();
+        }
+        // A = R^T, column-major: A[l][j] = R[j][l] (l >= j); R[j][l] is row j of
+        // the storage column of logical column l, R[j][j] the reflector's alpha
+        // (row n - 1 has no reflector)
+        {
+            double tv[kPerThread];
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                const int e = tid + kUpdThreads * q;
+                tv[q] = 0.0;
+                if (e < n * n) {
+                    const int j = e / n, l = e - (e / n) * n;
+                    if (l > j || (l == j && j == n - 1)) tv[q] = sA[scol[l] * ld + j];
+                    else if (l == j) tv[q] = sdiag[j];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                const int e = tid + kUpdThreads * q;
+                if (e < n * n) {
+                    const int j = e / n, l = e - (e / n) * n;
+                    sA[j * ld + l] = tv[q];
+                }
+            }
+            if (tid < n) sinv[scol[tid]] = tid;
+            __syncthreads();
+        }
+
+        // one-sided Jacobi on the columns of A
         const int npair = n >> 1;
-        int sweeps = kMaxSweeps;
-        for (int sw = 0; sw < kMaxSweeps; ++sw) {
+        int sweeps = max_sweeps + 1;   // not converged
+        for (int sw = 0; sw < max_sweeps; ++sw) {
             if (tid == 0) srot = 0;
             __syncthreads();
             for (int rd = 0; rd < n - 1; ++rd) {
@@ -214,35 +366,24 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev
                         q = rd - g;
                         q += q < 0 ? n - 1 : 0;
                     }
-                    double* Wp = sW + p * ld;
-                    double* Wq = sW + q * ld;
-                    double* Vp = sV + p * ld;
-                    double* Vq = sV + q * ld;
-                    // both columns of W and of V in registers: the V loads are in
-                    // flight while the dot products and the rotation are formed
-                    double wp[kRowsPerLane], wq[kRowsPerLane], vpr[kRowsPerLane], vqr[kRowsPerLane];
+                    double* Ap = sA + p * ld;
+                    double* Aq = sA + q * ld;
+                    double wp[kRows], wq[kRows];
                     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                    for (int r = 0; r < kRowsPerLane; ++r) {
-                        const int i = lane + kLanesPerPair * r;
-                        wp[r] = i < n ? Wp[i] : 0.0;
-                        wq[r] = i < n ? Wq[i] : 0.0;
+                    for (int m = 0; m < kRows; ++m) {
+                        wp[m] = Ap[r + kLanes * m];
+                        wq[m] = Aq[r + kLanes * m];
                     }
 #pragma unroll
-                    for (int r = 0; r < kRowsPerLane; ++r) {
-                        const int i = lane + kLanesPerPair * r;
-                        vpr[r] = i < n ? Vp[i] : 0.0;
-                        vqr[r] = i < n ? Vq[i] : 0.0;
+                    for (int m = 0; m < kRows; ++m) {
+                        al = fma(wp[m], wp[m], al);
+                        be = fma(wq[m], wq[m], be);
+                        ga = fma(wp[m], wq[m], ga);
                     }
-#pragma unroll
-                    for (int r = 0; r < kRowsPerLane; ++r) {
-                        al = fma(wp[r], wp[r], al);
-                        be = fma(wq[r], wq[r], be);
-                        ga = fma(wp[r], wq[r], ga);
-                    }
-                    al = sum16(al);
-                    be = sum16(be);
-                    ga = sum16(ga);
+                    al = sum8(al);
+                    be = sum8(be);
+                    ga = sum8(ga);
                     // rotate while ga^2 > kTol^2 al be (the relative test, squared)
                     if (ga * ga > (kTol * kTol) * (al * be)) {
                         // the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga):
@@ -251,18 +392,13 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev
                         const double t = (d >= 0.0 ? g2 : -g2) / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
                         const double c = rsqrt(fma(t, t, 1.0)), s = c * t;
 #pragma unroll
-                        for (int r = 0; r < kRowsPerLane; ++r) {
-                            const int i = lane + kLanesPerPair * r;
-                            if (i < n) {
-                                Wp[i] = c * wp[r] - s * wq[r];
-                                Wq[i] = s * wp[r] + c * wq[r];
-                                Vp[i] = c * vpr[r] - s * vqr[r];
-                                Vq[i] = s * vpr[r] + c * vqr[r];
-                            }
+                        for (int m = 0; m < kRows; ++m) {
+                            Ap[r + kLanes * m] = c * wp[m] - s * wq[m];
+                            Aq[r + kLanes * m] = s * wp[m] + c * wq[m];
                         }
-                        if (lane == 0) {
+                        if (r == 0) {
                             srot = 1;
-                            atomicAdd(&srotc, 1u);
+                            ++nrot;
                         }
                     }
                 }
@@ -275,15 +411,26 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev
                 break;
             }
         }
-        max_sweeps = max(max_sweeps, sweeps);
+        if (sweeps > max_sweeps) {
+            fail |= ITEBD_CHAIN_SWEEP_CAP;   // the last sweep still rotated: used as it stands
+            sweeps = max_sweeps;
+        }
+        max_sw = max(max_sw, sweeps);
         tot_sweeps += (unsigned long long)sweeps;
-        tot_rot += (unsigned long long)srotc;   // read after the sweeps' barriers
 
-        // singular values, the chi largest (ties: lower column first)
-        for (int j = tid; j < n; j += kUpdThreads) {
-            double acc = 0.0;
-            for (int i = 0; i < n; ++i) acc = fma(sW[j * ld + i], sW[j * ld + i], acc);
-            ssig[j] = sqrt(acc);
+        // singular values (column norms), the chi largest (ties: lower column first)
+        for (int h = 0; h < 2; ++h) {
+            const int l = g + kGroups * h;
+            if (l < n) {
+                double s2 = 0.0;
+#pragma unroll
+                for (int m = 0; m < kRows; ++m) {
+                    const double a = sA[l * ld + r + kLanes * m];
+                    s2 = fma(a, a, s2);
+                }
+                s2 = sum8(s2);
+                if (r == 0) ssig[l] = sqrt(s2);
+            }
         }
         __syncthreads();
         for (int j = tid; j < n; j += kUpdThreads) {
@@ -292,56 +439,59 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev
             if (rank < chi) sord[rank] = j;
         }
         __syncthreads();
-        // sign gauge of the kept right vectors; norm of the kept values
+        // kept right vectors y_c[m] = A[sinv[m]][sord[c]] / sigma: sign gauge (largest
+        // magnitude entry positive, the lowest m on ties) and scale; norm of the kept values
         for (int c = tid; c < chi; c += kUpdThreads) {
             const int j = sord[c];
             double best = -1.0;
-            int bi = 0;
-            for (int i = 0; i < n; ++i) {
-                const double a = fabs(sV[j * ld + i]);
+            int bm = 0;
+            for (int m = 0; m < n; ++m) {
+                const double a = fabs(sA[j * ld + sinv[m]]);
                 if (a > best) {
                     best = a;
-                    bi = i;
+                    bm = m;
                 }
             }
-            ssgn[c] = sV[j * ld + bi] < 0.0 ? -1.0 : 1.0;
+            const double sgn = sA[j * ld + sinv[bm]] < 0.0 ? -1.0 : 1.0;
+            ssgn[c] = sgn;
+            sscale[c] = ssig[j] > 0.0 ? sgn / ssig[j] : 0.0;   // a zero value keeps a zero vector
         }
         if (tid == 0) {
             double acc = 0.0;
             for (int c = 0; c < chi; ++c) acc = fma(ssig[sord[c]], ssig[sord[c]], acc);
             snrm = sqrt(acc);
         }
-        // the bond's right vectors for the next warm start
-        for (int idx = tid; idx < n * n; idx += kUpdThreads) {
-            const int j = idx / n, i = idx - (idx / n) * n;
-            vpar[idx] = sV[j * ld + i];
-        }
         __syncthreads();
+        const double nrm = snrm;
+        if (!(nrm > 0.0) || !isfinite(nrm)) {   // the same in every thread
+            fail |= ITEBD_CHAIN_NONFINITE;      // this update is not applied, and no later one
+            break;
+        }
         // new tensors, roles exchanged, into the state row:
-        //   B1 <- B2' = V_kept^T, B2 <- B1' = P V_kept / nrm
-        const double inv = 1.0 / snrm;
+        //   B1 <- B2' = Y_kept^T, B2 <- B1' = P Y_kept / nrm
+        const double inv = 1.0 / nrm;
         for (int idx = tid; idx < nb; idx += kUpdThreads) {
             const int t = idx / (chi * chi), rem = idx - t * chi * chi;
             const int c = rem / chi, b = rem - (rem / chi) * chi;
-            st[idx] = ssgn[c] * sV[sord[c] * ld + t * chi + b];
+            st[idx] = sscale[c] * sA[sord[c] * ld + sinv[t * chi + b]];
         }
-        if (pgrp < ng) {   // row (a s) = prow, kept columns c = g, g + ng, ...
+        if (pgrp < ng) {   // row (a s) = prow, kept columns c = pgrp, pgrp + ng, ...
             double acc[kMaxColsPerLane];
 #pragma unroll
             for (int q = 0; q < kMaxColsPerLane; ++q) acc[q] = 0.0;
-            for (int k = 0; k < n; ++k) {
-                const double pk = gP[k * n + prow];
+            for (int i = 0; i < n; ++i) {
+                const double pk = gP[scol[i] * n + prow];
 #pragma unroll
                 for (int q = 0; q < kMaxColsPerLane; ++q) {
                     const int c = pgrp + q * ng;
-                    if (c < chi) acc[q] = fma(pk, sV[sord[c] * ld + k], acc[q]);
+                    if (c < chi) acc[q] = fma(pk, sA[sord[c] * ld + i], acc[q]);
                 }
             }
             const int a = prow >> 1, sp = prow & 1;
 #pragma unroll
             for (int q = 0; q < kMaxColsPerLane; ++q) {
                 const int c = pgrp + q * ng;
-                if (c < chi) st[nb + (sp * chi + a) * chi + c] = ssgn[c] * inv * acc[q];
+                if (c < chi) st[nb + (sp * chi + a) * chi + c] = sscale[c] * inv * acc[q];
             }
         }
         for (int c = tid; c < chi; c += kUpdThreads) {
@@ -352,14 +502,19 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ vprev
         __syncthreads();
     }
 
+    // the weights of the last applied update (after a failed one, the state
+    // row still holds that update's tensors)
     for (int i = tid; i < chi; i += kUpdThreads) {
         st[2 * nb + i] = sl1[i];
         st[2 * nb + chi + i] = sl2[i];
     }
+    if (r == 0 && nrot) atomicAdd(&srotc, (unsigned long long)nrot);
+    __syncthreads();
     if (tid == 0) {
-        sweeps_out[blockIdx.x] = max_sweeps;
+        sweeps_out[blockIdx.x] = max_sw;
         work[2 * blockIdx.x] += tot_sweeps;
-        work[2 * blockIdx.x + 1] += tot_rot;
+        work[2 * blockIdx.x + 1] += srotc;
+        status[blockIdx.x] |= fail;
     }
 }
 
@@ -420,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void itebd_energy_kernel(const double* __
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t states, vprev, pair, sweeps, work, energies, total;
+    size_t states, pair, status, sweeps, work, energies, total;
 };
 
 Layout plan(int batch, int chi) {
@@ -430,10 +585,10 @@ Layout plan(int batch, int chi) {
     size_t o = 0;
     L.states = o;
     o = round_up(o + 8 * len * batch, 256);
-    L.vprev = o;
-    o = round_up(o + 8 * 2 * n * n * batch, 256);
     L.pair = o;
     o = round_up(o + 8 * n * n * batch, 256);
+    L.status = o;
+    o = round_up(o + 4 * (size_t)batch, 256);
     L.sweeps = o;
     o = round_up(o + 4 * (size_t)batch, 256);
     L.work = o;
@@ -491,6 +646,9 @@ Gate gate_of(const double* h, double tau) {
 
 }  // namespace
 
+struct itebd_batch;
+static int chain_status(itebd_batch* b, int* per_chain);
+
 struct itebd_batch {
     int batch = 0, chi = 0;
     double h[16];
@@ -498,6 +656,7 @@ struct itebd_batch {
     char* ws = nullptr;
     Layout L;
     long updates = 0;
+    int max_sweeps = ITEBD_MAX_SWEEPS;
     int host_status = HOTRG_OK;
     double* states() const { return reinterpret_cast<double*>(ws + L.states); }
 };
@@ -538,6 +697,7 @@ int itebd_init(int batch, int chi, const double* h, const double* states, void* 
     b->L = L;
     const size_t bytes = 8 * itebd_state_len(chi) * (size_t)batch;
     if (hipMemcpyAsync(b->states(), states, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemsetAsync(b->ws + L.status, 0, 4 * (size_t)batch, b->stream) != hipSuccess ||
         hipMemsetAsync(b->ws + L.sweeps, 0, 4 * (size_t)batch, b->stream) != hipSuccess ||
         hipMemsetAsync(b->ws + L.work, 0, 16 * (size_t)batch, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
@@ -552,14 +712,14 @@ int itebd_evolve(itebd_batch* b, double tau, int nupdates) {
     if (!b || nupdates < 0 || !(tau > 0.0) || !isfinite(tau)) return HOTRG_EINVAL;
     if (b->host_status) return HOTRG_ESTATE;
     const Gate G = gate_of(b->h, tau);
-    double* vprev = reinterpret_cast<double*>(b->ws + b->L.vprev);
     double* pair = reinterpret_cast<double*>(b->ws + b->L.pair);
+    int* status = reinterpret_cast<int*>(b->ws + b->L.status);
     int* sweeps = reinterpret_cast<int*>(b->ws + b->L.sweeps);
     unsigned long long* work = reinterpret_cast<unsigned long long*>(b->ws + b->L.work);
     for (int done = 0; done < nupdates;) {
         const int k = std::min(kUpdatesPerLaunch, nupdates - done);
         hipLaunchKernelGGL(itebd_update_kernel, dim3((unsigned)b->batch), dim3(kUpdThreads), 0, b->stream, b->states(),
-                           vprev, pair, sweeps, work, b->chi, G, b->updates, k);
+                           pair, status, sweeps, work, b->chi, G, k, b->max_sweeps);
         if (hipGetLastError() != hipSuccess) {
             b->host_status = HOTRG_EHIP;
             return HOTRG_EHIP;
@@ -582,7 +742,7 @@ int itebd_energy(itebd_batch* b, double* energies) {
         hipMemcpyAsync(energies, dev, 8 * (size_t)b->batch, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return HOTRG_EHIP;
-    return HOTRG_OK;
+    return chain_status(b, nullptr);
 }
 
 int itebd_copy_states(itebd_batch* b, double* host, size_t capacity) {
@@ -629,8 +789,46 @@ int itebd_info(itebd_batch* b, long* updates, int* max_sweeps) {
         if (!ok) return HOTRG_EHIP;
         *max_sweeps = m;
     }
+    return chain_status(b, nullptr);
+}
+
+int itebd_status(itebd_batch* b, int* status) {
+    if (!b || !status) return HOTRG_EINVAL;
+    const int rc = chain_status(b, status);
+    return rc == HOTRG_EHIP ? rc : HOTRG_OK;
+}
+
+int itebd_set_max_sweeps(itebd_batch* b, int max_sweeps) {
+    if (!b || max_sweeps < 1 || max_sweeps > ITEBD_MAX_SWEEPS) return HOTRG_EINVAL;
+    b->max_sweeps = max_sweeps;
     return HOTRG_OK;
 }
+
+}  // extern "C"
+
+// Synchronises, copies the per-chain status words (into per_chain when
+// given) and maps them to one code: ENONFINITE if a chain stopped on a
+// vanishing or non-finite norm, else EEIG if a decomposition reached the
+// sweep limit, else OK.
+static int chain_status(itebd_batch* b, int* per_chain) {
+    int* host = new (std::nothrow) int[b->batch];
+    if (!host) return HOTRG_EINVAL;
+    const bool ok = hipMemcpyAsync(host, b->ws + b->L.status, 4 * (size_t)b->batch, hipMemcpyDeviceToHost,
+                                   b->stream) == hipSuccess &&
+                    hipStreamSynchronize(b->stream) == hipSuccess;
+    int any = 0;
+    for (int i = 0; ok && i < b->batch; ++i) {
+        any |= host[i];
+        if (per_chain) per_chain[i] = host[i];
+    }
+    delete[] host;
+    if (!ok) return HOTRG_EHIP;
+    if (any & ITEBD_CHAIN_NONFINITE) return HOTRG_ENONFINITE;
+    if (any & ITEBD_CHAIN_SWEEP_CAP) return HOTRG_EEIG;
+    return HOTRG_OK;
+}
+
+extern "C" {
 
 void itebd_destroy(itebd_batch* b) {
     if (!b) return;

@@ -145,14 +145,16 @@ def test_itebd_sizes_and_error_paths(lib):
     assert lib.itebd_state_len(0) == 0 and lib.itebd_state_len(33) == 0
     assert lib.itebd_workspace_bytes(0, 8) == 0 and lib.itebd_workspace_bytes(4, 33) == 0
     w = lib.itebd_workspace_bytes(256, 32)
-    # states, the evolved pair and two warm-start bases per chain (n^2 each, n = 64), counters
-    per_chain = (4 * 1024 + 64) + 3 * 64 * 64
-    assert 256 * per_chain * 8 <= w < 1.01 * (256 * per_chain * 8) + 8192
+    # states and the evolved pair per chain (n^2, n = 64), status words, counters
+    per_chain = (4 * 1024 + 64) + 64 * 64
+    assert 256 * per_chain * 8 <= w < 1.01 * (256 * per_chain * 8) + 16384
     h = ctypes.c_void_p()
     assert lib.itebd_init(1, 8, None, None, None, 0, None, ctypes.byref(h)) == binding.EINVAL
     assert lib.itebd_evolve(None, 0.1, 1) == binding.EINVAL
     assert lib.itebd_energy(None, None) == binding.EINVAL
     assert lib.itebd_info(None, None, None) == binding.EINVAL
+    assert lib.itebd_status(None, None) == binding.EINVAL
+    assert lib.itebd_set_max_sweeps(None, 5) == binding.EINVAL
     lib.itebd_destroy(None)
 
 

@@ -181,3 +181,62 @@ def test_benchmark_launch_configuration_elementwise_tfim(gpu_lib):
         np.testing.assert_allclose(g.B2, ref.B2, atol=1e-9)
         er = oracle.energy_per_site(ref, h)
         assert abs(e[i] - er) <= 1e-12 * abs(er)
+
+
+def test_vanishing_chain_is_frozen_and_reported_others_unaffected(gpu_lib):
+    """A chain whose state is all zeros contracts to a zero pair: its kept
+    singular values have zero norm, so its status word gets
+    ITEBD_CHAIN_NONFINITE, the update is not applied (the state row stays
+    as uploaded) and itebd_energy / itebd_info return ENONFINITE.  The
+    batch's other chains are bitwise what they are without it.  Every
+    kernel runs to its normal end (a zero matrix needs no rotation)."""
+    from paper_2602_05900_amd import binding
+    chi = 8
+    h = workloads.ising_transverse_bond(1.5)
+    states = workloads.random_chain_states(3, chi, seed=13)
+    states[1] = 0.0
+    c = binding.Chains(h, states, chi)
+    c.evolve(0.05, 40)
+    with pytest.raises(binding.HotrgError) as e:
+        c.energies()
+    assert e.value.status == binding.ENONFINITE
+    with pytest.raises(binding.HotrgError) as e:
+        c.info()
+    assert e.value.status == binding.ENONFINITE
+    assert list(c.status()) == [0, binding.ITEBD_CHAIN_NONFINITE, 0]
+    got = c.states()
+    assert np.array_equal(got[1], states[1])
+    c.close()
+    alone = gpu_run(h, states[[0, 2]], chi, ((0.05, 40),))
+    assert list(alone.status()) == [0, 0]
+    assert np.array_equal(alone.states(), got[[0, 2]])
+    alone.close()
+
+
+def test_sweep_limit_is_reported(gpu_lib):
+    """With a limit of one Jacobi sweep no decomposition can be recognised
+    as converged (that takes a sweep without rotations): every chain's
+    status word gets ITEBD_CHAIN_SWEEP_CAP and the synchronising calls
+    return EEIG, while the updates are still applied and stay finite.  The
+    default limit reports nothing; limits outside 1..ITEBD_MAX_SWEEPS are
+    rejected."""
+    from paper_2602_05900_amd import binding
+    chi = 8
+    h = workloads.heisenberg_bond()
+    states = workloads.random_chain_states(2, chi, seed=17)
+    c = binding.Chains(h, states, chi)
+    for bad in (0, binding.ITEBD_MAX_SWEEPS + 1):
+        with pytest.raises(binding.HotrgError) as e:
+            c.set_max_sweeps(bad)
+        assert e.value.status == binding.EINVAL
+    c.set_max_sweeps(1)
+    c.evolve(0.05, 4)
+    with pytest.raises(binding.HotrgError) as e:
+        c.info()
+    assert e.value.status == binding.EEIG
+    assert list(c.status()) == [binding.ITEBD_CHAIN_SWEEP_CAP] * 2
+    assert np.all(np.isfinite(c.states()))
+    c.close()
+    d = gpu_run(h, states, chi, ((0.05, 4),))
+    assert d.info()[0] == 4 and list(d.status()) == [0, 0]
+    d.close()
