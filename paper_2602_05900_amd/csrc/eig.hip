@@ -206,6 +206,7 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
     __shared__ double cs[EIG_PMAX / 2], sn[EIG_PMAX / 2], tt[EIG_PMAX / 2];
     __shared__ int pi[EIG_PMAX / 2], pj[EIG_PMAX / 2];
     __shared__ int any_rot;
+    __shared__ double sfloor;
     __shared__ int rank[EIG_PMAX];
     const int tid = threadIdx.x;
     const int pp = p + (p & 1);   // even number of players; index p (if any) is a zero dummy
@@ -221,13 +222,21 @@ __global__ __launch_bounds__(EIG_JT) void eig_jacobi_kernel(const double* __rest
         H[i * EIG_LDP + j] = h;
         V[i * EIG_LDP + j] = (i == j) ? 1.0 : 0.0;
     }
+    if (tid == 0) {
+        double m = 0.0;
+        for (int i = 0; i < p; ++i) m = fmax(m, fabs(Hin[(long)i * ldh + i]));
+        sfloor = fmax(1e-300, 1e-18 * m);
+    }
     __syncthreads();
     // Rotation test: an off-diagonal element is zeroed while it is large
-    // relative to its own diagonal pair, |hij| > 1e-14 sqrt|hii hjj|, taken
-    // squared (no square root on the round's critical path; off-diagonal
-    // elements below ~1e-154 count as zero).
+    // relative to its own diagonal pair, |hij| > 1e-14 sqrt|hii hjj| (taken
+    // squared: no square root on the round's critical path), and above
+    // 1e-18 of the largest diagonal element: smaller elements lie under the
+    // rounding of the matrix itself (a rank-deficient tail would otherwise be
+    // rotated until its elements are tiny next to its own tiny diagonal).
+    const double floor_abs = sfloor;
     auto passes = [&](double hij, double hii, double hjj) {
-        return hij * hij > 1e-28 * fabs(hii * hjj) && fabs(hij) > 1e-300;
+        return hij * hij > 1e-28 * fabs(hii * hjj) && fabs(hij) > floor_abs;
     };
     int sweeps = 0, capped = 0;
     for (int sweep = 0;; ++sweep) {

@@ -102,11 +102,67 @@ __device__ __forceinline__ double sum8(double v) {
     return v;
 }
 
-// butterfly sum over the 64 lanes of a wave (identical bits in every lane)
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+// sum over a row of sixteen lanes: sum8, then the mirror lane 15 - l inside
+// the row (the other half-row)
+__device__ __forceinline__ double sum16(double v) {
+    v = sum8(v);
+    v += dpp_d<0x140>(v);
     return v;
+}
+
+template <int Ctrl>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, Ctrl, 0xF, 0xF, false);
+}
+
+// a double of lane l (uniform l) in every lane
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// sum over the 64 lanes of a wave: the four row sums (sum16), read from one
+// lane of each row and added in a fixed order, so every lane, and every wave
+// holding the same data, gets the same bits
+__device__ __forceinline__ double wave_sum(double v) {
+    v = sum16(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// (v, i) beats (w, j): larger value, lower index on ties
+__device__ __forceinline__ bool beats(double v, int i, double w, int j) { return v > w || (v == w && i < j); }
+
+template <int Ctrl>
+__device__ __forceinline__ void argmax_step(double& v, int& i) {
+    const double ov = dpp_d<Ctrl>(v);
+    const int oi = dpp_i<Ctrl>(i);
+    if (beats(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+// index of the largest value over the wave (lowest index on ties): the same
+// pairings as sum16 inside each row, then the four row winners in order
+__device__ __forceinline__ int wave_argmax(double v, int i) {
+    argmax_step<0xB1>(v, i);
+    argmax_step<0x4E>(v, i);
+    argmax_step<0x141>(v, i);
+    argmax_step<0x140>(v, i);
+    double bv = readlane_d(v, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+        const double ov = readlane_d(v, 16 * w);
+        const int oi = __builtin_amdgcn_readlane(i, 16 * w);
+        if (beats(ov, oi, bv, bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    return bi;
 }
 
 __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(2)))
@@ -250,27 +306,20 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ pair,
         int col = lane;   // storage column of logical column `lane` (the same in every wave)
         for (int k = 0; k < n - 1; ++k) {
             const int cur = k & 1, nxt = cur ^ 1;
+            // storage columns of this group's trailing logical columns k + 1 + g and
+            // k + 1 + g + kGroups before this step's swap (fetched while the pivot is found)
+            const int l0 = k + 1 + g, l1 = l0 + kGroups;
+            const int cb0 = __shfl(col, min(l0, n - 1), 64), cb1 = __shfl(col, min(l1, n - 1), 64);
             // pivot: the largest remaining norm, lowest logical index on ties
-            double cv = (lane >= k && lane < n) ? scn[cur][lane] : -1.0;
-            int ci = lane;
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-                const double ov = __shfl_xor(cv, m, 64);
-                const int oi = __shfl_xor(ci, m, 64);
-                if (ov > cv || (ov == cv && oi < ci)) {
-                    cv = ov;
-                    ci = oi;
-                }
-            }
-            int jm = __builtin_amdgcn_readfirstlane(ci);
+            int jm = wave_argmax((lane >= k && lane < n) ? scn[cur][lane] : -1.0, lane);
             if (jm < k || jm >= n) jm = k;   // only with non-finite norms
-            const int colk = __shfl(col, k, 64), coljm = __shfl(col, jm, 64);
+            const int colk = __builtin_amdgcn_readlane(col, k), coljm = __builtin_amdgcn_readlane(col, jm);
             col = lane == k ? coljm : (lane == jm ? colk : col);
             // the reflector H = I - beta v v^T mapping rows k.. of the pivot column to (alpha, 0, ...)
             const double* Wc = sA + coljm * ld;
             const double x = k + lane < kMaxN ? Wc[k + lane] : 0.0;
             const double sig = wave_sum(x * x);
-            const double x0 = __shfl(x, 0, 64);
+            const double x0 = readlane_d(x, 0);
             // a remaining column below 1e-140 in norm (zero, in practice) is
             // left as it is: R[k][k] = x0 and the entries below it, which the
             // transposition never reads, are dropped; beta then stays finite
@@ -282,9 +331,8 @@ void itebd_update_kernel(double* __restrict__ states, double* __restrict__ pair,
             const double v0 = x0 - al;
             if (tid == 0) sdiag[k] = al;
             if (k == n - 2 && tid < n) scol[tid] = col;   // the final order (wave 0)
-            // trailing logical columns k + 1 + g and k + 1 + g + kGroups
-            const int l0 = k + 1 + g, l1 = l0 + kGroups;
-            const int c0 = __shfl(col, min(l0, n - 1), 64), c1 = __shfl(col, min(l1, n - 1), 64);
+            // the swap moved logical column jm's storage to k and k's to jm
+            const int c0 = l0 == jm ? colk : cb0, c1 = l1 == jm ? colk : cb1;
             double vv[kRows];
 #pragma unroll
             for (int m = 0; m < kRows; ++m) {
