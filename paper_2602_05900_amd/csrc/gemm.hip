@@ -515,6 +515,56 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         }
     }
 
+    // Wave tiles of more than four 32 x 32 fragments: the output goes
+    // through 16-row FP32 slabs in LDS (the A and B tiles are free now), so
+    // the accumulators are only ever indexed with constants; indexing them
+    // by a loop counter the compiler keeps as a loop would put the whole
+    // accumulator array in scratch memory in every launch.  A lane stores
+    // columns lane, lane + 64, ... of each slab row.
+    constexpr int RW4 = WN + 4;
+    constexpr int SLAB4 = 16 * RW4;
+    constexpr int A_SLABS = (int)(sizeof(As) / sizeof(float)) / SLAB4;
+    constexpr int B_SLABS = (int)(sizeof(Bs) / sizeof(float)) / SLAB4;
+    constexpr int NW = WAVES_M * WAVES_N;
+    if constexpr (FM * FN > 4 && A_SLABS + B_SLABS >= NW) {
+        constexpr int CPLG = (WN + 63) / 64;
+        float* reg = wave < A_SLABS ? reinterpret_cast<float*>(&As[0][0][0]) + wave * SLAB4
+                                    : reinterpret_cast<float*>(&Bs[0][0][0]) + (wave - A_SLABS) * SLAB4;
+        MapPart gcol[CPLG];
+        bool gok[CPLG];
+#pragma unroll
+        for (int t = 0; t < CPLG; ++t) {
+            const int c = lane + 64 * t;
+            const int n = c < WN ? n0 + wn * WN + c : N;
+            gok[t] = n < N;
+            gcol[t] = gok[t] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int rr = 0; rr < 8; ++rr) {
+                        const int row = 8 * (rr >> 2) + 4 * fk + (rr & 3);
+                        reg[row * RW4 + j * 32 + frow] = acc[i][j][8 * h + rr];
+                    }
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's staging writes are done
+                for (int row = 0; row < 16; ++row) {
+                    const int m = m0 + wm * WM + i * 32 + 16 * h + row;
+                    if (m >= M) break;
+                    const MapPart roff = map_row(mp, (unsigned)m);
+#pragma unroll
+                    for (int t = 0; t < CPLG; ++t)
+                        if (gok[t]) store(map_off(mp, roff, gcol[t]), reg[row * RW4 + lane + 64 * t]);
+                }
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // staging reads are done before the region is rewritten
+            }
+        }
+        return;
+    }
+
     MapPart coff[FN];
     bool cin[FN];
 #pragma unroll
@@ -959,6 +1009,50 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             }
             return;
         }
+        // Any other output (element stores through the map, in any format):
+        // through the same FP32 slabs, so the accumulators are only ever
+        // indexed with constants.  (Indexing them by a loop counter that the
+        // compiler keeps as a loop puts the whole accumulator array in scratch
+        // memory: zeroed at the start and stored after the K loop in every
+        // launch, whatever the output path, 2 x 512 bytes per lane.)  A lane
+        // stores columns lane, lane + 64, ... of each slab row.
+        constexpr int CPLG = (WN + 63) / 64;
+        __syncthreads();   // every wave is done reading the stages
+        const int ar = wave / PER_ARRAY4;
+        float* reg = reinterpret_cast<float*>(ar == 0 ? S0 : (ar == 1 ? S1 : S2)) + (wave - ar * PER_ARRAY4) * SLAB4;
+        MapPart gcol[CPLG];
+        bool gok[CPLG];
+#pragma unroll
+        for (int t = 0; t < CPLG; ++t) {
+            const int c = lane + 64 * t;
+            const int n = c < WN ? ncol(wn * WN + c) : N;
+            gok[t] = n < N;
+            gcol[t] = gok[t] ? map_col(mp, (unsigned)n) : MapPart{0, 0};
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int rr = 0; rr < 8; ++rr) {
+                        const int row = 8 * (rr >> 2) + 4 * fk + (rr & 3);
+                        reg[row * RW4 + j * 32 + frow] = acc[i][j][8 * h + rr];
+                    }
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's staging writes are done
+                for (int row = 0; row < 16; ++row) {
+                    const int m = m0 + wm * WM + i * 32 + 16 * h + row;
+                    if (m >= M) break;
+                    const MapPart roff = map_row(mp, (unsigned)m);
+#pragma unroll
+                    for (int t = 0; t < CPLG; ++t)
+                        if (gok[t]) store(map_off(mp, roff, gcol[t]), reg[row * RW4 + lane + 64 * t]);
+                }
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // staging reads are done before the region is rewritten
+            }
+        }
+        return;
     }
 
     MapPart coff[FN];
