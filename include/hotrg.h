@@ -238,8 +238,14 @@ int hotrg_log_z_chain(hotrg_solve* s, double* lnz_per_tensor);
 /* Synchronises and reports diagnostics of step n (1..steps taken): the
  * normalisation c_n = max|T'|, the truncation error (discarded eigenvalue
  * weight over total weight of E) and the relative gap at the cut
- * (lam[D'-1] - lam[D']) / lam[0] (+inf when nothing is cut).  n = 0 gives
- * c_0 and zeros.  Any output pointer may be NULL.  Errors: EINVAL, latched. */
+ * (lam[D'-1] - lam[D']) / lam[0] (+inf when nothing is cut).  When E is
+ * diagonalised in full (n <= 96) these are its eigenvalues; above that the
+ * subspace iteration tests only the D' kept Ritz pairs for convergence, so
+ * lam[D'] there is the next Ritz value of the block, which is not tested
+ * and lies at or below the eigenvalue it approximates, so that gap is an
+ * estimate from above; the discarded weight is the trace of E minus the
+ * kept Ritz values.  n = 0 gives c_0 and
+ * zeros.  Any output pointer may be NULL.  Errors: EINVAL, latched. */
 int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err,
                     double* cut_gap);
 

@@ -147,13 +147,16 @@ def test_random_nonsymmetric_tensor_stepwise(gpu_lib, seed):
     T = T0 / np.max(np.abs(T0))
     for n in range(1, nsteps + 1):
         st = oracle.coarse_grain_step(T, D)
+        # the kept subspace is unique at every step of these inputs (the
+        # oracle's relative gap at the cut is 2.7e-3 or more), so the next
+        # tensor is compared element by element
+        assert st.trunc.cut_gap > 1e-6, (n, st.trunc.cut_gap)
         s.coarse_grain(1)
         G = s.tensor()
         assert G.shape == st.T_next.shape
         c, _, gap = s.step_info(n)
         assert rel(c, st.c) <= TOL_F
-        if st.trunc.cut_gap > 1e-6:
-            np.testing.assert_allclose(G, st.T_next, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(G, st.T_next, rtol=0, atol=1e-11)
         T = G  # continue from the GPU tensor so each step is checked on its own input
 
 
@@ -210,24 +213,6 @@ def test_potts_split_doublet_is_ambiguous_but_close(gpu_lib):
     assert min(g for g in ref.cut_gap if np.isfinite(g)) < 1e-12
     s = gpu_solve(gpu_lib, 16, model="potts", q=3, temperature=T, dmax=16)
     assert rel(s.log_z(), ref.lnz_per_site) <= 1e-9
-
-
-def test_d48_full_size_one_step_against_oracle(gpu_lib):
-    """At the benchmark size (D = 48, steady state) the oracle computes one
-    step from the GPU's own input tensor; the GPU's next tensor and c_n match."""
-    from paper_2602_05900_amd import binding
-    T = 2.25
-    s = binding.Solve(model="ising", q=2, temperature=T, dmax=48, max_steps=8)
-    s.coarse_grain(7)        # dims reach (48, 48) at step 7
-    Tin = s.tensor()
-    assert Tin.shape == (48, 48, 48, 48)
-    st = oracle.coarse_grain_step(Tin, 48)
-    s.coarse_grain(1)
-    c, _, gap = s.step_info(8)
-    assert rel(c, st.c) <= TOL_F
-    G = s.tensor()
-    if st.trunc.cut_gap > 1e-6:
-        np.testing.assert_allclose(G, st.T_next, rtol=0, atol=1e-10)
 
 
 @pytest.mark.parametrize("T", [2.0, 2.269185314213022, 2.5])

@@ -39,26 +39,6 @@ def test_potts_solve_error_within_claim(gpu_lib, precision):
     assert rel(s.log_z(), ref) <= CLAIM[precision]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("bf16x6", 2e-5), ("bf16x3", 5e-4)])
-def test_d48_full_size_step_reduced_precision(gpu_lib, precision, tol):
-    """The D = 48 steady-state step in each precision from the same FP64 input
-    tensor as the oracle: the next tensor agrees elementwise to the precision's
-    level (relative to its largest entry, which is 1)."""
-    from paper_2602_05900_amd import binding
-    T = 2.25
-    f = binding.Solve(model="ising", q=2, temperature=T, dmax=48, max_steps=8)
-    f.coarse_grain(7)
-    Tin = f.tensor()
-    st = oracle.coarse_grain_step(Tin, 48)
-    s = binding.Solve(model="custom", tensor=Tin, dmax=48, temperature=1.0, precision=precision, max_steps=1)
-    s.coarse_grain(1)
-    c, _, _ = s.step_info(1)
-    assert rel(c, st.c) <= tol
-    if st.trunc.cut_gap > 1e-6:
-        G = s.tensor()
-        assert np.max(np.abs(G - st.T_next)) <= tol
-
-
 def test_c5_d64_bf16x6_against_fp64_and_onsager(gpu_lib):
     """Ising at Tc, D = 64, 40 steps (n = 4096 environments): BF16x6 within
     its claim of the FP64 path on the same GPU; both near Onsager's exact
