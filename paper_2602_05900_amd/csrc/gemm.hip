@@ -42,10 +42,13 @@ constexpr int kDmaWM = 4, kDmaWN = 2;
 // narrow outputs (T', N = D'): three stages (two measured slower for T':
 // 12.1 -> 16.1 ms per D = 48 solve), one workgroup per CU
 constexpr int kNarrowNst = 3, kNarrowMinw = 1;
-// T' reading Y in FP32 (split on load): register-staged 64 x 64 tiles, two
-// waves, one prefetch stage (per D = 48 solve: 13.1 ms, against 13.5 with two
-// stages, 16-17 ms with 128 or 256 rows, 17-20 ms with one wave)
-constexpr int kTpBM = 64, kTpWM = 2, kTpPF = 1;
+// T' reading Y in FP32 (split on load): register-staged 128 x 64 tiles,
+// four waves, one prefetch stage and one LDS tile (two barriers per K step)
+// so that five workgroups fit a CU: the product is bound by the latency of
+// its A loads, and more workgroups keep more of them in flight (per D = 48
+// solve: 10.4 ms, against 14.4 with two LDS tiles of 64 rows, 11.0 with one
+// of 64 rows, 17.4 with one of 32)
+constexpr int kTpBM = 128, kTpWM = 4, kTpPF = 1, kTpNbuf = 1;
 // mid-size products (half environments, E): two stages, up to three
 // workgroups per CU (env 19.2 -> 18.3 ms per D = 48 solve)
 constexpr int kMidNst = 2, kMidMinw = 2;
@@ -297,7 +300,7 @@ template <> struct SplitProducts<6> {
 // its rows are fetched as FP32 and split into the BF16 planes (hi, mid, lo
 // by round-to-nearest-even, the split the producers' epilogues use) as the
 // tile is written to LDS, so each element is split once.
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE, bool AF32 = false>
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE, bool AF32 = false, int NBUF = 2>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N)
 void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane,
                             const __bf16* __restrict__ B, long ldb, long b_plane,
@@ -320,8 +323,11 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     constexpr int B_CH = (BN * CPR + NT - 1) / NT;
     static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be whole 32x32 fragments");
 
-    __shared__ __attribute__((aligned(16))) __bf16 As[2][NPL][BM * LDK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NPL][BN * LDK];
+    // NBUF = 1: one LDS tile (two barriers per K step), so that twice as many
+    // workgroups, and twice as many loads, fit a CU
+    static_assert(NBUF == 2 || (NBUF == 1 && PF == 1), "one LDS buffer only with one prefetch stage");
+    __shared__ __attribute__((aligned(16))) __bf16 As[NBUF][NPL][BM * LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[NBUF][NPL][BN * LDK];
 
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * per_xcd + (bid >> 3);
@@ -488,7 +494,16 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     const int nk = (K + BK - 1) / BK;
     load_tile(0, S0{});
     store_tile(0, S0{});
-    if constexpr (PF == 1) {
+    if constexpr (NBUF == 1) {
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk) load_tile((kt + 1) * BK, S0{});
+            compute(0);
+            __syncthreads();
+            if (kt + 1 < nk) store_tile(0, S0{});
+            __syncthreads();
+        }
+    } else if constexpr (PF == 1) {
         __syncthreads();
         for (int kt = 0; kt < nk; ++kt) {
             const int buf = kt & 1;
@@ -587,7 +602,7 @@ void gemm_nt_bf16p32_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     }
 }
 
-template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE, bool AF32 = false>
+template <int NPROD, int BM, int BN, int WAVES_M, int WAVES_N, int PF, int ROLE, bool AF32 = false, int NBUF = 2>
 static hipError_t run_gemm_p32(const Buf& A, long lda, const Buf& B, long ldb, int M, int N, int K,
                                const Store& st, const OutMap& mp, hipStream_t stream)
 {
@@ -599,7 +614,7 @@ static hipError_t run_gemm_p32(const Buf& A, long lda, const Buf& B, long ldb, i
     if (grid > 0x7fffffffL) return hipErrorInvalidValue;
     const bool vec = (AF32 ? lda % 4 == 0 : lda % 8 == 0 && (long)A.plane % 8 == 0) && ldb % 8 == 0 &&
                      (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 && ((uintptr_t)B.ptr & 15) == 0;
-    hipLaunchKernelGGL((gemm_nt_bf16p32_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, PF, ROLE, AF32>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((gemm_nt_bf16p32_kernel<NPROD, BM, BN, WAVES_M, WAVES_N, PF, ROLE, AF32, NBUF>), dim3((unsigned)grid),
                        dim3(64 * WAVES_M * WAVES_N), 0, stream, static_cast<const __bf16*>(A.ptr), lda, (long)A.plane,
                        static_cast<const __bf16*>(B.ptr), ldb, (long)B.plane, M, N, K, st, mp, tiles_m, tiles_n,
                        per_xcd, vec ? 1 : 0);
@@ -1161,10 +1176,10 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
         // into the planes of B's format as it is written to LDS
         if (A.panel_k || B.panel_k) return hipErrorInvalidValue;
         return B.fmt == Fmt::BF16x2
-                   ? run_gemm_p32<3, kTpBM, 64, kTpWM, 1, kTpPF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
-                                                                                     stream)
-                   : run_gemm_p32<6, kTpBM, 64, kTpWM, 1, kTpPF, ROLE, true>(A, lda, B, ldb, M, N, K, st, map,
-                                                                                     stream);
+                   ? run_gemm_p32<3, kTpBM, 64, kTpWM, 1, kTpPF, ROLE, true, kTpNbuf>(A, lda, B, ldb, M, N, K, st,
+                                                                                              map, stream)
+                   : run_gemm_p32<6, kTpBM, 64, kTpWM, 1, kTpPF, ROLE, true, kTpNbuf>(A, lda, B, ldb, M, N, K, st,
+                                                                                              map, stream);
     }
     if (A.panel_k || B.panel_k) {
         // panel-layout operands (row length lda / ldb >= K, whole 32-row
