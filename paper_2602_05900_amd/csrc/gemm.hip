@@ -643,12 +643,16 @@ __device__ __forceinline__ int lds_swz(int r) { return ((r >> 2) ^ (r >> 3)) & 1
 // 16 zero bytes: the source of every lane's load in a padding K step
 __device__ __attribute__((aligned(16))) const unsigned int kZeroChunk[4] = {0u, 0u, 0u, 0u};
 
-template <int N>
-__device__ __forceinline__ void wait_vmem_le() {
-    static_assert(N >= 0 && N < 16, "vmcnt immediate");
-    // gfx9 s_waitcnt: vmcnt[3:0] = N, expcnt[6:4] = 7 (no wait), lgkmcnt[11:8] = 0
-    __builtin_amdgcn_s_waitcnt(N | (7 << 4));
+// gfx9 s_waitcnt: vmcnt[3:0] and [15:14] (six bits), expcnt[6:4], lgkmcnt[11:8]
+template <int VM, int LG>
+__device__ __forceinline__ void wait_vmem_lds_le() {
+    static_assert(VM >= 0 && VM < 64 && LG >= 0 && LG < 16, "vmcnt / lgkmcnt immediates");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4) | (LG << 8));
 }
+
+// at most N vector-memory operations of this wave in flight, and no LDS ones
+template <int N>
+__device__ __forceinline__ void wait_vmem_le() { wait_vmem_lds_le<N, 0>(); }
 
 __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
@@ -702,6 +706,8 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
     __shared__ __attribute__((aligned(1024))) __bf16 S0[STAGE];
     __shared__ __attribute__((aligned(1024))) __bf16 S1[STAGE];
     __shared__ __attribute__((aligned(1024))) __bf16 S2[NST == 3 ? STAGE : 8];
+    // the stage arrays double as per-wave staging regions of the epilogues
+    auto stage_at = [&](int i) -> __bf16* { return i == 0 ? S0 : (i == 1 ? S1 : S2); };
 
     const int bid = blockIdx.x;
     const int tile = (bid & 7) * per_xcd + (bid >> 3);
@@ -764,13 +770,17 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         }
         dsto[j] = (isA ? pl * A_EL : NPL * A_EL + pl * B_EL) + rb * 32 * BK;
     }
-    // padding K steps (past K) load zeros: every lane reads the same 16 bytes
-    const __bf16* zsrc = reinterpret_cast<const __bf16*>(kZeroChunk);
+    // padding K steps (past K) load zeros: every lane reads the same 16 bytes.
+    // The address is chosen by a select, not a branch: control flow around
+    // the LDS-DMA loads makes the compiler's wait insertion fall back to
+    // waiting for every load in flight before the next LDS read.
+    const uintptr_t zsrc = reinterpret_cast<uintptr_t>(kZeroChunk);
     auto issue = [&](__bf16* S, int k0) {
         const bool pad = k0 >= K;
 #pragma unroll
         for (int j = 0; j < LPW; ++j) {
-            const __bf16* g = pad ? zsrc : gsrc[j] + (long)kmul[j] * k0;
+            const uintptr_t a = reinterpret_cast<uintptr_t>(gsrc[j] + (long)kmul[j] * k0);
+            const __bf16* g = reinterpret_cast<const __bf16*>(pad ? zsrc : a);
             __builtin_amdgcn_global_load_lds(g, (lds_void*)(S + dsto[j]), 16, 0, 0);
         }
     };
@@ -852,7 +862,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             constexpr int CPL = NCH / 64;          // chunks per lane
             __syncthreads();   // every wave is done reading the stages
             const int ar = wave / PER_ARRAY;
-            __bf16* reg = (ar == 0 ? S0 : (ar == 1 ? S1 : S2)) + (wave - ar * PER_ARRAY) * REG;
+            __bf16* reg = stage_at(ar) + (wave - ar * PER_ARRAY) * REG;
             __bf16* outp = static_cast<__bf16*>(store.ptr);
             const long pstride = (long)store.plane;
             // this lane's chunks: staged row and column, output column part
@@ -921,7 +931,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             constexpr int CPL = NCH / 64;
             __syncthreads();   // every wave is done reading the stages
             const int ar = wave / PER_ARRAY3;
-            _Float16* reg = reinterpret_cast<_Float16*>(ar == 0 ? S0 : (ar == 1 ? S1 : S2)) +
+            _Float16* reg = reinterpret_cast<_Float16*>(stage_at(ar)) +
                             (wave - ar * PER_ARRAY3) * REG3;
             _Float16* outp = static_cast<_Float16*>(store.ptr);
             const long pstride = (long)store.plane;
@@ -984,7 +994,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
             constexpr int CPL = NCH / 64;
             __syncthreads();   // every wave is done reading the stages
             const int ar = wave / PER_ARRAY4;
-            float* reg = reinterpret_cast<float*>(ar == 0 ? S0 : (ar == 1 ? S1 : S2)) + (wave - ar * PER_ARRAY4) * SLAB4;
+            float* reg = reinterpret_cast<float*>(stage_at(ar)) + (wave - ar * PER_ARRAY4) * SLAB4;
             float* outp = static_cast<float*>(store.ptr);
             MapPart ccol[CPL];
             bool cok[CPL];
@@ -1034,7 +1044,7 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         constexpr int CPLG = (WN + 63) / 64;
         __syncthreads();   // every wave is done reading the stages
         const int ar = wave / PER_ARRAY4;
-        float* reg = reinterpret_cast<float*>(ar == 0 ? S0 : (ar == 1 ? S1 : S2)) + (wave - ar * PER_ARRAY4) * SLAB4;
+        float* reg = reinterpret_cast<float*>(stage_at(ar)) + (wave - ar * PER_ARRAY4) * SLAB4;
         MapPart gcol[CPLG];
         bool gok[CPLG];
 #pragma unroll
