@@ -13,9 +13,10 @@ one HIP stream and workspace each) through the continuous-batching server.
 value = algorithmic contraction FLOPs of the timed solves (O(D^7) order,
 eigensolve excluded from the count but not from the time) / wall time of
 the timed region, in the headline precision (default FP16X3: the D^7
-product Y with its operands split into two FP16 terms of the value times a
-fixed power of two, 3 products, the other products split into three BF16
-terms, 6 products, all with FP32 accumulation; eigensolve, normalisation
+product Y and the environment products with their operands split into two
+FP16 terms of the value times a fixed power of two, 3 products, the X and
+T' products split into three BF16 terms, 6 products, all with FP32
+accumulation; eigensolve, normalisation
 and ln Z in FP64).  Also reported: the same batch in BF16x6 and in FP64, per-solve service time
 p50/p99, per-stage GPU times from HIP events, |delta f| against the FP64
 oracle's stored values for these temperatures, the roofline of the dominant
@@ -56,7 +57,7 @@ Y_OUT_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4, "fp16x3": 4}
 # MFMA products per algorithmic product in Y
 PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-split/f32acc", "bf16x6": "bf16x6-split/f32acc",
-         "fp16x3": "fp16x3-split/f32acc (Y), bf16x6-split/f32acc (other products)"}
+         "fp16x3": "fp16x3-split/f32acc (Y, environments), bf16x6-split/f32acc (X, T')"}
 
 
 def measured_traffic(precision: str, dmax: int, nsteps: int):

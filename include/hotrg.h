@@ -91,11 +91,13 @@ extern "C" {
 #define HOTRG_BF16X3  2  /* operands split in 2 BF16 terms, 3 products, FP32 acc */
 #define HOTRG_BF16X6  3  /* operands split in 3 BF16 terms, 6 products, FP32 acc */
 #define HOTRG_FP16X3  4  /* as HOTRG_BF16X6, except the D^7 product at full size
-                            (Y = X . T, Sec. II.B): its operands split in 2 FP16
-                            terms of the value times a fixed power of two
-                            (2^11 for X, 2^14 for T, both bounded because
-                            max|T| = 1 and U is an isometry, so that neither
-                            term falls into FP16's subnormal range), 3
+                            (Y = X . T, Sec. II.B) and the environment
+                            products in the panel layout: their operands
+                            split in 2 FP16 terms of the value times a fixed
+                            power of two (2^11 for X, 2^14 for T, s_H with
+                            s_H Dx Dy <= 2^15 for the half environments, all
+                            bounded because max|T| = 1 and U is an isometry,
+                            so that the terms stay in FP16's range), 3
                             products, FP32 accumulation; no observables     */
 
 #define HOTRG_MAX_STEPS 60  /* total steps per handle (2^60 sites)            */
@@ -392,8 +394,9 @@ int hotrg_gemm_nt(int precision, int M, int N, int K,
  *   panel  1: both converted operands are stored in the 32 x 16 panel layout
  *          a solve's producers write for the environment and Y products
  *          (split precisions only; M and N multiples of 32, K of 16)
- * HOTRG_FP16X3 runs only as the full-size Y product (role HOTRG_ROLE_Y,
- * panel 1, at least 512 tiles of 256 x 256); each operand is converted as
+ * HOTRG_FP16X3 runs as the full-size Y product (role HOTRG_ROLE_Y, panel 1,
+ * at least 512 tiles of 256 x 256) and as the environment product (role
+ * HOTRG_ROLE_GENERIC, panel 1, N > 64); each operand is converted as
  * 2^11 times its value into two FP16 planes, so |A| and |B| must stay below
  * 31 (larger entries overflow FP16 and give non-finite results).
  * The output is FP64 through the map, as for hotrg_gemm_nt (a solve's Y

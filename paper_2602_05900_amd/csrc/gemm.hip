@@ -918,8 +918,8 @@ void gemm_nt_bf16dma_kernel(const __bf16* __restrict__ A, long lda, long a_plane
         }
     }
     // FP16-plane outputs (F16x2: hi, lo of alpha * acc, the scale being part
-    // of alpha), from BF16 operands: the same 16-row slab staging as above
-    // with two 2-byte planes.
+    // of alpha), from BF16 or FP16 operands: the same 16-row slab staging as
+    // above with two 2-byte planes.
     constexpr int REG3 = 2 * SLAB;
     constexpr int PER_ARRAY3 = STAGE / REG3;
     if constexpr (PER_ARRAY3 > 0 && NW <= PER_ARRAY3 * NST) {
@@ -1122,11 +1122,12 @@ static hipError_t run_gemm_dma(const Buf& A, long lda, const Buf& B, long ldb, i
     if (!vec_out && st.fmt == (int)Fmt::F32 && mp.panel_k == 0 && mp.cs_lo == 1 && mp.rs_hi % 4 == 0 &&
         mp.rs_lo % 4 == 0 && mp.cs_hi % 4 == 0 && mp.sn % 4 == 0 && N % 4 == 0 && ((uintptr_t)st.ptr & 15) == 0)
         vec_out = 2;
-    // FP16 planes from BF16 operands (the X product feeding an FP16 Y)
-    if (!vec_out && !F16 && st.fmt == (int)Fmt::F16x2 && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 &&
+    if (F16 && vec_out == 1) vec_out = 0;   // the BF16-plane staging does not apply to FP16 operands
+    // FP16-plane outputs (the X product feeding an FP16 Y, the half
+    // environments feeding an FP16 E)
+    if (!vec_out && st.fmt == (int)Fmt::F16x2 && (rm_ok || pn_ok) && mp.sn % 8 == 0 && N % 8 == 0 &&
         st.plane % 8 == 0 && ((uintptr_t)st.ptr & 15) == 0)
         vec_out = 3;
-    if (F16 && vec_out == 1) vec_out = 0;   // the BF16-plane staging does not apply to FP16 operands
     const int tiles_m = (M + BM - 1) / BM;
     const int tiles_n = (N + BN - 1) / BN;
     const long tiles = (long)tiles_m * tiles_n;
@@ -1165,15 +1166,20 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
 {
     (void)products;
     if (A.fmt == Fmt::F16x2 || B.fmt == Fmt::F16x2) {
-        // FP16 two-plane operands: the Y product at full size only (panel
-        // operands, 256 x 256 tiles), hi*hi + hi*lo + lo*hi
-        if constexpr (ROLE == 2) {
-            const bool ok = A.fmt == Fmt::F16x2 && B.fmt == Fmt::F16x2 && A.panel_k && B.panel_k && K >= 16 &&
-                            K % 16 == 0 && A.panel_k == lda && B.panel_k == ldb && K <= lda && K <= ldb &&
-                            lda % 16 == 0 && ldb % 16 == 0 && M % 32 == 0 && N % 32 == 0 && N > 64 &&
-                            (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 &&
-                            ((uintptr_t)B.ptr & 15) == 0 && (long)((M + 255) / 256) * ((N + 255) / 256) >= 512;
-            if (!ok) return hipErrorInvalidValue;
+        // FP16 two-plane operands, hi*hi + hi*lo + lo*hi: the Y product at
+        // full size (panel operands, 256 x 256 tiles) and the environment
+        // products (panel operands, mid-size tiles)
+        const bool f16_panels = A.fmt == Fmt::F16x2 && B.fmt == Fmt::F16x2 && A.panel_k && B.panel_k && K >= 16 &&
+                                K % 16 == 0 && A.panel_k == lda && B.panel_k == ldb && K <= lda && K <= ldb &&
+                                lda % 16 == 0 && ldb % 16 == 0 && M % 32 == 0 && N % 32 == 0 && N > 64 &&
+                                (long)A.plane % 8 == 0 && (long)B.plane % 8 == 0 && ((uintptr_t)A.ptr & 15) == 0 &&
+                                ((uintptr_t)B.ptr & 15) == 0;
+        if constexpr (ROLE == 0) {
+            if (!f16_panels) return hipErrorInvalidValue;
+            return run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true, kMidNst, kMidMinw, true>(A, lda, B, ldb, M, N,
+                                                                                               K, st, map, stream);
+        } else if constexpr (ROLE == 2) {
+            if (!f16_panels || (long)((M + 255) / 256) * ((N + 255) / 256) < 512) return hipErrorInvalidValue;
             return run_gemm_dma<3, kYBM, kYBN, kYWM, kYWN, ROLE, true, true, kYNst,
                                 kYMinw, true>(A, lda, B, ldb, M, N, K, st, map, stream, (int)map.ngroup);
         } else {

@@ -84,6 +84,18 @@ int products_of(int prec) {
 constexpr float kF16ScaleT = 16384.f;   // 2^14
 constexpr float kF16ScaleX = 2048.f;    // 2^11
 
+// HOTRG_FP16X3, environment products: P1 and P2 (re-layouts of T, |.| <= 1)
+// are planes of 2^14 x T as for Y; a half environment sums Dx Dy products of
+// two such entries, so |Ah|, |Bh| <= Dx Dy, and they are stored as planes of
+// s_H x value with s_H the largest power of two for which s_H Dx Dy <= 2^15
+// (under 65504 after rounding); E's product undoes s_H^2.
+double f16_half_scale(long k) {
+    double sc = 1.0;
+    while (sc * 2.0 * (double)k <= 32768.0) sc *= 2.0;
+    while (sc * (double)k > 32768.0) sc *= 0.5;
+    return sc;
+}
+
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // bytes of a buffer of `count` elements in format f (planes 64-element aligned)
@@ -564,7 +576,20 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
     const bool split = f == Fmt::BF16x2 || f == Fmt::BF16x3;
     const long mxy = (long)Dx * Dy, mxx = (long)Dx * Dx, myy = (long)Dy * Dy;
     const bool panel_env = split && mxy % 32 == 0 && mxy > 64 && mxx % 32 == 0 && mxx > 64 && myy % 16 == 0;
-    Buf P1b = Pa, P2b = Pb, Ahb = Ah, Bhb = Bh;
+    // HOTRG_FP16X3: with the panel layout the three products take two scaled
+    // FP16 planes per operand (three split products instead of six), views of
+    // the same buffers
+    const bool f16env = s->p.precision == HOTRG_FP16X3 && panel_env && nimp == 0;
+    const double sH = f16env ? f16_half_scale(mxy) : 1.0;
+    Buf P1b = f16env ? make_buf(w, L.oPa, Fmt::F16x2, L.nP) : Pa;
+    Buf P2b = f16env ? make_buf(w, L.oPb, Fmt::F16x2, L.nP) : Pb;
+    Buf Aho = f16env ? make_buf(w, L.oAh, Fmt::F16x2, L.nAB) : Ah;
+    Buf Bho = f16env ? make_buf(w, L.oBh, Fmt::F16x2, L.nAB) : Bh;
+    if (f16env) {
+        P1b.scale = P2b.scale = kF16ScaleT;
+        Aho.scale = Bho.scale = (float)sH;
+    }
+    Buf Ahb = Aho, Bhb = Bho;
     if (panel_env) {
         P1b.panel_k = P2b.panel_k = mxy;
         Ahb.panel_k = Bhb.panel_k = myy;
@@ -583,10 +608,13 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
         HIP_TRY(s, launch_permute4(s->T(), dims, p1, P1b, s->stream));
         HIP_TRY(s, launch_permute4(s->T(), dims, p2, P2b, s->stream));
         if (Eout == E) record(s, step_index, 1);
-        if ((r = gemm(s, P1b, m, P1b, m, Ah, m, m, m, half))) return r;
-        if ((r = gemm(s, P2b, m, P2b, m, Bh, m, m, m, half))) return r;
+        const double a_half = f16env ? sH / ((double)kF16ScaleT * (double)kF16ScaleT) : 1.0;
+        if ((r = gemm(s, P1b, m, P1b, m, Aho, m, m, m, half, GemmRole::Generic, a_half))) return r;
+        if ((r = gemm(s, P2b, m, P2b, m, Bho, m, m, m, half, GemmRole::Generic, a_half))) return r;
         const Buf Eo{Eout, Fmt::F64, 0};
-        if ((r = gemm(s, Ahb, (long)Dy * Dy, Bhb, (long)Dy * Dy, Eo, nE, nE, Dy * Dy, env))) return r;
+        if ((r = gemm(s, Ahb, (long)Dy * Dy, Bhb, (long)Dy * Dy, Eo, nE, nE, Dy * Dy, env, GemmRole::Generic,
+                      f16env ? 1.0 / (sH * sH) : 1.0)))
+            return r;
         HIP_TRY(s, launch_symmetrize(Eout, nE, s->stream));
         return HOTRG_OK;
     };

@@ -82,3 +82,86 @@ def test_d32_against_oracle_golden(gpu_lib, precision):
         print(f"D=32 {precision} T={T:.4f} |df|/|f| = {e:.2e}")
         assert e <= CLAIM[precision]
         s.close()
+
+
+# ------------------------------------------------------------------ FP16 environment products
+
+@pytest.mark.parametrize("M,N,K", [(128, 96, 16), (288, 320, 272), (1024, 1024, 1024)])
+def test_gemm_nt_fp16x3_environment_role(gpu_lib, M, N, K):
+    """The environment products' FP16 form (generic role, panel operands):
+    C = 0.75 A B^T against NumPy.  Each operand is converted as 2^11 x value
+    into two FP16 terms (22 significant bits for |value| >= 2^-14, an absolute
+    floor of 2^-35 below), the lo*lo product is dropped, FP32 accumulation:
+    |err| <= (4 * 2^-22 + 8 sqrt(K) 2^-24) sum_k |a_k b_k| plus the floor.
+    M = 288 leaves a ragged row tile, K = 272 an odd number of K steps."""
+    import torch
+    from paper_2602_05900_amd import binding
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((N, K))
+    ref = (A @ B.T) * 0.75
+    absdot = (np.abs(A) @ np.abs(B).T) * 0.75
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.full((M * N,), float("nan"), dtype=torch.float64, device="cuda")
+    binding.gemm_nt(dA, dB, dC, M, N, K, K, K, (1, N, 0, 1, 1, 0), precision="fp16x3", role="generic", panel=True,
+                    alpha=0.75)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy().reshape(M, N)
+    assert np.all(np.isfinite(C))
+    floor = 2.0 ** -33 * K * np.max(np.abs(A)) * np.max(np.abs(B))
+    bound = (4 * 2.0 ** -22 + 8 * np.sqrt(K) * 2.0 ** -24) * absdot + floor
+    assert np.all(np.abs(C - ref) <= bound), float(np.max(np.abs(C - ref) / bound))
+
+
+def environment_error_bound(T, eps):
+    """Componentwise bound on the error of E computed by the split products,
+    E = sum_{k,k'} Ah[a1,k,b1,k'] Bh[a2,k,b2,k'] with Ah, Bh the half
+    environments (sums over K1 = Dx Dy products of entries of T):
+      |dAh| <= e1 |T||T| (the half environment of |T|), e1 = 3 eps (operand
+              splits and the split of Ah itself) + 8 sqrt(K1) 2^-24 (FP32
+              accumulation), and the same for Bh;
+      |dE|  <= |dAh| |Bh| + |Ah| |dBh| + e2 |Ah| |Bh|, e2 = 2 eps +
+              8 sqrt(K2) 2^-24 over K2 = Dy^2;
+    eps the relative error of one split operand term (2^-22 for two FP16
+    terms, 2^-24 for three BF16 terms); symmetrised as E is."""
+    Dx, Dy = T.shape[0], T.shape[2]
+    aA, aB = oracle.half_environments(np.abs(T))
+    e1 = 3 * eps + 8 * np.sqrt(Dx * Dy) * 2.0 ** -24
+    e2 = 2 * eps + 8 * np.sqrt(Dy * Dy) * 2.0 ** -24
+    b4 = (2 * e1 + e2) * np.einsum("ikjl,mknl->imjn", aA, aB, optimize=True)
+    b = b4.reshape(Dx * Dx, Dx * Dx)
+    return 0.5 * (b + b.T)
+
+
+@pytest.fixture(scope="module")
+def d32_tensor():
+    """A D = 32 fixed-point-regime tensor (FP64 solve, 8 steps at Tc) and
+    the oracle's environment of it."""
+    from paper_2602_05900_amd import binding
+    s = binding.Solve(model="ising", q=2, temperature=exact.ISING_TC, dmax=32, max_steps=8)
+    s.coarse_grain(8)
+    Tin = s.tensor()
+    s.close()
+    assert Tin.shape == (32, 32, 32, 32)
+    return Tin, oracle.environment(Tin)
+
+
+@pytest.mark.parametrize("precision,eps", [("fp16x3", 2.0 ** -22), ("bf16x6", 2.0 ** -24)])
+def test_split_environment_within_error_bound(gpu_lib, d32_tensor, precision, eps):
+    """One step from the same D = 32 tensor: the environment E the split
+    products build (FP16 terms for fp16x3, whose environment products take
+    the panel layout at these dims; BF16 terms for bf16x6) against the
+    oracle's FP64 E, within the componentwise bound above plus 2^-26 of
+    max|E| (entries far below the largest meet FP16's absolute floor)."""
+    from paper_2602_05900_amd import binding
+    Tin, E_ref = d32_tensor
+    s = binding.Solve(model="custom", tensor=Tin, dmax=32, temperature=1.0, precision=precision, max_steps=1)
+    s.coarse_grain(1)
+    E = s.environment()
+    s.close()
+    assert E.shape == E_ref.shape
+    bound = environment_error_bound(Tin, eps) + 2.0 ** -26 * np.max(np.abs(E_ref))
+    err = np.abs(E - E_ref)
+    print(f"{precision}: max |dE| / max |E| = {np.max(err) / np.max(np.abs(E_ref)):.2e}, "
+          f"max |dE| / bound = {np.max(err / bound):.3f}")
+    assert np.all(err <= bound), float(np.max(err / bound))
