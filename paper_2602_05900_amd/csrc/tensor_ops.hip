@@ -10,13 +10,9 @@ namespace hotrg {
 
 // ---------------------------------------------------------------- stores
 
-__device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
-    if (o.cols) {
-        const long r = (long)(idx / o.cols), c = (long)(idx % o.cols);
-        idx = o.panel_k ? (size_t)panel_index(r, c, o.panel_k) : (size_t)(r * o.ld + c);
-    } else if (o.panel_k) {
-        idx = (size_t)panel_index((long)(idx / o.panel_k), (long)(idx % o.panel_k), o.panel_k);
-    }
+// store v as element `idx` of the storage of o (after any sub-block or
+// panel mapping), in o's format
+__device__ __forceinline__ void put_at(const Buf& o, size_t idx, double v) {
     switch (o.fmt) {
         case Fmt::F64: static_cast<double*>(o.ptr)[idx] = v; break;
         case Fmt::F32: static_cast<float*>(o.ptr)[idx] = (float)v; break;
@@ -38,6 +34,30 @@ __device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
     }
 }
 
+__device__ __forceinline__ void put(const Buf& o, size_t idx, double v) {
+    if (o.cols) {
+        const long r = (long)(idx / o.cols), c = (long)(idx % o.cols);
+        idx = o.panel_k ? (size_t)panel_index(r, c, o.panel_k) : (size_t)(r * o.ld + c);
+    } else if (o.panel_k) {
+        idx = (size_t)panel_index((long)(idx / o.panel_k), (long)(idx % o.panel_k), o.panel_k);
+    }
+    put_at(o, idx, v);
+}
+
+// the storage index of logical element idx of o, for idx < 2^32 (32-bit
+// divisions; the 64-bit ones of put() cost more than the element's store)
+__device__ __forceinline__ size_t storage_index32(const Buf& o, unsigned idx) {
+    if (o.cols) {
+        const unsigned w = (unsigned)o.cols, r = idx / w, c = idx - r * w;
+        return o.panel_k ? (size_t)panel_index(r, c, o.panel_k) : (size_t)r * (size_t)o.ld + c;
+    }
+    if (o.panel_k) {
+        const unsigned w = (unsigned)o.panel_k, r = idx / w, c = idx - r * w;
+        return (size_t)panel_index(r, c, o.panel_k);
+    }
+    return idx;
+}
+
 // ---------------------------------------------------------------- permute
 
 struct Perm4 {
@@ -45,18 +65,20 @@ struct Perm4 {
     long is[4];    // input stride of the input axis feeding each output axis
 };
 
-__global__ void permute4_kernel(const double* __restrict__ in, Perm4 p, Buf out, size_t total) {
-    size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; o < total; o += stride) {
-        size_t t = o;
-        const int j3 = (int)(t % p.od[3]); t /= p.od[3];
-        const int j2 = (int)(t % p.od[2]); t /= p.od[2];
-        const int j1 = (int)(t % p.od[1]); t /= p.od[1];
-        const int j0 = (int)t;
-        const long src = j0 * p.is[0] + j1 * p.is[1] + j2 * p.is[2] + j3 * p.is[3];
-        put(out, o, in[src]);
-    }
+// out[j0, j1, j2, j3] = in[j0 is0 + j1 is1 + j2 is2 + j3 is3]: one thread per
+// element, blockIdx.y = (j0, j1), the threads of a row of blocks over
+// (j2, j3); every index fits 32 bits (the host checks the element count)
+__global__ __launch_bounds__(256) void permute4_kernel(const double* __restrict__ in, Perm4 p, Buf out) {
+    const unsigned inner = (unsigned)p.od[2] * (unsigned)p.od[3];
+    const unsigned t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= inner) return;
+    const unsigned y = blockIdx.y;
+    const unsigned j0 = y / (unsigned)p.od[1], j1 = y - j0 * (unsigned)p.od[1];
+    const unsigned j2 = t / (unsigned)p.od[3], j3 = t - j2 * (unsigned)p.od[3];
+    const unsigned src = j0 * (unsigned)p.is[0] + j1 * (unsigned)p.is[1] + j2 * (unsigned)p.is[2] +
+                         j3 * (unsigned)p.is[3];
+    const unsigned o = y * inner + t;
+    put_at(out, storage_index32(out, o), in[src]);
 }
 
 hipError_t launch_permute4(const double* in, const int dims[4], const int perm[4],
@@ -74,10 +96,10 @@ hipError_t launch_permute4(const double* in, const int dims[4], const int perm[4
         total *= (size_t)p.od[a];
     }
     if (total == 0) return hipSuccess;
-    const int threads = 256;
-    size_t blocks = (total + threads - 1) / threads;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(permute4_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, in, p, out, total);
+    const size_t rows = (size_t)p.od[0] * p.od[1], inner = (size_t)p.od[2] * p.od[3];
+    if (total >= (1ull << 32) || rows > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(permute4_kernel, dim3((unsigned)((inner + 255) / 256), (unsigned)rows), dim3(256), 0, stream,
+                       in, p, out);
     return hipGetLastError();
 }
 
