@@ -146,16 +146,33 @@ def d32_tensor():
     return Tin, oracle.environment(Tin)
 
 
-@pytest.mark.parametrize("precision,eps", [("fp16x3", 2.0 ** -22), ("bf16x6", 2.0 ** -24)])
-def test_split_environment_within_error_bound(gpu_lib, d32_tensor, precision, eps):
-    """One step from the same D = 32 tensor: the environment E the split
-    products build (FP16 terms for fp16x3, whose environment products take
-    the panel layout at these dims; BF16 terms for bf16x6) against the
-    oracle's FP64 E, within the componentwise bound above plus 2^-26 of
-    max|E| (entries far below the largest meet FP16's absolute floor)."""
+@pytest.fixture(scope="module")
+def d36_step5_tensor():
+    """The tensor entering step 6 of a D = 36 FP64 solve at Tc: dims (Dx, Dy)
+    = (16, 36), where the environment products take the panel layout but
+    Dy is not a multiple of 8, so the half environments leave the product
+    kernel through its element-store path rather than 16-byte stores."""
     from paper_2602_05900_amd import binding
-    Tin, E_ref = d32_tensor
-    s = binding.Solve(model="custom", tensor=Tin, dmax=32, temperature=1.0, precision=precision, max_steps=1)
+    s = binding.Solve(model="ising", q=2, temperature=exact.ISING_TC, dmax=36, max_steps=5)
+    s.coarse_grain(5)
+    Tin = s.tensor()
+    s.close()
+    assert Tin.shape == (16, 16, 36, 36)
+    return Tin, oracle.environment(Tin)
+
+
+@pytest.mark.parametrize("tensor", ["d32_tensor", "d36_step5_tensor"])
+@pytest.mark.parametrize("precision,eps", [("fp16x3", 2.0 ** -22), ("bf16x6", 2.0 ** -24)])
+def test_split_environment_within_error_bound(gpu_lib, request, tensor, precision, eps):
+    """One step from the same tensor: the environment E the split products
+    build (FP16 terms for fp16x3, whose environment products take the panel
+    layout at these dims; BF16 terms for bf16x6) against the oracle's FP64
+    E, within the componentwise bound above plus 2^-26 of max|E| (entries
+    far below the largest meet FP16's absolute floor)."""
+    from paper_2602_05900_amd import binding
+    Tin, E_ref = request.getfixturevalue(tensor)
+    s = binding.Solve(model="custom", tensor=Tin, dmax=Tin.shape[2], temperature=1.0, precision=precision,
+                      max_steps=1)
     s.coarse_grain(1)
     E = s.environment()
     s.close()
@@ -165,3 +182,20 @@ def test_split_environment_within_error_bound(gpu_lib, d32_tensor, precision, ep
     print(f"{precision}: max |dE| / max |E| = {np.max(err) / np.max(np.abs(E_ref)):.2e}, "
           f"max |dE| / bound = {np.max(err / bound):.3f}")
     assert np.all(err <= bound), float(np.max(err / bound))
+
+
+def test_fp16x3_d36_solve_within_claim(gpu_lib):
+    """FP16X3 at D = 36 (10 steps at Tc): step 6 has dims (16, 36), where the
+    environment products run in FP16 terms with element stores (Dy not a
+    multiple of 8), and the later (36, 36) steps keep BF16 planes for the
+    environment (Dx^2 not a multiple of 32); ln Z against the oracle within
+    the mode's claim."""
+    from paper_2602_05900_amd import binding
+    T = exact.ISING_TC
+    ref = oracle.solve("ising", 2, T, 36, 10, keep_tensor=False).lnz_per_site
+    s = binding.Solve(model="ising", q=2, temperature=T, dmax=36, precision="fp16x3", max_steps=10)
+    s.coarse_grain(10)
+    err = rel(s.log_z(), ref)
+    s.close()
+    print(f"fp16x3 D=36 |d lnZ|/|lnZ| = {err:.2e}")
+    assert err <= CLAIM["fp16x3"]
