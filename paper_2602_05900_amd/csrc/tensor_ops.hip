@@ -81,6 +81,44 @@ __global__ __launch_bounds__(256) void permute4_kernel(const double* __restrict_
     put_at(out, storage_index32(out, o), in[src]);
 }
 
+// The same re-layout when the output's fastest axis is not the input's
+// (perm[3] != 3): a 32 x 32 tile of (input axis 3, input axis perm[3]) goes
+// through LDS, read along the input's contiguous axis and written along the
+// output's fastest one.  Output axis `a` is fed by input axis 3; `o1`, `o2`
+// are the other two output axes (blockIdx.y = (j_o1, j_o2)); blockIdx.x
+// enumerates the tiles over (output axis a, output axis 3).
+struct PermT {
+    int od[4];       // output dims
+    unsigned is[4];  // input stride of the input axis feeding each output axis
+    unsigned os[4];  // output (logical, row-major) stride of each output axis
+    int a, o1, o2;   // output axis fed by input axis 3; the two outer output axes
+};
+
+__global__ __launch_bounds__(256) void permute4_tiled_kernel(const double* __restrict__ in, PermT p, Buf out) {
+    __shared__ double tile[32][33];
+    const unsigned na = (unsigned)p.od[p.a], n3 = (unsigned)p.od[3];
+    const unsigned ta = blockIdx.x % ((na + 31) / 32), t3 = blockIdx.x / ((na + 31) / 32);
+    const unsigned y = blockIdx.y;
+    const unsigned j1 = y / (unsigned)p.od[p.o2], j2 = y - j1 * (unsigned)p.od[p.o2];
+    const unsigned base_in = j1 * p.is[p.o1] + j2 * p.is[p.o2];
+    const unsigned base_out = j1 * p.os[p.o1] + j2 * p.os[p.o2];
+    const unsigned lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
+    // read: lanes along output axis a (the input's contiguous axis)
+    for (unsigned r = ly; r < 32; r += 8) {
+        const unsigned ia = ta * 32 + lx, i3 = t3 * 32 + r;
+        if (ia < na && i3 < n3) tile[r][lx] = in[base_in + ia * p.is[p.a] + i3 * p.is[3]];
+    }
+    __syncthreads();
+    // write: lanes along output axis 3
+    for (unsigned r = ly; r < 32; r += 8) {
+        const unsigned ia = ta * 32 + r, i3 = t3 * 32 + lx;
+        if (ia < na && i3 < n3) {
+            const unsigned o = base_out + ia * p.os[p.a] + i3;
+            put_at(out, storage_index32(out, o), tile[lx][r]);
+        }
+    }
+}
+
 hipError_t launch_permute4(const double* in, const int dims[4], const int perm[4],
                            const Buf& out, hipStream_t stream) {
     long st[4];
@@ -98,6 +136,29 @@ hipError_t launch_permute4(const double* in, const int dims[4], const int perm[4
     if (total == 0) return hipSuccess;
     const size_t rows = (size_t)p.od[0] * p.od[1], inner = (size_t)p.od[2] * p.od[3];
     if (total >= (1ull << 32) || rows > 65535) return hipErrorInvalidValue;
+    if (perm[3] != 3) {
+        PermT q;
+        for (int a = 0; a < 4; ++a) {
+            q.od[a] = p.od[a];
+            q.is[a] = (unsigned)p.is[a];
+        }
+        q.os[3] = 1;
+        q.os[2] = (unsigned)q.od[3];
+        q.os[1] = q.os[2] * (unsigned)q.od[2];
+        q.os[0] = q.os[1] * (unsigned)q.od[1];
+        q.a = perm[0] == 3 ? 0 : (perm[1] == 3 ? 1 : 2);
+        int k = 0, outer[2];
+        for (int a = 0; a < 3; ++a)
+            if (a != q.a) outer[k++] = a;
+        q.o1 = outer[0];
+        q.o2 = outer[1];
+        const size_t tiles = (size_t)((q.od[q.a] + 31) / 32) * ((q.od[3] + 31) / 32);
+        const size_t ys = (size_t)q.od[q.o1] * q.od[q.o2];
+        if (ys > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(permute4_tiled_kernel, dim3((unsigned)tiles, (unsigned)ys), dim3(256), 0, stream, in, q,
+                           out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(permute4_kernel, dim3((unsigned)((inner + 255) / 256), (unsigned)rows), dim3(256), 0, stream,
                        in, p, out);
     return hipGetLastError();
