@@ -447,16 +447,16 @@ def run_roofline(binding, accounting, precision, dmax, nsteps, temperature):
     }
 
 
-def run_c4(serve, accounting, workloads, precision, slots, budget):
+def run_c4(serve, accounting, workloads, precision, slots, budget, polled=False):
     """Served solves under Poisson arrivals (the serving workload's request
     mix), time-bounded: a rate below the knee and the overloaded 50 req/s.
     Requests without a result when the horizon ends are counted and enter
     the latency percentiles with the time they had waited by then (so those
     percentiles are lower bounds under overload)."""
-    srv = serve.Server(slots=slots, budget=budget, precision=precision)
+    srv = serve.Server(slots=slots, budget=budget, precision=precision, polled=polled)
     out = {"workload": "Poisson arrivals; Ising/Potts(q=3) uniform, T ~ U[0.5, 1.5] Tc, D in {16,24,32,48}, "
                        "20-40 steps, seeded; served with continuous batching",
-           "precision": precision, "slots": slots, "runs": []}
+           "precision": precision, "slots": slots, "stepping": "polled" if polled else "whole", "runs": []}
     for rate, seconds, horizon in ((10.0, 15.0, 30.0), (50.0, 10.0, 20.0)):
         reqs = workloads.request_stream(rate_hz=rate, duration_s=seconds)
         offered = sum(accounting.solve_flops(r.q, r.dmax, r.nsteps) for r in reqs) / seconds / 1e12
@@ -527,6 +527,8 @@ def main(argv=None):
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--concurrency", type=int, default=4, help="solves in flight (streams)")
+    ap.add_argument("--stepping", default="whole", choices=["whole", "polled"],
+                    help="whole steps (every eigensolver pass up to the cap enqueued) or host-polled steps")
     ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
     ap.add_argument("--no-c2", dest="c2", action="store_false", help="skip the D=24 temperature scan")
     ap.add_argument("--no-c4", dest="c4", action="store_false", help="skip the served Poisson stream")
@@ -560,7 +562,7 @@ def main(argv=None):
 
     def run_batch(precision, concurrency, warm_reqs, reqs):
         server = serve.Server(slots=concurrency, budget=args.budget_gb << 30, precision=precision,
-                              device="cuda:0", timing=True)
+                              device="cuda:0", timing=True, polled=args.stepping == "polled")
         if warm_reqs:
             server.run(warm_reqs, realtime=False)
         torch.cuda.synchronize()
@@ -621,6 +623,7 @@ def main(argv=None):
             "contraction_precision": args.precision,
             "eigensolve": "FP64",
             "concurrency": args.concurrency,
+            "stepping": args.stepping,
             "flops_per_solve": flops_solve,
         },
         "p50_solve_ms": serve.percentile(service, 50) * 1e3,
@@ -660,7 +663,8 @@ def main(argv=None):
     if args.c2:
         run_leg(line, "c2", run_c2, serve, accounting, workloads, args.budget_gb << 30)
     if args.c4:
-        run_leg(line, "c4", run_c4, serve, accounting, workloads, args.precision, 8, 160 << 30)
+        run_leg(line, "c4", run_c4, serve, accounting, workloads, args.precision, 8, 160 << 30,
+                args.stepping == "polled")
     if args.c5:
         run_leg(line, "c5", run_c5, binding, accounting)
     if args.observables:

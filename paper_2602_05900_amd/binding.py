@@ -26,6 +26,8 @@ MAX_STEPS = 60
 # how a step's eigensolve ended (hotrg_eig_info)
 EIG_CONVERGED, EIG_STAGNATED, EIG_PASS_CAP = 0, 1, 2
 EIG_MAX_PASSES = 60
+# host-polled stepping (hotrg_step_poll)
+POLL_IDLE, POLL_RUNNING, POLL_PASSES, POLL_STEPPED = 0, 1, 2, 3
 STAGES = ["permute", "env", "eig", "x", "y", "tp", "norm", "obs"]
 # observable slots (hotrg_observables): order parameter per site, energy of one y bond
 OBS_MAGNETIZATION, OBS_BOND_ENERGY = 1, 2
@@ -33,7 +35,8 @@ OBSERVABLES = {"m": OBS_MAGNETIZATION, "e": OBS_BOND_ENERGY}
 
 EXPORTS = [
     "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain",
-    "hotrg_coarse_grain_batch", "hotrg_coarse_grain_axis", "hotrg_log_z", "hotrg_log_z_chain",
+    "hotrg_coarse_grain_batch", "hotrg_coarse_grain_axis", "hotrg_step_begin", "hotrg_step_poll",
+    "hotrg_log_z", "hotrg_log_z_chain",
     "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_set_eig_limits",
     "hotrg_copy_tensor", "hotrg_copy_environment", "hotrg_copy_isometry", "hotrg_set_timing", "hotrg_stage_times", "hotrg_step_stage_times",
     "hotrg_gemm_y_time", "hotrg_destroy", "hotrg_strerror", "hotrg_device_count",
@@ -96,6 +99,8 @@ def load() -> ctypes.CDLL:
     lib.hotrg_coarse_grain.argtypes = [c_void_p, c_int]
     lib.hotrg_coarse_grain_batch.argtypes = [P(c_void_p), c_int, c_int]
     lib.hotrg_coarse_grain_axis.argtypes = [c_void_p, c_int, c_int]
+    lib.hotrg_step_begin.argtypes = [c_void_p, c_int, c_int, P(c_int)]
+    lib.hotrg_step_poll.argtypes = [c_void_p, P(c_int)]
     lib.hotrg_log_z_chain.argtypes = [c_void_p, P(c_double)]
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
@@ -270,6 +275,22 @@ class Solve:
         else:
             _check(self._lib.hotrg_coarse_grain_axis(self._h, int(nsteps), 0), "hotrg_coarse_grain_axis")
         return self
+
+    def step_begin(self, exchange: bool = True, extra: int = 0) -> bool:
+        """Begin one host-polled step (hotrg_step_begin) with `extra` passes
+        beyond the handle's history; True if it waits for step_poll, False
+        if the whole step was enqueued."""
+        pending = ctypes.c_int()
+        _check(self._lib.hotrg_step_begin(self._h, 1 if exchange else 0, int(extra), ctypes.byref(pending)),
+               "hotrg_step_begin")
+        return bool(pending.value)
+
+    def step_poll(self) -> int:
+        """One non-waiting poll of the pending step (hotrg_step_poll): one of
+        POLL_IDLE, POLL_RUNNING, POLL_PASSES, POLL_STEPPED."""
+        state = ctypes.c_int()
+        _check(self._lib.hotrg_step_poll(self._h, ctypes.byref(state)), "hotrg_step_poll")
+        return state.value
 
     def log_z_chain(self) -> float:
         """ln Z per tensor with x infinite and y closed (hotrg_log_z_chain)."""

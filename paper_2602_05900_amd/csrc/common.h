@@ -179,9 +179,22 @@ inline int eig_block(int n, int k) {
 // A solve that stops unconverged with a residual above fail_tol (relative to
 // theta_0), with non-finite eigenvalues, or a dense Jacobi at its sweep cap,
 // latches HOTRG_EEIG in st->status (first error sticks).
+//
+// The subspace iteration can be enqueued in parts (host-polled stepping):
+// `range` selects the start (initial block and its orthonormalisation),
+// passes [first, last) of the maxit passes, and the end (selection of the
+// kept vectors and the statistics).  A pass enqueued after the solve has
+// converged exits at once, so any split of [0, maxit) that stops at a pass
+// after which the convergence word reads done gives the result of the whole
+// range.  A dense solve (n <= kEigPMax) runs entirely with the start.
+struct EigRange {
+    int first = 0, last = -1;   // passes [first, last); last < 0: up to maxit
+    bool start = true, end = true;
+};
 hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
                            unsigned long long seed, int maxit, double tol, double fail_tol, const Buf& Ut,
-                           const Buf& Ux, DevState* st, int step, hipStream_t stream, int slot = 0);
+                           const Buf& Ux, DevState* st, int step, hipStream_t stream, int slot = 0,
+                           const EigRange& range = EigRange());
 
 // Two-sided truncation: when eps_right[step] < eps_left[step], copies the
 // right isometry (UtR, UxR: `bytes` bytes each, 16-byte multiple) over the

@@ -746,9 +746,13 @@ hipError_t launch_choose_side(DevState* st, int step, void* Ut, void* Ux, const 
 
 hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork& w, int parity, bool warm,
                            unsigned long long seed, int maxit, double tol, double fail_tol, const Buf& Ut,
-                           const Buf& Ux, DevState* st, int step, hipStream_t stream, int slot) {
+                           const Buf& Ux, DevState* st, int step, hipStream_t stream, int slot,
+                           const EigRange& range) {
     if (n < 1 || k < 1 || k > n || maxit < 1) return hipErrorInvalidValue;
+    const int it_first = range.first < 0 ? 0 : range.first;
+    const int it_last = range.last < 0 || range.last > maxit ? maxit : range.last;
     if (n <= EIG_PMAX) {
+        if (!range.start) return hipSuccess;
         hipLaunchKernelGGL(eig_init_kernel, dim3(1), dim3(256), 0, stream, E, n, (double*)nullptr, 0, 1, seed, w.ctl);
         hipLaunchKernelGGL(eig_jacobi_kernel, dim3(1), dim3(EIG_JT), 0, stream, E, n, n, w.theta, w.S, w.ctl, 0);
         hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, w.S, n, n, dx, k, Ut, Ux);
@@ -762,7 +766,9 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
     const int pstride = EIG_PMAX * EIG_PMAX + EIG_PMAX;
     const int nb = (n + EIG_GRAM_ROWS - 1) / EIG_GRAM_ROWS;
     const unsigned g_init = grid_for((long)n * p, 256) > 1024 ? 1024 : grid_for((long)n * p, 256);
-    hipLaunchKernelGGL(eig_init_kernel, dim3(g_init), dim3(256), 0, stream, E, n, V, p, warm ? 1 : 0, seed, w.ctl);
+    if (range.start)
+        hipLaunchKernelGGL(eig_init_kernel, dim3(g_init), dim3(256), 0, stream, E, n, V, p, warm ? 1 : 0, seed,
+                           w.ctl);
 
     auto orth = [&](const double* src, double shift1, unsigned long long s2) {
         // pass 1 (column-scaled, shifted) from src into V, pass 2 in place
@@ -782,8 +788,8 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
                            w.ctl);
     };
     const double shift = 1e-13;
-    orth(V, shift, seed * 31 + 7);
-    for (int it = 0; it < maxit; ++it) {
+    if (range.start) orth(V, shift, seed * 31 + 7);
+    for (int it = it_first; it < it_last; ++it) {
         hipLaunchKernelGGL(eig_ev_kernel, dim3(grid_for(n, 16)), dim3(256), 0, stream, E, n, V, w.W, p, w.ctl);
         if (it % EIG_RR_EVERY != EIG_RR_EVERY - 1 && it != maxit - 1) {
             // power step without Rayleigh-Ritz: V <- orth(E V)
@@ -812,6 +818,7 @@ hipError_t launch_eig_topk(const double* E, int n, int k, int dx, const EigWork&
         hipLaunchKernelGGL(eig_orth_apply_kernel, dim3(nb), dim3(256), 0, stream, w.W, V, n, p, w.L, w.dsc,
                            seed * 131 + it, w.ctl);
     }
+    if (!range.end) return hipGetLastError();
     hipLaunchKernelGGL(eig_select_kernel, dim3(k), dim3(256), 0, stream, V, p, n, dx, k, Ut, Ux);
     hipLaunchKernelGGL(eig_stats_kernel, dim3(1), dim3(64), 0, stream, w.theta, p, n, k, w.ctl, st, step, slot,
                        fail_tol);

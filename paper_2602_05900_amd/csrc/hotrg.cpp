@@ -463,6 +463,16 @@ struct hotrg_solve {
     int last_n = 0, last_dp = 0;    // fused-leg size and kept count of the last step
     int eig_maxit = kEigMaxIt;      // subspace passes per eigensolve
     double eig_fail = kEigFailTol;  // residual above which an unconverged solve fails
+    // host-polled stepping: the convergence word of the eigensolve in flight
+    // is copied to pinned host memory after each group of passes, so the
+    // host enqueues only the passes a solve needs
+    EigCtl* mail = nullptr;         // pinned host copy (hipHostMalloc)
+    hipEvent_t mail_ev = nullptr;   // recorded after the copy
+    bool pend = false;              // a begun step waits for its eigensolve
+    bool pend_exchange = true;
+    int pend_next = 0;              // next subspace pass to enqueue
+    int pend_par = 0;
+    int hist[2] = {0, 0};           // passes the last polled eigensolve of each parity used
     bool timing = false;
     int timed_from = 0;  // first step recorded with events
     std::vector<hipEvent_t> ev;
@@ -544,7 +554,16 @@ bool step_fits(const Layout& L, int Dx, int Dy, int Dp) {
     return true;
 }
 
-int enqueue_step(hotrg_solve* s, bool exchange = true) {
+// Which parts of a step enqueue_step enqueues: the environment(s), a range
+// of the eigensolve, and the products with the normalisation and the step
+// bookkeeping.  The default is the whole step.
+struct StepPart {
+    bool env = true;
+    EigRange eig;
+    bool rest = true;
+};
+
+int enqueue_step(hotrg_solve* s, bool exchange = true, const StepPart& part = StepPart()) {
     const int n = s->steps + 1;       // 1-based step number
     const int Dx = s->dx, Dy = s->dy;
     const int Dp = (int)std::min<long>(s->p.dmax, (long)Dx * Dx);
@@ -565,7 +584,7 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
     const int dims[4] = {Dx, Dx, Dy, Dy};
     const int step_index = s->steps;
     int rc;
-    if (s->timing && step_index >= s->timed_from) s->timed_dims.push_back({Dx, Dy, Dp});
+    if (part.env && s->timing && step_index >= s->timed_from) s->timed_dims.push_back({Dx, Dy, Dp});
 
     // -- half environments and E
     // With the split formats and whole 32-row panels, the half-environment
@@ -618,17 +637,19 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
         HIP_TRY(s, launch_symmetrize(Eout, nE, s->stream));
         return HOTRG_OK;
     };
-    record(s, step_index, 0);
-    {
-        const int p1[4] = {0, 3, 1, 2}, p2[4] = {0, 2, 1, 3};
-        if ((rc = environment(p1, p2, E))) return rc;
-    }
     double* ER = two ? reinterpret_cast<double*>(w + L.oER) : nullptr;
-    if (two) {
-        const int p1[4] = {1, 3, 0, 2}, p2[4] = {1, 2, 0, 3};
-        if ((rc = environment(p1, p2, ER))) return rc;
+    if (part.env) {
+        record(s, step_index, 0);
+        {
+            const int p1[4] = {0, 3, 1, 2}, p2[4] = {0, 2, 1, 3};
+            if ((rc = environment(p1, p2, E))) return rc;
+        }
+        if (two) {
+            const int p1[4] = {1, 3, 0, 2}, p2[4] = {1, 2, 0, 3};
+            if ((rc = environment(p1, p2, ER))) return rc;
+        }
+        record(s, step_index, 2);
     }
-    record(s, step_index, 2);
     // -- FP64 eigensolve(s) and isometry
     {
         // Ritz block kept per fused axis: with the exchange the axes alternate,
@@ -639,8 +660,8 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
         const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)n;
         const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;
         HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, s->eig_maxit, kEigTol, s->eig_fail,
-                                   Ut, Ux, s->state(), n, s->stream, 0));
-        if (two) {
+                                   Ut, Ux, s->state(), n, s->stream, 0, part.eig));
+        if (two) {   // whole steps only (the host-polled form takes one-sided solves)
             const Buf UtR = make_buf(w, L.oUtR, f, L.nU), UxR = make_buf(w, L.oUxR, f, L.nU);
             const bool warm_r = nE > kEigPMax && s->warm_nr[par] == nE && s->warm_pr[par] == pblk;
             HIP_TRY(s, launch_eig_topk(ER, nE, Dp, Dx, s->eig_right(), par, warm_r, seed, s->eig_maxit,
@@ -648,11 +669,12 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
             HIP_TRY(s, launch_choose_side(s->state(), n, Ut.ptr, Ux.ptr, UtR.ptr, UxR.ptr, buf_bytes(f, L.nU),
                                           s->stream));
         }
-        if (nE > kEigPMax) {
+        if (nE > kEigPMax && part.eig.start) {
             s->warm_n[par] = s->warm_nr[par] = nE;
             s->warm_p[par] = s->warm_pr[par] = pblk;
         }
     }
+    if (!part.rest) return HOTRG_OK;
     record(s, step_index, 3);
     // The Y product's operands, X [(l,d,r1) x (a2,k)] and P4 [(u,r) x (l,d)],
     // both with rows of Kp = Dx Dy elements, are written in the 32 x 16 panel
@@ -758,12 +780,27 @@ int enqueue_step(hotrg_solve* s, bool exchange = true) {
     return HOTRG_OK;
 }
 
+// Host-polled stepping: the first group of subspace passes is as many as the
+// handle's last eigensolve of the same parity needed (kPollFirst before any
+// is known); later groups are kPollChunk passes.  Groups end on a pass with
+// a convergence check (every EIG_RR_EVERY = 2 passes).
+constexpr int kPollFirst = 8;
+constexpr int kPollChunk = 4;
+
+int mail_copy(hotrg_solve* s) {
+    HIP_TRY(s, hipMemcpyAsync(s->mail, s->eig().ctl, sizeof(EigCtl), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipEventRecord(s->mail_ev, s->stream));
+    return HOTRG_OK;
+}
+
 // Builds T0 (and the impurity tensors) for p on the host, normalises them by
 // c_0 = max|T0|, uploads them and a fresh device state (ln Z accumulator =
 // ln c_0), and resets the step count.
 int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     initial_dims(p, &s->dx, &s->dy);
     s->steps = 0;
+    s->pend = false;
+    s->hist[0] = s->hist[1] = 0;
     s->timed_from = 0;
     s->timed_dims.clear();
     for (int i = 0; i < 2; ++i) s->warm_n[i] = s->warm_p[i] = s->warm_nr[i] = s->warm_pr[i] = 0;
@@ -924,7 +961,7 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
 }
 
 int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
-    if (!s || nsteps < 0) return HOTRG_EINVAL;
+    if (!s || nsteps < 0 || s->pend) return HOTRG_EINVAL;
     if (s->host_status) return HOTRG_ESTATE;
     if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
     for (int i = 0; i < nsteps; ++i) {
@@ -935,7 +972,7 @@ int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
 }
 
 int hotrg_coarse_grain_axis(hotrg_solve* s, int nsteps, int exchange) {
-    if (!s || nsteps < 0 || (exchange != 0 && exchange != 1)) return HOTRG_EINVAL;
+    if (!s || nsteps < 0 || (exchange != 0 && exchange != 1) || s->pend) return HOTRG_EINVAL;
     if (s->host_status) return HOTRG_ESTATE;
     if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
     for (int i = 0; i < nsteps; ++i) {
@@ -965,7 +1002,7 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps) 
     // k times needs room for k * nsteps more steps
     for (int i = 0; i < count; ++i) {
         hotrg_solve* s = solves[i];
-        if (!s) return HOTRG_EINVAL;
+        if (!s || s->pend) return HOTRG_EINVAL;
         int times = 0;
         for (int j = 0; j < count; ++j) times += solves[j] == s;
         if (s->steps + (long)times * nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
@@ -977,6 +1014,80 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps) 
             const int rc = enqueue_step(solves[i]);
             if (rc) return rc;
         }
+    return HOTRG_OK;
+}
+
+int hotrg_step_begin(hotrg_solve* s, int exchange, int extra, int* pending) {
+    if (pending) *pending = 0;
+    if (!s || (exchange != 0 && exchange != 1) || extra < 0 || s->pend) return HOTRG_EINVAL;
+    if (s->host_status) return HOTRG_ESTATE;
+    if (s->steps + 1 > step_cap(&s->p)) return HOTRG_EINVAL;
+    // dense eigensolves and two-sided steps are enqueued whole
+    if (s->dx * s->dx <= kEigPMax || s->p.two_sided) return enqueue_step(s, exchange != 0);
+    if (!s->mail) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, sizeof(EigCtl), hipHostMallocDefault) != hipSuccess) return HOTRG_EHIP;
+        s->mail = static_cast<EigCtl*>(h);
+        if (hipEventCreateWithFlags(&s->mail_ev, hipEventDisableTiming) != hipSuccess) {
+            s->mail_ev = nullptr;
+            return HOTRG_EHIP;
+        }
+    }
+    const int par = exchange ? (s->steps & 1) : 0;
+    int first = (s->hist[par] > 0 ? s->hist[par] : kPollFirst) + std::min(extra, HOTRG_EIG_MAX_PASSES);
+    first = std::min((first + 1) / 2 * 2, s->eig_maxit);
+    StepPart part;
+    part.eig.last = first;
+    part.eig.end = false;
+    part.rest = false;
+    int rc = enqueue_step(s, exchange != 0, part);
+    if (rc) return rc;
+    if ((rc = mail_copy(s))) return rc;
+    s->pend = true;
+    s->pend_exchange = exchange != 0;
+    s->pend_next = first;
+    s->pend_par = par;
+    if (pending) *pending = 1;
+    return HOTRG_OK;
+}
+
+int hotrg_step_poll(hotrg_solve* s, int* state) {
+    if (!s || !state) return HOTRG_EINVAL;
+    *state = HOTRG_POLL_IDLE;
+    if (!s->pend) return HOTRG_OK;
+    if (s->host_status) return HOTRG_ESTATE;
+    const hipError_t q = hipEventQuery(s->mail_ev);
+    if (q == hipErrorNotReady) {
+        *state = HOTRG_POLL_RUNNING;
+        return HOTRG_OK;
+    }
+    if (q != hipSuccess) {
+        s->host_status = HOTRG_EHIP;
+        return HOTRG_EHIP;
+    }
+    EigCtl c;
+    memcpy(&c, s->mail, sizeof c);
+    StepPart part;
+    part.env = false;
+    part.eig.start = false;
+    part.eig.first = s->pend_next;
+    int rc;
+    if (c.done || s->pend_next >= s->eig_maxit) {
+        // converged, stagnated or at the pass cap: the rest of the step
+        part.eig.last = s->pend_next;
+        s->hist[s->pend_par] = c.iters > 0 ? c.iters : s->pend_next;
+        s->pend = false;
+        if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
+        *state = HOTRG_POLL_STEPPED;
+        return HOTRG_OK;
+    }
+    part.eig.last = std::min(s->pend_next + kPollChunk, s->eig_maxit);
+    part.eig.end = false;
+    part.rest = false;
+    if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
+    if ((rc = mail_copy(s))) return rc;
+    s->pend_next = part.eig.last;
+    *state = HOTRG_POLL_PASSES;
     return HOTRG_OK;
 }
 
@@ -1211,6 +1322,8 @@ void hotrg_destroy(hotrg_solve* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->mail_ev) (void)hipEventDestroy(s->mail_ev);
+    if (s->mail) (void)hipHostFree(s->mail);
     delete s;
 }
 

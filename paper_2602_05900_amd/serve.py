@@ -63,6 +63,7 @@ class _Active:
     admitted: float
     slot: int = -1
     enqueued: int = 0
+    pending: bool = False     # a host-polled step waits for its eigensolve
     events: collections.deque = field(default_factory=collections.deque)
 
 
@@ -75,12 +76,23 @@ class Server:
                 device (keeps every stream busy without flooding the host)
     precision   contraction precision of every solve
     timing      record per-stage HIP events of every solve (hotrg_stage_times)
+    polled      advance solves by host-polled steps (hotrg_step_begin /
+                hotrg_step_poll): the scheduler enqueues a step's products
+                once the host has seen its eigensolve converge, so no pass
+                after convergence is enqueued; otherwise whole steps
+                (hotrg_coarse_grain_batch) with every pass up to the cap
+    poll_extra  passes beyond a solve's history in a polled step's first group
+    idle_sleep  seconds the scheduling loop sleeps when a round enqueued nothing
     """
 
     def __init__(self, slots: int = 8, budget: int = 64 << 30, depth: int = 2,
-                 precision: str = "fp64", device: str = "cuda:0", timing: bool = False):
+                 precision: str = "fp64", device: str = "cuda:0", timing: bool = False,
+                 polled: bool = False, poll_extra: int = 0, idle_sleep: float = 2e-4):
         binding.load()
         self.timing = timing
+        self.polled = polled
+        self.poll_extra = poll_extra
+        self.idle_sleep = idle_sleep
         self.device = torch.device(device)
         self.slots = slots
         self.budget = budget
@@ -130,9 +142,41 @@ class Server:
                         slot=si)
             self.active.append(a)
 
+    def _stepped(self, a: _Active):
+        ev = torch.cuda.Event()
+        ev.record(a.stream)
+        a.events.append(ev)
+
+    def _advance_polled(self) -> bool:
+        """Poll every solve's pending step (enqueueing more eigensolver passes
+        or the step's products), and begin the next step of a solve that has
+        none pending and room on its stream; True if anything was enqueued."""
+        progressed = False
+        for a in self.active:
+            while a.events and a.events[0].query():
+                a.events.popleft()
+            if a.pending:
+                st = a.solve.step_poll()
+                if st == binding.POLL_RUNNING:
+                    continue
+                progressed = True
+                if st == binding.POLL_PASSES:
+                    continue
+                a.pending = False          # POLL_STEPPED
+                self._stepped(a)
+            if a.enqueued < a.req.nsteps and len(a.events) < self.depth:
+                a.enqueued += 1
+                a.pending = a.solve.step_begin(extra=self.poll_extra)
+                if not a.pending:
+                    self._stepped(a)
+                progressed = True
+        return progressed
+
     def _advance(self) -> bool:
         """Enqueue at most one step per active solve, as one grouped call over
         the solves that have room; returns True if any step was enqueued."""
+        if self.polled:
+            return self._advance_polled()
         ready = []
         for a in self.active:
             while a.events and a.events[0].query():
@@ -152,7 +196,7 @@ class Server:
     def _complete(self):
         still = []
         for a in self.active:
-            if a.enqueued == a.req.nsteps and all(e.query() for e in a.events):
+            if a.enqueued == a.req.nsteps and not a.pending and all(e.query() for e in a.events):
                 lnz = a.solve.log_z()          # its stream is idle: returns at once
                 st = a.solve.stage_times()[0] if self.timing else None
                 r = a.req
@@ -198,8 +242,8 @@ class Server:
             if progress and now - last_report >= 5.0:
                 progress(now, len(self.done) - n_before, n_total, len(self.active), len(self.queue))
                 last_report = now
-            if not progressed:
-                time.sleep(0.0002)
+            if not progressed and self.idle_sleep > 0:
+                time.sleep(self.idle_sleep)
         torch.cuda.synchronize(self.device)
         return sorted(self.done[n_before:], key=lambda c: c.rid)
 

@@ -51,7 +51,8 @@ def _fake_server_class(calls):
     from paper_2602_05900_amd import accounting, serve
 
     class FakeServer:
-        def __init__(self, slots=8, budget=0, depth=2, precision="fp64", device="cuda:0", timing=False):
+        def __init__(self, slots=8, budget=0, depth=2, precision="fp64", device="cuda:0", timing=False,
+                     polled=False):
             self.precision = precision
             self.timing = timing
             self.peak_in_use = self.in_use = 0

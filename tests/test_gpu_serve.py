@@ -62,3 +62,117 @@ def ctypes_steps(solve):
     v, n = ctypes.c_double(), ctypes.c_int()
     assert solve._lib.hotrg_log_z(solve._h, ctypes.byref(v), ctypes.byref(n)) == 0
     return n.value
+
+
+def _polled(solve, nsteps, exchange=True, extra=0):
+    """Advance `solve` by nsteps host-polled steps; returns the poll states seen."""
+    from paper_2602_05900_amd import binding
+    seen = []
+    for _ in range(nsteps):
+        if not solve.step_begin(exchange, extra):
+            seen.append("whole")
+            continue
+        while True:
+            st = solve.step_poll()
+            seen.append(st)
+            if st == binding.POLL_STEPPED:
+                break
+    assert solve.step_poll() == binding.POLL_IDLE
+    return seen
+
+
+@pytest.mark.parametrize("model,q,t,d,prec,n,extra", [
+    ("ising", 2, 2.25, 24, "fp64", 14, 0),
+    ("potts", 3, 1.0, 16, "fp64", 12, 1),
+    ("ising", 2, 2.3, 32, "bf16x6", 10, 0),
+    ("ising", 2, 2.269185314213022, 48, "fp16x3", 9, 2),
+])
+def test_polled_steps_equal_whole_steps(gpu_lib, model, q, t, d, prec, n, extra):
+    """hotrg_step_begin / hotrg_step_poll enqueue the same passes as a whole
+    step, minus those after convergence: ln Z, every c_n and the eigensolver
+    record (passes used, residual, stop reason) are bitwise those of
+    hotrg_coarse_grain."""
+    from paper_2602_05900_amd import binding
+    ref = binding.Solve(model=model, q=q, temperature=t, dmax=d, precision=prec, max_steps=n)
+    ref.coarse_grain(n)
+    s = binding.Solve(model=model, q=q, temperature=t, dmax=d, precision=prec, max_steps=n)
+    seen = _polled(s, n, extra=extra)
+    assert binding.POLL_STEPPED in seen and "whole" in seen
+    assert s.log_z() == ref.log_z()
+    for k in range(1, n + 1):
+        assert s.step_info(k) == ref.step_info(k), k
+        assert s.eig_info(k) == ref.eig_info(k), k
+    s.close()
+    ref.close()
+
+
+def test_polled_quantum_chain_and_pass_cap(gpu_lib):
+    """Steps without the axis exchange (quantum chain) and a pass cap below
+    what the eigensolve needs: the polled form stops at the same pass and
+    latches the same status as the whole-step form."""
+    from paper_2602_05900_amd import binding, workloads
+    h = workloads.heisenberg_bond()
+    tau, k = 2.0 ** -8, 8
+    ref = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=24, max_steps=k)
+    ref.coarse_grain(k, exchange=False)
+    s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=24, max_steps=k)
+    _polled(s, k, exchange=False)
+    assert s.log_z_chain() == ref.log_z_chain()
+    s.close()
+    ref.close()
+    outs = []
+    for polled in (False, True):
+        s = binding.Solve(model="ising", q=2, temperature=2.269185314213022, dmax=24, max_steps=12)
+        s.set_eig_limits(3, 1e-30)       # stops at pass 3; any residual above 1e-30 fails
+        if polled:
+            _polled(s, 12)
+        else:
+            s.coarse_grain(12)
+        with pytest.raises(binding.HotrgError) as e:
+            s.log_z()
+        outs.append(e.value.status)
+        s.close()
+    assert outs[0] == outs[1] == binding.EEIG
+
+
+def test_polled_pending_step_blocks_whole_steps(gpu_lib):
+    import torch
+    from paper_2602_05900_amd import binding
+    s = binding.Solve(model="ising", q=2, temperature=2.3, dmax=24, max_steps=10)
+    s.coarse_grain(4)                    # step 5 is the first with Dx^2 > 96
+    assert s.step_begin()
+    with pytest.raises(binding.HotrgError) as e:
+        s.coarse_grain(1)
+    assert e.value.status == binding.EINVAL
+    with pytest.raises(binding.HotrgError):
+        s.step_begin()
+    torch.cuda.synchronize()
+    while s.step_poll() != binding.POLL_STEPPED:
+        pass
+    s.coarse_grain(1)
+    ref = binding.Solve(model="ising", q=2, temperature=2.3, dmax=24, max_steps=10)
+    ref.coarse_grain(6)
+    assert s.log_z() == ref.log_z()
+    s.close()
+    ref.close()
+
+
+def test_polled_server_results_identical_alone_and_in_the_mix(gpu_lib):
+    from paper_2602_05900_amd import binding, serve, workloads
+    reqs = [workloads.Request(rid=i, arrival=0.001 * i, model=m, q=q, temperature=t, dmax=d, nsteps=n)
+            for i, (m, q, t, d, n) in enumerate([
+                ("ising", 2, 2.1, 16, 20), ("potts", 3, 1.05, 16, 24), ("ising", 2, 2.4, 24, 22),
+                ("potts", 3, 0.8, 24, 20), ("ising", 2, 1.3, 32, 21), ("ising", 2, 2.27, 48, 20)])]
+    alone = {}
+    for r in reqs:
+        s = binding.Solve(model=r.model, q=r.q, temperature=r.temperature, dmax=r.dmax, max_steps=r.nsteps,
+                          precision="fp16x3")
+        s.coarse_grain(r.nsteps)
+        alone[r.rid] = s.log_z()
+        s.close()
+    srv = serve.Server(slots=4, budget=32 << 30, precision="fp16x3", polled=True)
+    done = srv.run(reqs, realtime=False)
+    assert len(done) == len(reqs)
+    for c in done:
+        assert c.lnz_per_site == alone[c.rid], (c.rid, c.lnz_per_site, alone[c.rid])
+    assert srv.in_use == 0

@@ -23,11 +23,32 @@ class FakeSolve:
     def __init__(self, **kw):
         self.kw = kw
         self.steps = 0
+        self.polls = 0
         FakeSolve.live += 1
 
     def coarse_grain(self, n):
         self.steps += n
         return self
+
+    def step_begin(self, exchange=True, extra=0):
+        # steps of the small dims are enqueued whole; later ones need polls
+        if self.steps < 2:
+            self.steps += 1
+            return False
+        self.polls = 3
+        return True
+
+    def step_poll(self):
+        from paper_2602_05900_amd import binding
+        if self.polls == 0:
+            return binding.POLL_IDLE
+        self.polls -= 1
+        if self.polls == 2:
+            return binding.POLL_RUNNING
+        if self.polls == 1:
+            return binding.POLL_PASSES
+        self.steps += 1
+        return binding.POLL_STEPPED
 
     def log_z(self):
         return 1.0 + self.kw["temperature"] * 1e-3 + self.steps * 1e-6
@@ -79,6 +100,19 @@ def test_admission_respects_budget_and_completes_everything(fake_device):
     for c in done:
         r = reqs[c.rid]
         assert c.nsteps == r.nsteps and abs(c.lnz_per_site - (1.0 + r.temperature * 1e-3 + r.nsteps * 1e-6)) < 1e-12
+
+
+def test_polled_server_takes_every_step(fake_device):
+    """The host-polled form: every solve ends with exactly its step count,
+    whole steps and polled steps mixed, and nothing is left pending."""
+    reqs = workloads.request_stream(rate_hz=200.0, duration_s=0.3, seed=5)
+    srv = serve.Server(slots=4, budget=1 << 40, precision="fp64", device="cpu", polled=True)
+    done = srv.run(reqs, realtime=False)
+    assert len(done) == len(reqs)
+    for c in done:
+        r = reqs[c.rid]
+        assert abs(c.lnz_per_site - (1.0 + r.temperature * 1e-3 + r.nsteps * 1e-6)) < 1e-12
+    assert srv.in_use == 0 and FakeSolve.live == 0
 
 
 def test_request_larger_than_budget_is_rejected(fake_device):
