@@ -1028,10 +1028,10 @@ int hotrg_step_begin(hotrg_solve* s, int exchange, int extra, int* pending) {
         void* h = nullptr;
         if (hipHostMalloc(&h, sizeof(EigCtl), hipHostMallocDefault) != hipSuccess) return HOTRG_EHIP;
         s->mail = static_cast<EigCtl*>(h);
-        if (hipEventCreateWithFlags(&s->mail_ev, hipEventDisableTiming) != hipSuccess) {
-            s->mail_ev = nullptr;
-            return HOTRG_EHIP;
-        }
+    }
+    if (!s->mail_ev && hipEventCreateWithFlags(&s->mail_ev, hipEventDisableTiming) != hipSuccess) {
+        s->mail_ev = nullptr;
+        return HOTRG_EHIP;
     }
     const int par = exchange ? (s->steps & 1) : 0;
     int first = (s->hist[par] > 0 ? s->hist[par] : kPollFirst) + std::min(extra, HOTRG_EIG_MAX_PASSES);
