@@ -220,9 +220,10 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps);
  * the eigensolve of a step may need (up to the pass cap), and the passes
  * after convergence exit at once; with many solves on one device those
  * launches still take dispatch slots from the others.  In this form one step
- * is enqueued in parts and the host decides, from the eigensolver's
- * convergence word copied to pinned host memory, whether more passes are
- * needed before the step's products are enqueued:
+ * is enqueued in parts and the host decides, from the eigensolver's stop
+ * state written to pinned host memory (allocated by the library, one word
+ * per handle, freed by hotrg_destroy), whether more passes are needed
+ * before the step's products are enqueued:
  *   hotrg_step_begin  enqueues the step's environment, the start of its
  *                     eigensolve and as many subspace passes as the handle's
  *                     last eigensolve of the same parity needed (8 for the
@@ -230,24 +231,27 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps);
  *                     more passes that may run after convergence; the group
  *                     is rounded up to an even count, since convergence is
  *                     tested every second pass, and capped at the pass
- *                     limit), then the copy of the convergence word;
+ *                     limit), then the store of the stop state;
  *                     *pending (may be NULL) = 1.  A step whose environment
  *                     is diagonalised densely (Dx^2 <= 96) or a two-sided
  *                     handle has the whole step enqueued at once and
  *                     *pending = 0.  exchange as in hotrg_coarse_grain_axis.
  *   hotrg_step_poll   never waits.  *state = HOTRG_POLL_IDLE (no step
- *                     pending), HOTRG_POLL_RUNNING (the last copy has not
+ *                     pending), HOTRG_POLL_RUNNING (the last store has not
  *                     arrived; nothing enqueued), HOTRG_POLL_PASSES (not
- *                     converged: 4 more passes and a new copy enqueued) or
+ *                     converged: 4 more passes and a new store enqueued) or
  *                     HOTRG_POLL_STEPPED (the eigensolve has stopped: its end,
  *                     the products and the normalisation are enqueued and the
  *                     step counts among the steps taken).
  * The passes, their order and their arguments are those of the whole-step
- * form, so the results are bitwise the same.  While a step is pending, the
+ * form, so the results are bitwise the same.  Each step then waits for the
+ * host between its eigensolve and its products: with several solves in
+ * one process this form measures a few percent slower than whole steps; it
+ * is for devices whose dispatch is shared with other launchers.  While a
+ * step is pending, the
  * whole-step calls return EINVAL.  Errors: EINVAL (begin: exchange not
  * 0/1, extra < 0, a step already pending, step cap; poll: NULL state),
- * ESTATE, ENOMEM,
- * EHIP (pinned memory, events or enqueueing). */
+ * ESTATE, ENOMEM, EHIP (pinned memory or enqueueing). */
 #define HOTRG_POLL_IDLE     0
 #define HOTRG_POLL_RUNNING  1
 #define HOTRG_POLL_PASSES   2

@@ -140,6 +140,16 @@ struct EigCtl {
     int jac_capped;  // the last Jacobi diagonalisation ended at its sweep cap
 };
 
+// Host-visible stop state of an eigensolve (pinned, fine-grained host
+// memory), written by one device thread after a group of subspace passes as
+// one 64-bit word: seq << 32 | iters << 1 | done.  A single store needs no
+// fence (a release at system scope would write back the whole L2), and the
+// host that reads the seq it expects has the matching done and iters.
+struct EigMail {
+    unsigned long long word;
+};
+hipError_t launch_eig_mail(const EigCtl* ctl, EigMail* mail, int seq, hipStream_t stream);
+
 constexpr int kEigPMax = 96;   // largest Ritz block / largest fully diagonalised E
 
 // Device buffers of the eigensolver (FP64), carved from the workspace.

@@ -732,6 +732,21 @@ __global__ __launch_bounds__(256) void choose_side_kernel(DevState* st, int step
 
 static unsigned grid_for(long count, int per) { return (unsigned)((count + per - 1) / per); }
 
+// One thread copies the eigensolve's stop state to host memory as one
+// system-scope store, so that the host sees it without a copy engine or an
+// event.
+__global__ __launch_bounds__(64) void eig_mail_kernel(const EigCtl* __restrict__ ctl, EigMail* mail, int seq) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long word = ((unsigned long long)(unsigned)seq << 32) |
+                                    ((unsigned long long)(unsigned)ctl->iters << 1) | (ctl->done ? 1ull : 0ull);
+    __hip_atomic_store(&mail->word, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_eig_mail(const EigCtl* ctl, EigMail* mail, int seq, hipStream_t stream) {
+    hipLaunchKernelGGL(eig_mail_kernel, dim3(1), dim3(64), 0, stream, ctl, mail, seq);
+    return hipGetLastError();
+}
+
 hipError_t launch_choose_side(DevState* st, int step, void* Ut, void* Ux, const void* UtR, const void* UxR,
                               size_t bytes, hipStream_t stream) {
     if (bytes % 16) return hipErrorInvalidValue;

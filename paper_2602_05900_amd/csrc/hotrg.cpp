@@ -463,11 +463,11 @@ struct hotrg_solve {
     int last_n = 0, last_dp = 0;    // fused-leg size and kept count of the last step
     int eig_maxit = kEigMaxIt;      // subspace passes per eigensolve
     double eig_fail = kEigFailTol;  // residual above which an unconverged solve fails
-    // host-polled stepping: the convergence word of the eigensolve in flight
-    // is copied to pinned host memory after each group of passes, so the
-    // host enqueues only the passes a solve needs
-    EigCtl* mail = nullptr;         // pinned host copy (hipHostMalloc)
-    hipEvent_t mail_ev = nullptr;   // recorded after the copy
+    // host-polled stepping: the stop state of the eigensolve in flight is
+    // written to pinned host memory after each group of passes, so the host
+    // enqueues only the passes a solve needs
+    EigMail* mail = nullptr;        // pinned, fine-grained (hipHostMalloc)
+    int mail_seq = 0;               // seq of the last write enqueued
     bool pend = false;              // a begun step waits for its eigensolve
     bool pend_exchange = true;
     int pend_next = 0;              // next subspace pass to enqueue
@@ -788,8 +788,8 @@ constexpr int kPollFirst = 8;
 constexpr int kPollChunk = 4;
 
 int mail_copy(hotrg_solve* s) {
-    HIP_TRY(s, hipMemcpyAsync(s->mail, s->eig().ctl, sizeof(EigCtl), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(s, hipEventRecord(s->mail_ev, s->stream));
+    s->mail_seq += 1;
+    HIP_TRY(s, launch_eig_mail(s->eig().ctl, s->mail, s->mail_seq, s->stream));
     return HOTRG_OK;
 }
 
@@ -1026,12 +1026,10 @@ int hotrg_step_begin(hotrg_solve* s, int exchange, int extra, int* pending) {
     if (s->dx * s->dx <= kEigPMax || s->p.two_sided) return enqueue_step(s, exchange != 0);
     if (!s->mail) {
         void* h = nullptr;
-        if (hipHostMalloc(&h, sizeof(EigCtl), hipHostMallocDefault) != hipSuccess) return HOTRG_EHIP;
-        s->mail = static_cast<EigCtl*>(h);
-    }
-    if (!s->mail_ev && hipEventCreateWithFlags(&s->mail_ev, hipEventDisableTiming) != hipSuccess) {
-        s->mail_ev = nullptr;
-        return HOTRG_EHIP;
+        if (hipHostMalloc(&h, sizeof(EigMail), hipHostMallocCoherent) != hipSuccess) return HOTRG_EHIP;
+        s->mail = static_cast<EigMail*>(h);
+        memset(s->mail, 0, sizeof(EigMail));
+        s->mail_seq = 0;
     }
     const int par = exchange ? (s->steps & 1) : 0;
     int first = (s->hist[par] > 0 ? s->hist[par] : kPollFirst) + std::min(extra, HOTRG_EIG_MAX_PASSES);
@@ -1056,17 +1054,14 @@ int hotrg_step_poll(hotrg_solve* s, int* state) {
     *state = HOTRG_POLL_IDLE;
     if (!s->pend) return HOTRG_OK;
     if (s->host_status) return HOTRG_ESTATE;
-    const hipError_t q = hipEventQuery(s->mail_ev);
-    if (q == hipErrorNotReady) {
+    const unsigned long long word = __atomic_load_n(&s->mail->word, __ATOMIC_ACQUIRE);
+    if ((int)(word >> 32) != s->mail_seq) {
         *state = HOTRG_POLL_RUNNING;
         return HOTRG_OK;
     }
-    if (q != hipSuccess) {
-        s->host_status = HOTRG_EHIP;
-        return HOTRG_EHIP;
-    }
-    EigCtl c;
-    memcpy(&c, s->mail, sizeof c);
+    struct {
+        int done, iters;
+    } c{(int)(word & 1u), (int)((word >> 1) & 0x7fffffffu)};
     StepPart part;
     part.env = false;
     part.eig.start = false;
@@ -1322,7 +1317,6 @@ void hotrg_destroy(hotrg_solve* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
-    if (s->mail_ev) (void)hipEventDestroy(s->mail_ev);
     if (s->mail) (void)hipHostFree(s->mail);
     delete s;
 }
