@@ -30,6 +30,15 @@ temperatures with the finite-difference internal energy against Onsager
 solve at Tc in BF16x6 and in FP64 ("c5"), two-sided truncation with
 impurity observables, iTEBD chains and the quantum chain.
 
+Stepping (--stepping for the headline batch and the served stream,
+--latency-stepping for the one-solve-at-a-time legs C2 and the quantum
+chain): whole steps enqueue every eigensolver pass up to the cap, and a pass
+after convergence exits at once; host-polled steps enqueue a step's
+products once the eigensolve has stopped, either from the scheduler loop
+("polled") or from the library's progress thread ("engine").  The results
+are bitwise the same.  Measured, whole steps are faster with four solves in
+flight and the engine is faster for one solve at a time, hence the defaults.
+
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16x3|bf16x6|fp16x3] [--concurrency C]
 """
 from __future__ import annotations
@@ -96,26 +105,37 @@ def onsager_reference():
     return json.load(open(path)) if os.path.exists(path) else None
 
 
-def run_c2(serve, accounting, workloads, budget):
+def run_c2(serve, accounting, workloads, budget, stepping="engine"):
     """Ising, D = 24, 30 steps, FP64, 64 temperatures in [1.8, 2.8] one after
     another: throughput, f against Onsager, and the finite-difference internal
-    energy against Onsager's u."""
+    energy against Onsager's u.  One solve at a time is latency-bound, so the
+    steps are host-polled by the library's progress thread (`stepping`); the
+    same scan with whole steps is timed beside it (bitwise the same ln Z)."""
     import numpy as np
+    import torch
     temps = [float(t) for t in np.linspace(1.8, 2.8, 64)]
     reqs = [workloads.Request(rid=i, arrival=0.0, model="ising", q=2, temperature=t, dmax=24, nsteps=30)
             for i, t in enumerate(temps)]
-    server = serve.Server(slots=1, budget=budget, precision="fp64", device="cuda:0")
-    server.run(reqs[:1], realtime=False)
-    import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    done = server.run(reqs, realtime=False)
-    wall = time.perf_counter() - t0
+
+    def scan(mode):
+        server = serve.Server(slots=1, budget=budget, precision="fp64", device="cuda:0", stepping=mode)
+        server.run(reqs[:1], realtime=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = server.run(reqs, realtime=False)
+        return done, time.perf_counter() - t0
+
+    done, wall = scan(stepping)
     lnz = [c.lnz_per_site for c in sorted(done, key=lambda c: c.rid)]
     u = fd_energy(temps, lnz)
     out = {"workload": "Ising J=1, D=24, 30 steps, FP64, T = linspace(1.8, 2.8, 64), one solve at a time",
-           "solves": len(done), "seconds": wall,
+           "stepping": stepping, "solves": len(done), "seconds": wall,
            "tflops": len(done) * accounting.solve_flops(2, 24, 30) / wall / 1e12}
+    if stepping != "whole":
+        done_w, wall_w = scan("whole")
+        out["seconds_whole_steps"] = wall_w
+        out["lnz_bitwise_equal_to_whole_steps"] = \
+            [c.lnz_per_site for c in sorted(done_w, key=lambda c: c.rid)] == lnz
     ref = onsager_reference()
     if ref:
         g = ref["grid"]
@@ -271,7 +291,7 @@ def run_itebd(binding, workloads):
     return out
 
 
-def run_qchain(binding, workloads):
+def run_qchain(binding, workloads, stepping="engine"):
     """HOTRG of the S = 1/2 antiferromagnetic Heisenberg chain mapped onto an
     imaginary-time network (the paper's HOTRG workload), FP64: time per
     coarse-graining step against D_b (12 steps along imaginary time,
@@ -285,21 +305,26 @@ def run_qchain(binding, workloads):
                        "time, then the infinite chain (dominant eigenvalue of the column transfer matrix), FP64"}
     k = 12
     tau = 1.0 / 2 ** k
-    rows = []
+    rows, rows_whole = [], []
     for d in (4, 8, 16, 24, 32, 48):
         s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=d, max_steps=k)
         s.coarse_grain(k, exchange=False)
         s.log_z_chain()
-        s.reset(model="qchain", bond_h=h, tau=tau, dmax=d, max_steps=k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.coarse_grain(k, exchange=False)
-        s.log_z_chain()
-        dt = time.perf_counter() - t0
-        rows.append((d, dt / k * 1e3))
+        for mode, dest in ((stepping, rows), ("whole", rows_whole)):
+            s.reset(model="qchain", bond_h=h, tau=tau, dmax=d, max_steps=k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "engine":
+                s.coarse_grain_async(k, exchange=False)    # host-polled steps, the library's thread
+            else:
+                s.coarse_grain(k, exchange=False)
+            s.log_z_chain()
+            dest.append((d, (time.perf_counter() - t0) / k * 1e3))
         s.close()
     x = np.polyfit(np.log([r[0] for r in rows[1:]]), np.log([r[1] for r in rows[1:]]), 1)[0]
+    out["stepping"] = stepping
     out["ms_per_step"] = {str(d): t for d, t in rows}
+    out["ms_per_step_whole_steps"] = {str(d): t for d, t in rows_whole}
     out["fit_exponent_d8_to_d48"] = float(x)
     # where a step goes at D_b = 32: HIP events between the stages of every
     # step (a separate timed solve, so the timing above is not perturbed)
@@ -447,16 +472,16 @@ def run_roofline(binding, accounting, precision, dmax, nsteps, temperature):
     }
 
 
-def run_c4(serve, accounting, workloads, precision, slots, budget, polled=False):
+def run_c4(serve, accounting, workloads, precision, slots, budget, stepping="whole"):
     """Served solves under Poisson arrivals (the serving workload's request
     mix), time-bounded: a rate below the knee and the overloaded 50 req/s.
     Requests without a result when the horizon ends are counted and enter
     the latency percentiles with the time they had waited by then (so those
     percentiles are lower bounds under overload)."""
-    srv = serve.Server(slots=slots, budget=budget, precision=precision, polled=polled)
+    srv = serve.Server(slots=slots, budget=budget, precision=precision, stepping=stepping)
     out = {"workload": "Poisson arrivals; Ising/Potts(q=3) uniform, T ~ U[0.5, 1.5] Tc, D in {16,24,32,48}, "
                        "20-40 steps, seeded; served with continuous batching",
-           "precision": precision, "slots": slots, "stepping": "polled" if polled else "whole", "runs": []}
+           "precision": precision, "slots": slots, "stepping": stepping, "runs": []}
     for rate, seconds, horizon in ((10.0, 15.0, 30.0), (50.0, 10.0, 20.0)):
         reqs = workloads.request_stream(rate_hz=rate, duration_s=seconds)
         offered = sum(accounting.solve_flops(r.q, r.dmax, r.nsteps) for r in reqs) / seconds / 1e12
@@ -527,8 +552,12 @@ def main(argv=None):
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--concurrency", type=int, default=4, help="solves in flight (streams)")
-    ap.add_argument("--stepping", default="whole", choices=["whole", "polled"],
-                    help="whole steps (every eigensolver pass up to the cap enqueued) or host-polled steps")
+    ap.add_argument("--stepping", default="whole", choices=["whole", "polled", "engine"],
+                    help="whole steps (every eigensolver pass up to the cap enqueued), host-polled steps "
+                         "driven by the scheduler, or by the library's progress thread")
+    ap.add_argument("--latency-stepping", default="engine", choices=["whole", "engine"],
+                    help="steps of the one-solve-at-a-time legs (C2 scan, quantum chain): whole steps or "
+                         "host-polled steps driven by the library's progress thread")
     ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
     ap.add_argument("--no-c2", dest="c2", action="store_false", help="skip the D=24 temperature scan")
     ap.add_argument("--no-c4", dest="c4", action="store_false", help="skip the served Poisson stream")
@@ -562,7 +591,7 @@ def main(argv=None):
 
     def run_batch(precision, concurrency, warm_reqs, reqs):
         server = serve.Server(slots=concurrency, budget=args.budget_gb << 30, precision=precision,
-                              device="cuda:0", timing=True, polled=args.stepping == "polled")
+                              device="cuda:0", timing=True, stepping=args.stepping)
         if warm_reqs:
             server.run(warm_reqs, realtime=False)
         torch.cuda.synchronize()
@@ -661,10 +690,10 @@ def main(argv=None):
         if prec != args.precision and args.compare and (prec != "fp64" or args.compare_fp64):
             run_leg(line, f"{prec}_comparison", comparison, prec)
     if args.c2:
-        run_leg(line, "c2", run_c2, serve, accounting, workloads, args.budget_gb << 30)
+        run_leg(line, "c2", run_c2, serve, accounting, workloads, args.budget_gb << 30, args.latency_stepping)
     if args.c4:
         run_leg(line, "c4", run_c4, serve, accounting, workloads, args.precision, 8, 160 << 30,
-                args.stepping == "polled")
+                args.stepping)
     if args.c5:
         run_leg(line, "c5", run_c5, binding, accounting)
     if args.observables:
@@ -672,7 +701,7 @@ def main(argv=None):
     if args.itebd:
         run_leg(line, "itebd", run_itebd, binding, workloads)
     if args.qchain:
-        run_leg(line, "qchain", run_qchain, binding, workloads)
+        run_leg(line, "qchain", run_qchain, binding, workloads, args.latency_stepping)
     if not args.no_cpu_baseline:
         def cpu():
             out = cpu_baseline(args.dmax, args.cpu_sample_steps, float(temps[0]))

@@ -259,6 +259,28 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps);
 int hotrg_step_begin(hotrg_solve* s, int exchange, int extra, int* pending);
 int hotrg_step_poll(hotrg_solve* s, int* state);
 
+/* The host-polled form driven by the library itself: returns at once, and
+ * a thread of the library (one per process, started by the first call)
+ * begins the handle's nsteps steps one after another with
+ * hotrg_step_begin(s, exchange, extra) and polls each with hotrg_step_poll
+ * as soon as its eigensolve's stop state arrives, so that a step's
+ * products are enqueued microseconds after its eigensolve ends and no pass
+ * after convergence is launched.  The results are bitwise those of
+ * hotrg_coarse_grain_axis(s, nsteps, exchange).  The thread spins (yielding
+ * the CPU between rounds) while any handle is in flight and sleeps
+ * otherwise.  Every other call on the handle first waits until the thread
+ * has enqueued all of its steps (hotrg_async_busy tells without waiting);
+ * hotrg_destroy waits too.  An error met by the thread (ENOMEM for a step
+ * that does not fit, EHIP) puts the handle in the failed state: the next
+ * hotrg_log_z returns it.  Errors: EINVAL (nsteps < 0, exchange not 0/1,
+ * extra < 0, a polled step pending, step cap), ESTATE. */
+int hotrg_coarse_grain_async(hotrg_solve* s, int nsteps, int exchange, int extra);
+
+/* *busy = 1 while the library's thread still has steps of the handle to
+ * enqueue (hotrg_coarse_grain_async), else 0; never waits.  The enqueued
+ * work itself completes on the handle's stream.  Errors: EINVAL. */
+int hotrg_async_busy(hotrg_solve* s, int* busy);
+
 /* Synchronises the stream and returns ln Z / N of the torus reached so far:
  *   ln Z/N = ln c_0 + sum_n ln(c_n) / 2^n + ln(sum_{x,y} T[x,x,y,y]) / 2^n_steps
  * lnz_per_site receives that value, log2_sites (may be NULL) the number of

@@ -36,6 +36,7 @@ OBSERVABLES = {"m": OBS_MAGNETIZATION, "e": OBS_BOND_ENERGY}
 EXPORTS = [
     "hotrg_workspace_bytes", "hotrg_init_tensor", "hotrg_reset", "hotrg_coarse_grain",
     "hotrg_coarse_grain_batch", "hotrg_coarse_grain_axis", "hotrg_step_begin", "hotrg_step_poll",
+    "hotrg_coarse_grain_async", "hotrg_async_busy",
     "hotrg_log_z", "hotrg_log_z_chain",
     "hotrg_step_info", "hotrg_step_sides", "hotrg_observables", "hotrg_eig_info", "hotrg_set_eig_limits",
     "hotrg_copy_tensor", "hotrg_copy_environment", "hotrg_copy_isometry", "hotrg_set_timing", "hotrg_stage_times", "hotrg_step_stage_times",
@@ -101,6 +102,8 @@ def load() -> ctypes.CDLL:
     lib.hotrg_coarse_grain_axis.argtypes = [c_void_p, c_int, c_int]
     lib.hotrg_step_begin.argtypes = [c_void_p, c_int, c_int, P(c_int)]
     lib.hotrg_step_poll.argtypes = [c_void_p, P(c_int)]
+    lib.hotrg_coarse_grain_async.argtypes = [c_void_p, c_int, c_int, c_int]
+    lib.hotrg_async_busy.argtypes = [c_void_p, P(c_int)]
     lib.hotrg_log_z_chain.argtypes = [c_void_p, P(c_double)]
     lib.hotrg_log_z.argtypes = [c_void_p, P(c_double), P(c_int)]
     lib.hotrg_step_info.argtypes = [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]
@@ -291,6 +294,20 @@ class Solve:
         state = ctypes.c_int()
         _check(self._lib.hotrg_step_poll(self._h, ctypes.byref(state)), "hotrg_step_poll")
         return state.value
+
+    def coarse_grain_async(self, nsteps: int, exchange: bool = True, extra: int = 0) -> "Solve":
+        """Hand nsteps host-polled steps to the library's progress thread
+        (hotrg_coarse_grain_async); returns at once."""
+        _check(self._lib.hotrg_coarse_grain_async(self._h, int(nsteps), 1 if exchange else 0, int(extra)),
+               "hotrg_coarse_grain_async")
+        return self
+
+    def async_busy(self) -> bool:
+        """True while the progress thread still has steps of this solve to
+        enqueue (hotrg_async_busy); never waits."""
+        busy = ctypes.c_int()
+        _check(self._lib.hotrg_async_busy(self._h, ctypes.byref(busy)), "hotrg_async_busy")
+        return bool(busy.value)
 
     def log_z_chain(self) -> float:
         """ln Z per tensor with x infinite and y closed (hotrg_log_z_chain)."""

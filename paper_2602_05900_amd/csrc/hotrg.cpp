@@ -29,7 +29,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/hotrg.h"
@@ -473,6 +477,12 @@ struct hotrg_solve {
     int pend_next = 0;              // next subspace pass to enqueue
     int pend_par = 0;
     int hist[2] = {0, 0};           // passes the last polled eigensolve of each parity used
+    // steps driven by the library's progress thread (hotrg_coarse_grain_async);
+    // while async_active is set only that thread touches the handle
+    std::atomic<int> async_active{0};
+    int async_left = 0;
+    bool async_exchange = true;
+    int async_extra = 0;
     bool timing = false;
     int timed_from = 0;  // first step recorded with events
     std::vector<hipEvent_t> ev;
@@ -844,6 +854,169 @@ int upload_initial(hotrg_solve* s, const hotrg_params* p) {
     return HOTRG_OK;
 }
 
+int begin_step(hotrg_solve* s, int exchange, int extra, int* pending) {
+    if (pending) *pending = 0;
+    if (!s || (exchange != 0 && exchange != 1) || extra < 0 || s->pend) return HOTRG_EINVAL;
+    if (s->host_status) return HOTRG_ESTATE;
+    if (s->steps + 1 > step_cap(&s->p)) return HOTRG_EINVAL;
+    // dense eigensolves and two-sided steps are enqueued whole
+    if (s->dx * s->dx <= kEigPMax || s->p.two_sided) return enqueue_step(s, exchange != 0);
+    if (!s->mail) {
+        void* h = nullptr;
+        if (hipHostMalloc(&h, sizeof(EigMail), hipHostMallocCoherent) != hipSuccess) return HOTRG_EHIP;
+        s->mail = static_cast<EigMail*>(h);
+        memset(s->mail, 0, sizeof(EigMail));
+        s->mail_seq = 0;
+    }
+    const int par = exchange ? (s->steps & 1) : 0;
+    int first = (s->hist[par] > 0 ? s->hist[par] : kPollFirst) + std::min(extra, HOTRG_EIG_MAX_PASSES);
+    first = std::min((first + 1) / 2 * 2, s->eig_maxit);
+    StepPart part;
+    part.eig.last = first;
+    part.eig.end = false;
+    part.rest = false;
+    int rc = enqueue_step(s, exchange != 0, part);
+    if (rc) return rc;
+    if ((rc = mail_copy(s))) return rc;
+    s->pend = true;
+    s->pend_exchange = exchange != 0;
+    s->pend_next = first;
+    s->pend_par = par;
+    if (pending) *pending = 1;
+    return HOTRG_OK;
+}
+
+int poll_step(hotrg_solve* s, int* state) {
+    if (!s || !state) return HOTRG_EINVAL;
+    *state = HOTRG_POLL_IDLE;
+    if (!s->pend) return HOTRG_OK;
+    if (s->host_status) return HOTRG_ESTATE;
+    const unsigned long long word = __atomic_load_n(&s->mail->word, __ATOMIC_ACQUIRE);
+    if ((int)(word >> 32) != s->mail_seq) {
+        *state = HOTRG_POLL_RUNNING;
+        return HOTRG_OK;
+    }
+    struct {
+        int done, iters;
+    } c{(int)(word & 1u), (int)((word >> 1) & 0x7fffffffu)};
+    StepPart part;
+    part.env = false;
+    part.eig.start = false;
+    part.eig.first = s->pend_next;
+    int rc;
+    if (c.done || s->pend_next >= s->eig_maxit) {
+        // converged, stagnated or at the pass cap: the rest of the step
+        part.eig.last = s->pend_next;
+        s->hist[s->pend_par] = c.iters > 0 ? c.iters : s->pend_next;
+        s->pend = false;
+        if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
+        *state = HOTRG_POLL_STEPPED;
+        return HOTRG_OK;
+    }
+    part.eig.last = std::min(s->pend_next + kPollChunk, s->eig_maxit);
+    part.eig.end = false;
+    part.rest = false;
+    if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
+    if ((rc = mail_copy(s))) return rc;
+    s->pend_next = part.eig.last;
+    *state = HOTRG_POLL_PASSES;
+    return HOTRG_OK;
+}
+
+// ---------------------------------------------------------------- progress thread
+//
+// Host-polled steps without a host scheduling loop: the library's own thread
+// keeps every handle given to hotrg_coarse_grain_async moving, enqueueing its
+// next group of passes or the rest of its step as soon as the stop state of
+// its eigensolve arrives (a read of host memory), and beginning its next
+// step right after.  It spins (yielding) while any handle is in flight and
+// sleeps on a condition variable otherwise.  The thread and its registry
+// live until the process ends.
+
+// One round for one handle; true when it has nothing left to enqueue.
+bool advance_async(hotrg_solve* s, bool* progress) {
+    if (s->host_status) return true;
+    if (s->pend) {
+        int st = HOTRG_POLL_IDLE;
+        const int rc = poll_step(s, &st);
+        if (rc) {
+            if (!s->host_status) s->host_status = rc;
+            return true;
+        }
+        if (st == HOTRG_POLL_RUNNING) return false;
+        *progress = true;
+        if (st == HOTRG_POLL_PASSES) return false;
+    }
+    while (s->async_left > 0) {
+        int pending = 0;
+        s->async_left -= 1;
+        const int rc = begin_step(s, s->async_exchange ? 1 : 0, s->async_extra, &pending);
+        *progress = true;
+        if (rc) {
+            if (!s->host_status) s->host_status = rc;
+            s->async_left = 0;
+            return true;
+        }
+        if (pending) return false;
+    }
+    return true;
+}
+
+class Engine {
+public:
+    static Engine& get() {
+        static Engine* e = new Engine();   // never destroyed: its thread may outlive static destructors
+        return *e;
+    }
+    void add(hotrg_solve* s) {
+        std::lock_guard<std::mutex> lock(mu_);
+        incoming_.push_back(s);
+        has_incoming_.store(true, std::memory_order_release);
+        if (!started_) {
+            std::thread(&Engine::run, this).detach();
+            started_ = true;
+        }
+        cv_.notify_one();
+    }
+
+private:
+    void run() {
+        std::vector<hotrg_solve*> mine;
+        for (;;) {
+            if (mine.empty() || has_incoming_.load(std::memory_order_acquire)) {
+                std::unique_lock<std::mutex> lock(mu_);
+                if (mine.empty()) cv_.wait(lock, [&] { return !incoming_.empty(); });
+                mine.insert(mine.end(), incoming_.begin(), incoming_.end());
+                incoming_.clear();
+                has_incoming_.store(false, std::memory_order_release);
+            }
+            bool progress = false;
+            for (size_t i = 0; i < mine.size();) {
+                hotrg_solve* s = mine[i];
+                if (advance_async(s, &progress)) {
+                    mine[i] = mine.back();
+                    mine.pop_back();
+                    s->async_active.store(0, std::memory_order_release);
+                } else {
+                    ++i;
+                }
+            }
+            if (!progress) std::this_thread::yield();
+        }
+    }
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::vector<hotrg_solve*> incoming_;
+    std::atomic<bool> has_incoming_{false};
+    bool started_ = false;
+};
+
+// Every entry point that takes a handle first waits until the progress
+// thread has released it (all of its asynchronous steps enqueued).
+void quiesce(hotrg_solve* s) {
+    while (s->async_active.load(std::memory_order_acquire)) std::this_thread::yield();
+}
+
 int latched(const DevState& d) { return d.status; }
 
 }  // namespace
@@ -943,6 +1116,7 @@ int hotrg_init_tensor(const hotrg_params* p, void* workspace, size_t ws_bytes, v
 }
 
 int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
+    if (s) quiesce(s);
     if (!s || !valid_params(p) || !eig_feasible(p)) return HOTRG_EINVAL;
     if (hipStreamSynchronize(s->stream) != hipSuccess) return HOTRG_EHIP;
     const Layout L = plan(p);
@@ -961,6 +1135,7 @@ int hotrg_reset(hotrg_solve* s, const hotrg_params* p) {
 }
 
 int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
+    if (s) quiesce(s);
     if (!s || nsteps < 0 || s->pend) return HOTRG_EINVAL;
     if (s->host_status) return HOTRG_ESTATE;
     if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
@@ -972,6 +1147,7 @@ int hotrg_coarse_grain(hotrg_solve* s, int nsteps) {
 }
 
 int hotrg_coarse_grain_axis(hotrg_solve* s, int nsteps, int exchange) {
+    if (s) quiesce(s);
     if (!s || nsteps < 0 || (exchange != 0 && exchange != 1) || s->pend) return HOTRG_EINVAL;
     if (s->host_status) return HOTRG_ESTATE;
     if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
@@ -983,6 +1159,7 @@ int hotrg_coarse_grain_axis(hotrg_solve* s, int nsteps, int exchange) {
 }
 
 int hotrg_log_z_chain(hotrg_solve* s, double* lnz_per_tensor) {
+    if (s) quiesce(s);
     if (!s || !lnz_per_tensor) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     if (s->dx > 96) return HOTRG_EINVAL;
@@ -1002,6 +1179,7 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps) 
     // k times needs room for k * nsteps more steps
     for (int i = 0; i < count; ++i) {
         hotrg_solve* s = solves[i];
+        if (s) quiesce(s);
         if (!s || s->pend) return HOTRG_EINVAL;
         int times = 0;
         for (int j = 0; j < count; ++j) times += solves[j] == s;
@@ -1019,74 +1197,42 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps) 
 
 int hotrg_step_begin(hotrg_solve* s, int exchange, int extra, int* pending) {
     if (pending) *pending = 0;
-    if (!s || (exchange != 0 && exchange != 1) || extra < 0 || s->pend) return HOTRG_EINVAL;
-    if (s->host_status) return HOTRG_ESTATE;
-    if (s->steps + 1 > step_cap(&s->p)) return HOTRG_EINVAL;
-    // dense eigensolves and two-sided steps are enqueued whole
-    if (s->dx * s->dx <= kEigPMax || s->p.two_sided) return enqueue_step(s, exchange != 0);
-    if (!s->mail) {
-        void* h = nullptr;
-        if (hipHostMalloc(&h, sizeof(EigMail), hipHostMallocCoherent) != hipSuccess) return HOTRG_EHIP;
-        s->mail = static_cast<EigMail*>(h);
-        memset(s->mail, 0, sizeof(EigMail));
-        s->mail_seq = 0;
-    }
-    const int par = exchange ? (s->steps & 1) : 0;
-    int first = (s->hist[par] > 0 ? s->hist[par] : kPollFirst) + std::min(extra, HOTRG_EIG_MAX_PASSES);
-    first = std::min((first + 1) / 2 * 2, s->eig_maxit);
-    StepPart part;
-    part.eig.last = first;
-    part.eig.end = false;
-    part.rest = false;
-    int rc = enqueue_step(s, exchange != 0, part);
-    if (rc) return rc;
-    if ((rc = mail_copy(s))) return rc;
-    s->pend = true;
-    s->pend_exchange = exchange != 0;
-    s->pend_next = first;
-    s->pend_par = par;
-    if (pending) *pending = 1;
-    return HOTRG_OK;
+    if (!s) return HOTRG_EINVAL;
+    quiesce(s);
+    return begin_step(s, exchange, extra, pending);
 }
 
 int hotrg_step_poll(hotrg_solve* s, int* state) {
+    if (state) *state = HOTRG_POLL_IDLE;
     if (!s || !state) return HOTRG_EINVAL;
-    *state = HOTRG_POLL_IDLE;
-    if (!s->pend) return HOTRG_OK;
+    quiesce(s);
+    return poll_step(s, state);
+}
+
+int hotrg_coarse_grain_async(hotrg_solve* s, int nsteps, int exchange, int extra) {
+    if (!s || nsteps < 0 || (exchange != 0 && exchange != 1) || extra < 0) return HOTRG_EINVAL;
+    quiesce(s);
+    if (s->pend) return HOTRG_EINVAL;
     if (s->host_status) return HOTRG_ESTATE;
-    const unsigned long long word = __atomic_load_n(&s->mail->word, __ATOMIC_ACQUIRE);
-    if ((int)(word >> 32) != s->mail_seq) {
-        *state = HOTRG_POLL_RUNNING;
-        return HOTRG_OK;
-    }
-    struct {
-        int done, iters;
-    } c{(int)(word & 1u), (int)((word >> 1) & 0x7fffffffu)};
-    StepPart part;
-    part.env = false;
-    part.eig.start = false;
-    part.eig.first = s->pend_next;
-    int rc;
-    if (c.done || s->pend_next >= s->eig_maxit) {
-        // converged, stagnated or at the pass cap: the rest of the step
-        part.eig.last = s->pend_next;
-        s->hist[s->pend_par] = c.iters > 0 ? c.iters : s->pend_next;
-        s->pend = false;
-        if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
-        *state = HOTRG_POLL_STEPPED;
-        return HOTRG_OK;
-    }
-    part.eig.last = std::min(s->pend_next + kPollChunk, s->eig_maxit);
-    part.eig.end = false;
-    part.rest = false;
-    if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
-    if ((rc = mail_copy(s))) return rc;
-    s->pend_next = part.eig.last;
-    *state = HOTRG_POLL_PASSES;
+    if (s->steps + nsteps > step_cap(&s->p)) return HOTRG_EINVAL;
+    if (nsteps == 0) return HOTRG_OK;
+    s->async_left = nsteps;
+    s->async_exchange = exchange != 0;
+    s->async_extra = extra;
+    s->async_active.store(1, std::memory_order_release);
+    Engine::get().add(s);
+    return HOTRG_OK;
+}
+
+int hotrg_async_busy(hotrg_solve* s, int* busy) {
+    if (busy) *busy = 0;
+    if (!s || !busy) return HOTRG_EINVAL;
+    *busy = s->async_active.load(std::memory_order_acquire);
     return HOTRG_OK;
 }
 
 int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites) {
+    if (s) quiesce(s);
     if (!s || !lnz_per_site) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     HIP_TRY(s, launch_trace(s->T(), s->dx, s->dy, s->state(), s->stream));
@@ -1101,6 +1247,7 @@ int hotrg_log_z(hotrg_solve* s, double* lnz_per_site, int* log2_sites) {
 }
 
 int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err, double* cut_gap) {
+    if (s) quiesce(s);
     if (!s || n < 0 || n > s->steps) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     DevState d;
@@ -1114,6 +1261,7 @@ int hotrg_step_info(hotrg_solve* s, int n, double* c_n, double* trunc_err, doubl
 }
 
 int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* residual, int* stop) {
+    if (s) quiesce(s);
     if (!s || n < 1 || n > s->steps) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     DevState d;
@@ -1128,6 +1276,7 @@ int hotrg_eig_info(hotrg_solve* s, int n, int* iterations, int* sweeps, double* 
 }
 
 int hotrg_set_eig_limits(hotrg_solve* s, int max_passes, double fail_residual) {
+    if (s) quiesce(s);
     if (!s || max_passes < 1 || max_passes > HOTRG_EIG_MAX_PASSES) return HOTRG_EINVAL;
     if (!(fail_residual > 0.0) || !isfinite(fail_residual)) return HOTRG_EINVAL;
     s->eig_maxit = max_passes;
@@ -1136,6 +1285,7 @@ int hotrg_set_eig_limits(hotrg_solve* s, int max_passes, double fail_residual) {
 }
 
 int hotrg_step_sides(hotrg_solve* s, int n, double* eps_left, double* eps_right, int* side) {
+    if (s) quiesce(s);
     if (!s || n < 1 || n > s->steps) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     DevState d;
@@ -1149,6 +1299,7 @@ int hotrg_step_sides(hotrg_solve* s, int n, double* eps_left, double* eps_right,
 }
 
 int hotrg_observables(hotrg_solve* s, double values[2]) {
+    if (s) quiesce(s);
     if (!s || !values) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     HIP_TRY(s, launch_trace(s->T(), s->dx, s->dy, s->state(), s->stream));
@@ -1165,6 +1316,7 @@ int hotrg_observables(hotrg_solve* s, double values[2]) {
 }
 
 int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]) {
+    if (s) quiesce(s);
     if (!s || !dims) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     dims[0] = s->dx;
@@ -1181,6 +1333,7 @@ int hotrg_copy_tensor(hotrg_solve* s, double* host, size_t capacity, int dims[2]
 }
 
 int hotrg_copy_environment(hotrg_solve* s, double* host, size_t capacity, int* n) {
+    if (s) quiesce(s);
     if (!s || !n) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     *n = s->last_n;
@@ -1196,6 +1349,7 @@ int hotrg_copy_environment(hotrg_solve* s, double* host, size_t capacity, int* n
 }
 
 int hotrg_copy_isometry(hotrg_solve* s, double* host, size_t capacity, int dims[2]) {
+    if (s) quiesce(s);
     if (!s || !dims) return HOTRG_EINVAL;
     if (s->host_status) return s->host_status;
     const int n = s->last_n, dp = s->last_dp;
@@ -1240,6 +1394,7 @@ int hotrg_copy_isometry(hotrg_solve* s, double* host, size_t capacity, int dims[
 }
 
 int hotrg_set_timing(hotrg_solve* s, int enable) {
+    if (s) quiesce(s);
     if (!s) return HOTRG_EINVAL;
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
@@ -1262,6 +1417,7 @@ static float elapsed(hotrg_solve* s, int step, int a, int b) {
 }
 
 int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed) {
+    if (s) quiesce(s);
     if (!s || !ms) return HOTRG_EINVAL;
     for (int i = 0; i < HOTRG_NUM_STAGES; ++i) ms[i] = 0.0;
     const int nt = s->timing ? s->steps - s->timed_from : 0;
@@ -1282,6 +1438,7 @@ int hotrg_stage_times(hotrg_solve* s, double* ms, int* steps_timed) {
 }
 
 int hotrg_step_stage_times(hotrg_solve* s, int k, double* ms, int dims[3]) {
+    if (s) quiesce(s);
     if (!s || !ms || !s->timing || k < 0 || k >= s->steps - s->timed_from || (size_t)k >= s->timed_dims.size())
         return HOTRG_EINVAL;
     HIP_TRY(s, hipStreamSynchronize(s->stream));
@@ -1303,6 +1460,7 @@ int hotrg_step_stage_times(hotrg_solve* s, int k, double* ms, int dims[3]) {
 }
 
 int hotrg_gemm_y_time(hotrg_solve* s, double* ms, int* launches) {
+    if (s) quiesce(s);
     if (!s || !ms) return HOTRG_EINVAL;
     double st[HOTRG_NUM_STAGES];
     int nt = 0;
@@ -1315,6 +1473,7 @@ int hotrg_gemm_y_time(hotrg_solve* s, double* ms, int* launches) {
 
 void hotrg_destroy(hotrg_solve* s) {
     if (!s) return;
+    quiesce(s);
     (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->mail) (void)hipHostFree(s->mail);

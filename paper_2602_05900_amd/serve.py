@@ -76,21 +76,28 @@ class Server:
                 device (keeps every stream busy without flooding the host)
     precision   contraction precision of every solve
     timing      record per-stage HIP events of every solve (hotrg_stage_times)
-    polled      advance solves by host-polled steps (hotrg_step_begin /
-                hotrg_step_poll): the scheduler enqueues a step's products
-                once the host has seen its eigensolve converge, so no pass
-                after convergence is enqueued; otherwise whole steps
-                (hotrg_coarse_grain_batch) with every pass up to the cap
+    stepping    "whole": whole steps (hotrg_coarse_grain_batch), every
+                eigensolver pass up to the cap enqueued; "polled": host-
+                polled steps (hotrg_step_begin / hotrg_step_poll) driven by
+                this loop, a step's products enqueued once the host has seen
+                its eigensolve stop, so no pass after convergence is
+                enqueued; "engine": the same steps driven by the library's
+                own progress thread (hotrg_coarse_grain_async), this loop
+                only admitting and completing solves
     poll_extra  passes beyond a solve's history in a polled step's first group
     idle_sleep  seconds the scheduling loop sleeps when a round enqueued nothing
     """
 
+    STEPPINGS = ("whole", "polled", "engine")
+
     def __init__(self, slots: int = 8, budget: int = 64 << 30, depth: int = 2,
                  precision: str = "fp64", device: str = "cuda:0", timing: bool = False,
-                 polled: bool = False, poll_extra: int = 0, idle_sleep: float = 2e-4):
+                 stepping: str = "whole", poll_extra: int = 0, idle_sleep: float = 2e-4):
+        if stepping not in self.STEPPINGS:
+            raise ValueError(f"stepping must be one of {self.STEPPINGS}")
         binding.load()
         self.timing = timing
-        self.polled = polled
+        self.stepping = stepping
         self.poll_extra = poll_extra
         self.idle_sleep = idle_sleep
         self.device = torch.device(device)
@@ -140,6 +147,10 @@ class Server:
                 solve.set_timing(True)
             a = _Active(req=req, solve=solve, stream=stream, workspace=ws, footprint=fp, admitted=self._now(),
                         slot=si)
+            if self.stepping == "engine":
+                solve.coarse_grain_async(req.nsteps, extra=self.poll_extra)
+                a.enqueued = req.nsteps
+                a.pending = True
             self.active.append(a)
 
     def _stepped(self, a: _Active):
@@ -172,11 +183,24 @@ class Server:
                 progressed = True
         return progressed
 
+    def _advance_engine(self) -> bool:
+        """A solve whose steps the progress thread has all enqueued gets the
+        event its completion waits for."""
+        progressed = False
+        for a in self.active:
+            if a.pending and not a.solve.async_busy():
+                a.pending = False
+                self._stepped(a)
+                progressed = True
+        return progressed
+
     def _advance(self) -> bool:
         """Enqueue at most one step per active solve, as one grouped call over
         the solves that have room; returns True if any step was enqueued."""
-        if self.polled:
+        if self.stepping == "polled":
             return self._advance_polled()
+        if self.stepping == "engine":
+            return self._advance_engine()
         ready = []
         for a in self.active:
             while a.events and a.events[0].query():

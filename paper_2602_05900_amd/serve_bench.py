@@ -30,13 +30,13 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=int, default=160)
     ap.add_argument("--seed", type=int, default=None)
-    ap.add_argument("--stepping", default="whole", choices=["whole", "polled"])
+    ap.add_argument("--stepping", default="whole", choices=["whole", "polled", "engine"])
     args = ap.parse_args()
 
     import torch
     from . import accounting, serve, workloads
     srv = serve.Server(slots=args.slots, budget=args.budget_gb << 30, precision=args.precision,
-                       polled=args.stepping == "polled")
+                       stepping=args.stepping)
     rates = [float(r) for r in args.sweep.split(",")] if args.sweep else [args.rate]
     for rate in rates:
         serve_stream(args, srv, rate, accounting, serve, workloads, torch)

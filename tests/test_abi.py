@@ -178,6 +178,8 @@ def test_host_error_paths_without_device(lib):
     st = ctypes.c_int(-1)
     assert lib.hotrg_step_begin(None, 1, 0, ctypes.byref(st)) == binding.EINVAL and st.value == 0
     assert lib.hotrg_step_poll(None, ctypes.byref(st)) == binding.EINVAL
+    assert lib.hotrg_coarse_grain_async(None, 1, 1, 0) == binding.EINVAL
+    assert lib.hotrg_async_busy(None, ctypes.byref(st)) == binding.EINVAL
     lib.hotrg_destroy(None)
     assert lib.hotrg_strerror(binding.ENOMEM) == b"workspace too small"
     assert lib.hotrg_gemm_scratch_bytes(binding.FP64, 10, 10, 10) == 0

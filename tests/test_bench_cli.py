@@ -52,7 +52,7 @@ def _fake_server_class(calls):
 
     class FakeServer:
         def __init__(self, slots=8, budget=0, depth=2, precision="fp64", device="cuda:0", timing=False,
-                     polled=False):
+                     stepping="whole"):
             self.precision = precision
             self.timing = timing
             self.peak_in_use = self.in_use = 0

@@ -170,7 +170,89 @@ def test_polled_server_results_identical_alone_and_in_the_mix(gpu_lib):
         s.coarse_grain(r.nsteps)
         alone[r.rid] = s.log_z()
         s.close()
-    srv = serve.Server(slots=4, budget=32 << 30, precision="fp16x3", polled=True)
+    srv = serve.Server(slots=4, budget=32 << 30, precision="fp16x3", stepping="polled")
+    done = srv.run(reqs, realtime=False)
+    assert len(done) == len(reqs)
+    for c in done:
+        assert c.lnz_per_site == alone[c.rid], (c.rid, c.lnz_per_site, alone[c.rid])
+    assert srv.in_use == 0
+
+
+@pytest.mark.parametrize("model,q,t,d,prec,n", [
+    ("ising", 2, 2.25, 24, "fp64", 14),
+    ("ising", 2, 2.269185314213022, 48, "fp16x3", 9),
+    ("potts", 3, 0.9, 32, "bf16x6", 12),
+])
+def test_engine_steps_equal_whole_steps(gpu_lib, model, q, t, d, prec, n):
+    """hotrg_coarse_grain_async: the library's progress thread drives the
+    host-polled steps of several handles at once (one stream each); every
+    handle ends bitwise where hotrg_coarse_grain takes it, with the same c_n
+    and eigensolver records, and log_z right after the call waits for the
+    thread."""
+    import torch
+    from paper_2602_05900_amd import binding
+    temps = [t, t * 1.03, t * 0.97]
+    refs = []
+    for tt in temps:
+        r = binding.Solve(model=model, q=q, temperature=tt, dmax=d, precision=prec, max_steps=n)
+        r.coarse_grain(n)
+        refs.append(r)
+    solves = [binding.Solve(model=model, q=q, temperature=tt, dmax=d, precision=prec, max_steps=n,
+                            stream=torch.cuda.Stream()) for tt in temps]
+    for s in solves:
+        s.coarse_grain_async(n)
+    assert solves[0].log_z() == refs[0].log_z()
+    for s, r in zip(solves, refs):
+        assert s.log_z() == r.log_z()
+        assert not s.async_busy()
+        for k in range(1, n + 1):
+            assert s.step_info(k) == r.step_info(k), k
+            assert s.eig_info(k) == r.eig_info(k), k
+    for s in solves + refs:
+        s.close()
+
+
+def test_engine_quantum_chain_and_continuation(gpu_lib):
+    """Steps without the axis exchange, and an asynchronous run continued
+    by whole steps and by a second asynchronous run."""
+    from paper_2602_05900_amd import binding, workloads
+    h = workloads.heisenberg_bond()
+    tau, k = 2.0 ** -8, 8
+    ref = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=24, max_steps=k)
+    ref.coarse_grain(k, exchange=False)
+    s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=24, max_steps=k)
+    s.coarse_grain_async(k, exchange=False)
+    assert s.log_z_chain() == ref.log_z_chain()
+    s.close()
+    ref.close()
+    ref = binding.Solve(model="ising", q=2, temperature=2.3, dmax=24, max_steps=16)
+    ref.coarse_grain(16)
+    s = binding.Solve(model="ising", q=2, temperature=2.3, dmax=24, max_steps=16)
+    s.coarse_grain_async(7)
+    s.coarse_grain(2)                     # waits for the thread, then whole steps
+    s.coarse_grain_async(7, extra=2)
+    with pytest.raises(binding.HotrgError) as e:
+        s.coarse_grain_async(1)           # would exceed max_steps
+    assert e.value.status == binding.EINVAL
+    assert s.log_z() == ref.log_z()
+    s.close()
+    ref.close()
+
+
+def test_engine_server_results_identical_alone_and_in_the_mix(gpu_lib):
+    from paper_2602_05900_amd import binding, serve, workloads
+    reqs = [workloads.Request(rid=i, arrival=0.001 * i, model=m, q=q, temperature=t, dmax=d, nsteps=n)
+            for i, (m, q, t, d, n) in enumerate([
+                ("ising", 2, 2.1, 16, 20), ("potts", 3, 1.05, 16, 24), ("ising", 2, 2.4, 24, 22),
+                ("potts", 3, 0.8, 24, 20), ("ising", 2, 1.3, 32, 21), ("ising", 2, 2.27, 48, 20)])]
+    alone = {}
+    for r in reqs:
+        s = binding.Solve(model=r.model, q=r.q, temperature=r.temperature, dmax=r.dmax, max_steps=r.nsteps,
+                          precision="fp16x3")
+        s.coarse_grain(r.nsteps)
+        alone[r.rid] = s.log_z()
+        s.close()
+    srv = serve.Server(slots=4, budget=32 << 30, precision="fp16x3", stepping="engine")
     done = srv.run(reqs, realtime=False)
     assert len(done) == len(reqs)
     for c in done:

@@ -50,6 +50,14 @@ class FakeSolve:
         self.steps += 1
         return binding.POLL_STEPPED
 
+    def coarse_grain_async(self, n, exchange=True, extra=0):
+        self.steps += n
+        self.busy = 2
+
+    def async_busy(self):
+        self.busy = max(self.busy - 1, 0)
+        return self.busy > 0
+
     def log_z(self):
         return 1.0 + self.kw["temperature"] * 1e-3 + self.steps * 1e-6
 
@@ -106,13 +114,26 @@ def test_polled_server_takes_every_step(fake_device):
     """The host-polled form: every solve ends with exactly its step count,
     whole steps and polled steps mixed, and nothing is left pending."""
     reqs = workloads.request_stream(rate_hz=200.0, duration_s=0.3, seed=5)
-    srv = serve.Server(slots=4, budget=1 << 40, precision="fp64", device="cpu", polled=True)
+    srv = serve.Server(slots=4, budget=1 << 40, precision="fp64", device="cpu", stepping="polled")
     done = srv.run(reqs, realtime=False)
     assert len(done) == len(reqs)
     for c in done:
         r = reqs[c.rid]
         assert abs(c.lnz_per_site - (1.0 + r.temperature * 1e-3 + r.nsteps * 1e-6)) < 1e-12
     assert srv.in_use == 0 and FakeSolve.live == 0
+
+
+def test_engine_server_takes_every_step(fake_device):
+    reqs = workloads.request_stream(rate_hz=200.0, duration_s=0.3, seed=6)
+    srv = serve.Server(slots=4, budget=1 << 40, precision="fp64", device="cpu", stepping="engine")
+    done = srv.run(reqs, realtime=False)
+    assert len(done) == len(reqs)
+    for c in done:
+        r = reqs[c.rid]
+        assert abs(c.lnz_per_site - (1.0 + r.temperature * 1e-3 + r.nsteps * 1e-6)) < 1e-12
+    assert srv.in_use == 0 and FakeSolve.live == 0
+    with pytest.raises(ValueError):
+        serve.Server(slots=1, device="cpu", stepping="sometimes")
 
 
 def test_request_larger_than_budget_is_rejected(fake_device):
