@@ -273,7 +273,8 @@ int hotrg_step_poll(hotrg_solve* s, int* state);
  * hotrg_destroy waits too.  An error met by the thread (ENOMEM for a step
  * that does not fit, EHIP) puts the handle in the failed state: the next
  * hotrg_log_z returns it.  Errors: EINVAL (nsteps < 0, exchange not 0/1,
- * extra < 0, a polled step pending, step cap), ESTATE. */
+ * extra < 0, a polled step pending, step cap), ESTATE, EHIP (the thread
+ * could not be started; nothing is enqueued). */
 int hotrg_coarse_grain_async(hotrg_solve* s, int nsteps, int exchange, int extra);
 
 /* *busy = 1 while the library's thread still has steps of the handle to

@@ -64,20 +64,29 @@ def run_itebd(chains: int, chi: int, updates: int, tau: float = 0.01) -> dict:
             "energy_mean": float(e.mean()), "energy_minus_bethe_max": float(e.max() - (0.25 - math.log(2.0)))}
 
 
-def run_qchain(dmax: int, steps: int, temperature: float = 1.0) -> dict:
+def run_qchain(dmax: int, steps: int, temperature: float = 1.0, stepping: str = "whole") -> dict:
+    """stepping: "whole" (hotrg_coarse_grain_axis) or "engine" (host-polled
+    steps driven by the library's progress thread, hotrg_coarse_grain_async)."""
     h = workloads.heisenberg_bond()
     tau = (1.0 / temperature) / 2 ** steps
+
+    def advance(s):
+        if stepping == "engine":
+            s.coarse_grain_async(steps, exchange=False)
+        else:
+            s.coarse_grain(steps, exchange=False)
+
     s = binding.Solve(model="qchain", bond_h=h, tau=tau, dmax=dmax, max_steps=steps)
-    s.coarse_grain(steps, exchange=False)      # untimed warm-up solve
+    advance(s)                                 # untimed warm-up solve
     s.log_z_chain()
     s.reset(model="qchain", bond_h=h, tau=tau, dmax=dmax, max_steps=steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.coarse_grain(steps, exchange=False)
+    advance(s)
     f = -s.log_z_chain() / (2.0 * tau)
     dt = time.perf_counter() - t0
     s.close()
-    return {"dmax": dmax, "steps": steps, "temperature": temperature, "seconds": dt,
+    return {"dmax": dmax, "steps": steps, "temperature": temperature, "stepping": stepping, "seconds": dt,
             "ms_per_step": dt / steps * 1e3, "free_energy": f}
 
 
@@ -89,8 +98,11 @@ def main():
     ap.add_argument("--updates", type=int, default=2000)
     ap.add_argument("--dmax", type=int, default=32)
     ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--stepping", choices=("whole", "engine"), default="whole",
+                    help="quantum chain: whole steps or host-polled steps driven by the library's thread")
     a = ap.parse_args()
-    out = run_itebd(a.chains, a.chi, a.updates) if a.what == "itebd" else run_qchain(a.dmax, a.steps)
+    out = (run_itebd(a.chains, a.chi, a.updates) if a.what == "itebd"
+           else run_qchain(a.dmax, a.steps, stepping=a.stepping))
     print(json.dumps(out), flush=True)
 
 

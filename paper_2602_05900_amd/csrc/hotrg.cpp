@@ -968,14 +968,16 @@ public:
         static Engine* e = new Engine();   // never destroyed: its thread may outlive static destructors
         return *e;
     }
+    // Throws if the thread cannot be started or the registry cannot grow;
+    // the handle is then not registered.
     void add(hotrg_solve* s) {
         std::lock_guard<std::mutex> lock(mu_);
-        incoming_.push_back(s);
-        has_incoming_.store(true, std::memory_order_release);
         if (!started_) {
             std::thread(&Engine::run, this).detach();
             started_ = true;
         }
+        incoming_.push_back(s);
+        has_incoming_.store(true, std::memory_order_release);
         cv_.notify_one();
     }
 
@@ -993,7 +995,14 @@ private:
             bool progress = false;
             for (size_t i = 0; i < mine.size();) {
                 hotrg_solve* s = mine[i];
-                if (advance_async(s, &progress)) {
+                bool finished;
+                try {
+                    finished = advance_async(s, &progress);
+                } catch (...) {   // host allocation failure: the handle fails, the thread goes on
+                    if (!s->host_status) s->host_status = HOTRG_EHIP;
+                    finished = true;
+                }
+                if (finished) {
                     mine[i] = mine.back();
                     mine.pop_back();
                     s->async_active.store(0, std::memory_order_release);
@@ -1220,7 +1229,13 @@ int hotrg_coarse_grain_async(hotrg_solve* s, int nsteps, int exchange, int extra
     s->async_exchange = exchange != 0;
     s->async_extra = extra;
     s->async_active.store(1, std::memory_order_release);
-    Engine::get().add(s);
+    try {
+        Engine::get().add(s);   // may start the thread: no exception leaves this ABI
+    } catch (...) {
+        s->async_left = 0;
+        s->async_active.store(0, std::memory_order_release);
+        return HOTRG_EHIP;
+    }
     return HOTRG_OK;
 }
 
