@@ -1176,6 +1176,15 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                                 ((uintptr_t)B.ptr & 15) == 0;
         if constexpr (ROLE == 0) {
             if (!f16_panels) return hipErrorInvalidValue;
+            // fewer 128 x 128 tiles than two per CU (D = 48: 324 of them)
+            // leave the CUs unevenly loaded; 64 x 128 tiles on four waves
+            // took the environment stage of a D = 48 step from 0.443 to
+            // 0.387 ms (D = 32: 0.161 -> 0.123), and were slower where the
+            // 128 x 128 grid already fills the chip (D = 64: 1.14 -> 1.59)
+            if ((long)((M + 127) / 128) * ((N + 127) / 128) < 512)
+                return run_gemm_dma<3, 64, 128, 2, 2, ROLE, true, true, kMidNst, kMidMinw, true>(A, lda, B, ldb, M,
+                                                                                                  N, K, st, map,
+                                                                                                  stream);
             return run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true, kMidNst, kMidMinw, true>(A, lda, B, ldb, M, N,
                                                                                                K, st, map, stream);
         } else if constexpr (ROLE == 2) {
