@@ -1216,7 +1216,9 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                           (!B.panel_k || (B.panel_k == ldb && K <= ldb && ldb % 16 == 0 && N % 32 == 0));
         const bool both = base && A.panel_k && B.panel_k && N > 64;
         if constexpr (ROLE == 0) {
-            // half environments and E (N = K = D^2): mid-size tiles
+            // half environments and E (N = K = D^2): mid-size tiles (64 x 128
+            // as in the FP16 form measured slower here: 0.591 -> 0.627 ms for
+            // the environment stage of a D = 48 BF16x6 step)
             if (!both) return hipErrorInvalidValue;
             return A.fmt == Fmt::BF16x2
                        ? run_gemm_dma<3, 128, 128, 2, 2, ROLE, true, true, kMidNst, kMidMinw>(
@@ -1300,12 +1302,27 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                       : run_gemm_p32<6, kP32BM, kP32BN, kP32WM, kP32WN, kP32PF,
                                      ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
     }
+    // FP64 / FP32: 64 x 64 tiles for narrow outputs (T', N = D') and where
+    // 128 x 128 gives fewer than two tiles per CU (the D = 24 products, the
+    // D = 48 environments), so that more workgroups share the work (FP64,
+    // per steady step: D = 24 environment 0.367 -> 0.136 ms and T' 0.123 ->
+    // 0.048; D = 48 environment 2.63 -> 1.86 and T' 1.72 -> 0.69; results
+    // bitwise unchanged, the K order of every element being the same)
+    const bool small_tiles = N <= 64 || (long)((M + 127) / 128) * ((N + 127) / 128) < 512;
     switch (A.fmt) {
         case Fmt::F64:
+            if (small_tiles)
+                return run_gemm<double, 64, 64, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
+                                                                static_cast<const double*>(B.ptr), ldb,
+                                                                M, N, K, st, map, stream);
             return run_gemm<double, 128, 128, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
                                                               static_cast<const double*>(B.ptr), ldb,
                                                               M, N, K, st, map, stream);
         case Fmt::F32:
+            if (small_tiles)
+                return run_gemm<float, 64, 64, 32, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
+                                                               static_cast<const float*>(B.ptr), ldb,
+                                                               M, N, K, st, map, stream);
             return run_gemm<float, 128, 128, 32, 2, 2, ROLE>(static_cast<const float*>(A.ptr), lda,
                                                              static_cast<const float*>(B.ptr), ldb,
                                                              M, N, K, st, map, stream);
