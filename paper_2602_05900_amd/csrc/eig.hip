@@ -517,24 +517,33 @@ __global__ __launch_bounds__(1024) void eig_chol_kernel(const double* __restrict
     __shared__ double d2[EIG_PMAX];
     for (int i = tid; i < p; i += 1024) d2[i] = 1.0 / A[i * EIG_LDP + i];
     __syncthreads();
-    // one column of M per thread: column j is the forward substitution
-    // L m = e_j, which reads only L and the column's own earlier entries, so
-    // the columns need no barriers between them (four partial sums per dot
-    // product for instruction-level parallelism)
-    for (int j = tid; j < p; j += 1024) {
-        for (int i = j + 1; i < p; ++i) {
-            const double* Li = A + i * EIG_LDP;
+    // One column of M per group of four lanes: column j is the forward
+    // substitution L m = e_j, which reads only L and the column's own
+    // earlier entries, so the columns need no barriers between them.  The
+    // dot product of row i is four partial sums: lane r of the group takes
+    // the terms m = j + 1 + r + 4t of the whole groups of four, lane 0 also
+    // the first term (m = j) and the remaining terms after the last whole
+    // group, in order, and lane 0 combines them as ((a0 + a1) + (a2 + a3)).
+    // Every entry is the same sequence of operations as a single thread
+    // running the four sums would perform.
+    {
+        const int r = tid & 3;
+        const int gbase = tid & 60;        // first lane of this group within the wave
+        for (int j = tid >> 2; j < p; j += 256) {
             const double* Mj = A + j * EIG_LDP;   // M[m][j] at A[j][m]
-            double a0 = Li[j] * d2[j], a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int m = j + 1;
-            for (; m + 3 < i; m += 4) {
-                a0 = fma(Li[m], Mj[m], a0);
-                a1 = fma(Li[m + 1], Mj[m + 1], a1);
-                a2 = fma(Li[m + 2], Mj[m + 2], a2);
-                a3 = fma(Li[m + 3], Mj[m + 3], a3);
+            for (int i = j + 1; i < p; ++i) {
+                const double* Li = A + i * EIG_LDP;
+                const int groups = (i - j - 1) >> 2;
+                double a = r == 0 ? Li[j] * d2[j] : 0.0;
+                for (int t = 0, m = j + 1 + r; t < groups; ++t, m += 4) a = fma(Li[m], Mj[m], a);
+                if (r == 0)
+                    for (int m = j + 1 + 4 * groups; m < i; ++m) a = fma(Li[m], Mj[m], a);
+                const double a1 = __shfl(a, gbase + 1), a2 = __shfl(a, gbase + 2), a3 = __shfl(a, gbase + 3);
+                if (r == 0) A[j * EIG_LDP + i] = -((a + a1) + (a2 + a3)) * d2[i];
+                // the group's next row reads this entry: the write must land first
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+                __builtin_amdgcn_wave_barrier();
             }
-            for (; m < i; ++m) a0 = fma(Li[m], Mj[m], a0);
-            A[j * EIG_LDP + i] = -((a0 + a1) + (a2 + a3)) * d2[i];
         }
     }
     __syncthreads();
