@@ -1303,19 +1303,23 @@ static hipError_t dispatch(const Buf& A, long lda, const Buf& B, long ldb, int M
                                      ROLE>(A, lda, B, ldb, M, N, K, st, map, stream);
     }
     // FP64 / FP32: 64 x 64 tiles for narrow outputs (T', N = D') and where
-    // 128 x 128 gives fewer than two tiles per CU (the D = 24 products, the
-    // D = 48 environments), so that more workgroups share the work (FP64,
-    // per steady step: D = 24 environment 0.367 -> 0.136 ms and T' 0.123 ->
-    // 0.048; D = 48 environment 2.63 -> 1.86 and T' 1.72 -> 0.69; results
-    // bitwise unchanged, the K order of every element being the same)
-    const bool small_tiles = N <= 64 || (long)((M + 127) / 128) * ((N + 127) / 128) < 512;
+    // 128 x 128 gives fewer than four tiles per CU (the D = 24 products, the
+    // D = 48 environments), so that the work spreads evenly over the CUs
+    // (FP64, per steady step: D = 24 environment 0.367 -> 0.136 ms, Y 0.376
+    // -> 0.227, X 0.068 -> 0.033, T' 0.123 -> 0.048; D = 48 environment
+    // 2.63 -> 1.86 and T' 1.72 -> 0.69; results bitwise unchanged, the K
+    // order of every element being the same)
+    const bool small_tiles = N <= 64 || (long)((M + 127) / 128) * ((N + 127) / 128) < 1024;
     switch (A.fmt) {
         case Fmt::F64:
             if (small_tiles)
                 return run_gemm<double, 64, 64, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
                                                                 static_cast<const double*>(B.ptr), ldb,
                                                                 M, N, K, st, map, stream);
-            return run_gemm<double, 128, 128, 16, 2, 2, ROLE>(static_cast<const double*>(A.ptr), lda,
+            // 256 x 128 tiles on 16 waves (64 x 32 each): the steady D = 48
+            // Y launch 26.4 -> 20.3 ms against 128 x 128 on 4 waves (2 x 4
+            // waves of 64 x 64: 21.0 ms; 256 x 256 spills the accumulators)
+            return run_gemm<double, 256, 128, 16, 4, 4, ROLE>(static_cast<const double*>(A.ptr), lda,
                                                               static_cast<const double*>(B.ptr), ldb,
                                                               M, N, K, st, map, stream);
         case Fmt::F32:
