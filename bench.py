@@ -17,7 +17,7 @@ product Y and the environment products with their operands split into two
 FP16 terms of the value times a fixed power of two, 3 products, the X and
 T' products split into three BF16 terms, 6 products, all with FP32
 accumulation; eigensolve, normalisation
-and ln Z in FP64).  Also reported: the same batch in BF16x6 and in FP64, per-solve service time
+and ln Z in FP64).  Also reported: the same batch in BF16x6, FP32 and FP64, per-solve service time
 p50/p99, per-stage GPU times from HIP events, |delta f| against the FP64
 oracle's stored values for these temperatures, the roofline of the dominant
 kernel (the steady-state Y product, 2 D^7 algorithmic FLOPs a launch,
@@ -546,7 +546,7 @@ def main(argv=None):
     ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
                     help="skip the FP64 run of the same batch")
     ap.add_argument("--no-compare", dest="compare", action="store_false",
-                    help="skip the BF16x6 and FP64 runs of the same batch")
+                    help="skip the BF16x6, FP32 and FP64 runs of the same batch")
     ap.add_argument("--dmax", type=int, default=48)
     ap.add_argument("--nsteps", type=int, default=30, help="coarse-graining steps per solve")
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
@@ -686,7 +686,9 @@ def main(argv=None):
             out["max_rel_err_vs_fp64_oracle"] = max(ferr)
         return out
 
-    for prec in ("bf16x6", "fp64"):
+    # the same requests in the other precisions of the mixed-precision
+    # workload (FP32 and BF16 split contractions) and in FP64
+    for prec in ("bf16x6", "fp32", "fp64"):
         if prec != args.precision and args.compare and (prec != "fp64" or args.compare_fp64):
             run_leg(line, f"{prec}_comparison", comparison, prec)
     if args.c2:
