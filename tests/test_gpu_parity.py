@@ -48,6 +48,9 @@ GEMM_CASES = [
     # (128x64 for N <= 64, 128x128, and 256x256 from 512 such tiles up);
     # K steps 10 -> 12 and 2 -> 3 exercise the zero padding
     (257, 300, 160), (70, 1000, 32), (600, 520, 2304), (8192, 4096, 48),
+    # FP64 / FP32: 64 x 64 tiles below four 128 x 128 tiles per CU (the cases
+    # above), 256 x 128 tiles on 16 waves from there: ragged in M, N and K
+    (4100, 4200, 19),
 ]
 
 
