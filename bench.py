@@ -31,8 +31,8 @@ solve at Tc in BF16x6 and in FP64 ("c5"), two-sided truncation with
 impurity observables, iTEBD chains and the quantum chain.
 
 Stepping (--stepping for the headline batch and the served stream,
---latency-stepping for the one-solve-at-a-time legs C2 and the quantum
-chain): whole steps enqueue every eigensolver pass up to the cap, and a pass
+--latency-stepping for the one-solve-at-a-time legs C2, the observables and
+the quantum chain): whole steps enqueue every eigensolver pass up to the cap, and a pass
 after convergence exits at once; host-polled steps enqueue a step's
 products once the eigensolve has stopped, either from the scheduler loop
 ("polled") or from the library's progress thread ("engine").  The results
@@ -154,15 +154,23 @@ def run_c2(serve, accounting, workloads, budget, stepping="engine"):
     return out
 
 
-def run_observables(binding, accounting):
+def run_observables(binding, accounting, stepping="engine"):
     """Two-sided truncation with the magnetisation and bond-energy impurity
     tensors carried along.  (1) Ising, D = 24, 30 steps, FP64, 16
     temperatures of the D = 24 grid (every fourth of linspace(1.8, 2.8, 64)),
     field 1e-8 to select the ordered state below T_c, one solve at a time:
     throughput, the direct internal energy 2 <e_b> - h <m> against Onsager
     and <m> against Yang's spontaneous magnetisation.  (2) The same mode at
-    D = 48 in BF16x6 at four temperatures: throughput."""
+    D = 48 in BF16x6 at four temperatures: throughput.  One solve at a time:
+    the steps are host-polled by the library's progress thread (`stepping`),
+    and the D = 24 scan is timed with whole steps beside it."""
     import torch
+
+    def advance(s, mode):
+        if mode == "engine":
+            s.coarse_grain_async(30)
+        else:
+            s.coarse_grain(30)
     ref = onsager_reference()
     g = ref["grid"] if ref else None
     idx = list(range(0, 64, 4))
@@ -175,20 +183,27 @@ def run_observables(binding, accounting):
                       field=h, two_sided=True, observables=("m", "e"))
     s.coarse_grain(30)
     s.observables()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = []
-    for t in temps:
-        s.reset(model="ising", q=2, temperature=t, dmax=24, precision="fp64", max_steps=30, field=h,
-                two_sided=True, observables=("m", "e"))
-        s.coarse_grain(30)
-        v = s.observables()
-        res.append((t, s.log_z(), v["m"], v["e"]))
-    wall = time.perf_counter() - t0
-    s.close()
+    def scan(mode):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = []
+        for t in temps:
+            s.reset(model="ising", q=2, temperature=t, dmax=24, precision="fp64", max_steps=30, field=h,
+                    two_sided=True, observables=("m", "e"))
+            advance(s, mode)
+            v = s.observables()
+            res.append((t, s.log_z(), v["m"], v["e"]))
+        return res, time.perf_counter() - t0
+
+    res, wall = scan(stepping)
     flops = accounting.solve_flops(2, 24, 30, two_sided=True, nimp=nimp)
-    out.update({"solves": len(res), "seconds": wall, "tflops": len(res) * flops / wall / 1e12,
-                "flops_per_solve": flops})
+    out.update({"stepping": stepping, "solves": len(res), "seconds": wall,
+                "tflops": len(res) * flops / wall / 1e12, "flops_per_solve": flops})
+    if stepping != "whole":
+        res_w, wall_w = scan("whole")
+        out["seconds_whole_steps"] = wall_w
+        out["results_bitwise_equal_to_whole_steps"] = res_w == res
+    s.close()
     if g:
         tc = ref["critical"]["temperature"]
         du, dm, dmf = [], [], []
@@ -213,7 +228,7 @@ def run_observables(binding, accounting):
     for t in temps48:
         s.reset(model="ising", q=2, temperature=t, dmax=48, precision="bf16x6", max_steps=30, field=h,
                 two_sided=True, observables=("m", "e"))
-        s.coarse_grain(30)
+        advance(s, stepping)
         s.observables()
     wall = time.perf_counter() - t0
     s.close()
@@ -556,7 +571,7 @@ def main(argv=None):
                     help="whole steps (every eigensolver pass up to the cap enqueued), host-polled steps "
                          "driven by the scheduler, or by the library's progress thread")
     ap.add_argument("--latency-stepping", default="engine", choices=["whole", "engine"],
-                    help="steps of the one-solve-at-a-time legs (C2 scan, quantum chain): whole steps or "
+                    help="steps of the one-solve-at-a-time legs (C2 scan, observables, quantum chain): whole steps or "
                          "host-polled steps driven by the library's progress thread")
     ap.add_argument("--budget-gb", type=int, default=128, help="device memory for solve workspaces")
     ap.add_argument("--no-c2", dest="c2", action="store_false", help="skip the D=24 temperature scan")
@@ -699,7 +714,7 @@ def main(argv=None):
     if args.c5:
         run_leg(line, "c5", run_c5, binding, accounting)
     if args.observables:
-        run_leg(line, "observables", run_observables, binding, accounting)
+        run_leg(line, "observables", run_observables, binding, accounting, args.latency_stepping)
     if args.itebd:
         run_leg(line, "itebd", run_itebd, binding, workloads)
     if args.qchain:

@@ -233,9 +233,13 @@ int hotrg_coarse_grain_batch(hotrg_solve* const* solves, int count, int nsteps);
  *                     tested every second pass, and capped at the pass
  *                     limit), then the store of the stop state;
  *                     *pending (may be NULL) = 1.  A step whose environment
- *                     is diagonalised densely (Dx^2 <= 96) or a two-sided
- *                     handle has the whole step enqueued at once and
- *                     *pending = 0.  exchange as in hotrg_coarse_grain_axis.
+ *                     is diagonalised densely (Dx^2 <= 96) is enqueued whole
+ *                     at once and *pending = 0.  On a two-sided handle the
+ *                     left eigensolve goes first; once it has stopped, a poll
+ *                     enqueues its end and the right one's start and first
+ *                     passes (HOTRG_POLL_PASSES), and the step's products
+ *                     follow the right one.  exchange as in
+ *                     hotrg_coarse_grain_axis.
  *   hotrg_step_poll   never waits.  *state = HOTRG_POLL_IDLE (no step
  *                     pending), HOTRG_POLL_RUNNING (the last store has not
  *                     arrived; nothing enqueued), HOTRG_POLL_PASSES (not

@@ -476,6 +476,8 @@ struct hotrg_solve {
     bool pend_exchange = true;
     int pend_next = 0;              // next subspace pass to enqueue
     int pend_par = 0;
+    int pend_side = 0;              // two-sided: 0 left eigensolve in flight, 1 right
+    bool pend_warm_r = false;       // warm start of the right eigensolve
     int hist[2] = {0, 0};           // passes the last polled eigensolve of each parity used
     // steps driven by the library's progress thread (hotrg_coarse_grain_async);
     // while async_active is set only that thread touches the handle
@@ -569,7 +571,9 @@ bool step_fits(const Layout& L, int Dx, int Dy, int Dp) {
 // bookkeeping.  The default is the whole step.
 struct StepPart {
     bool env = true;
-    EigRange eig;
+    bool left = true, right = true;   // launch the range of the left / right eigensolve
+    EigRange eig;                     // of the left one
+    EigRange eigR;                    // of the right one (two-sided handles)
     bool rest = true;
 };
 
@@ -669,17 +673,27 @@ int enqueue_step(hotrg_solve* s, bool exchange = true, const StepPart& part = St
         const int pblk = nE > kEigPMax ? eig_block(nE, Dp) : nE;
         const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)n;
         const bool warm = nE > kEigPMax && s->warm_n[par] == nE && s->warm_p[par] == pblk;
-        HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, s->eig_maxit, kEigTol, s->eig_fail,
-                                   Ut, Ux, s->state(), n, s->stream, 0, part.eig));
-        if (two) {   // whole steps only (the host-polled form takes one-sided solves)
+        if (part.left)
+            HIP_TRY(s, launch_eig_topk(E, nE, Dp, Dx, s->eig(), par, warm, seed, s->eig_maxit, kEigTol,
+                                       s->eig_fail, Ut, Ux, s->state(), n, s->stream, 0, part.eig));
+        if (two) {
+            // the right eigensolve follows the left one on the same control
+            // block; in the host-polled form it starts in a later part, with
+            // the warm-start choice taken when the left one started
             const Buf UtR = make_buf(w, L.oUtR, f, L.nU), UxR = make_buf(w, L.oUxR, f, L.nU);
-            const bool warm_r = nE > kEigPMax && s->warm_nr[par] == nE && s->warm_pr[par] == pblk;
-            HIP_TRY(s, launch_eig_topk(ER, nE, Dp, Dx, s->eig_right(), par, warm_r, seed, s->eig_maxit,
-                                       kEigTol, s->eig_fail, UtR, UxR, s->state(), n, s->stream, 1));
-            HIP_TRY(s, launch_choose_side(s->state(), n, Ut.ptr, Ux.ptr, UtR.ptr, UxR.ptr, buf_bytes(f, L.nU),
-                                          s->stream));
+            const bool warm_r = part.left && part.eig.start
+                                    ? nE > kEigPMax && s->warm_nr[par] == nE && s->warm_pr[par] == pblk
+                                    : s->pend_warm_r;
+            if (part.right)
+                HIP_TRY(s, launch_eig_topk(ER, nE, Dp, Dx, s->eig_right(), par, warm_r, seed, s->eig_maxit,
+                                           kEigTol, s->eig_fail, UtR, UxR, s->state(), n, s->stream, 1,
+                                           part.eigR));
+            if (part.rest)
+                HIP_TRY(s, launch_choose_side(s->state(), n, Ut.ptr, Ux.ptr, UtR.ptr, UxR.ptr,
+                                              buf_bytes(f, L.nU), s->stream));
+            if (part.left && part.eig.start) s->pend_warm_r = warm_r;
         }
-        if (nE > kEigPMax && part.eig.start) {
+        if (nE > kEigPMax && part.left && part.eig.start) {
             s->warm_n[par] = s->warm_nr[par] = nE;
             s->warm_p[par] = s->warm_pr[par] = pblk;
         }
@@ -859,8 +873,8 @@ int begin_step(hotrg_solve* s, int exchange, int extra, int* pending) {
     if (!s || (exchange != 0 && exchange != 1) || extra < 0 || s->pend) return HOTRG_EINVAL;
     if (s->host_status) return HOTRG_ESTATE;
     if (s->steps + 1 > step_cap(&s->p)) return HOTRG_EINVAL;
-    // dense eigensolves and two-sided steps are enqueued whole
-    if (s->dx * s->dx <= kEigPMax || s->p.two_sided) return enqueue_step(s, exchange != 0);
+    // steps whose environment is diagonalised densely are enqueued whole
+    if (s->dx * s->dx <= kEigPMax) return enqueue_step(s, exchange != 0);
     if (!s->mail) {
         void* h = nullptr;
         if (hipHostMalloc(&h, sizeof(EigMail), hipHostMallocCoherent) != hipSuccess) return HOTRG_EHIP;
@@ -872,6 +886,7 @@ int begin_step(hotrg_solve* s, int exchange, int extra, int* pending) {
     int first = (s->hist[par] > 0 ? s->hist[par] : kPollFirst) + std::min(extra, HOTRG_EIG_MAX_PASSES);
     first = std::min((first + 1) / 2 * 2, s->eig_maxit);
     StepPart part;
+    part.right = false;            // a two-sided step starts with the left eigensolve
     part.eig.last = first;
     part.eig.end = false;
     part.rest = false;
@@ -882,6 +897,7 @@ int begin_step(hotrg_solve* s, int exchange, int extra, int* pending) {
     s->pend_exchange = exchange != 0;
     s->pend_next = first;
     s->pend_par = par;
+    s->pend_side = 0;
     if (pending) *pending = 1;
     return HOTRG_OK;
 }
@@ -899,26 +915,46 @@ int poll_step(hotrg_solve* s, int* state) {
     struct {
         int done, iters;
     } c{(int)(word & 1u), (int)((word >> 1) & 0x7fffffffu)};
+    // the eigensolve in flight: the left one, or the right one of a
+    // two-sided step once the left one has ended
+    const bool on_right = s->pend_side == 1;
     StepPart part;
     part.env = false;
-    part.eig.start = false;
-    part.eig.first = s->pend_next;
+    part.left = !on_right;
+    part.right = on_right;
+    EigRange& cur = on_right ? part.eigR : part.eig;
+    cur.start = false;
+    cur.first = s->pend_next;
     int rc;
     if (c.done || s->pend_next >= s->eig_maxit) {
-        // converged, stagnated or at the pass cap: the rest of the step
-        part.eig.last = s->pend_next;
+        // converged, stagnated or at the pass cap: the end of this
+        // eigensolve, then the right one's start or the rest of the step
+        cur.last = s->pend_next;
         s->hist[s->pend_par] = c.iters > 0 ? c.iters : s->pend_next;
+        if (s->p.two_sided && !on_right) {
+            const int first = std::min((s->hist[s->pend_par] + 1) / 2 * 2, s->eig_maxit);
+            part.right = true;
+            part.eigR.last = first;
+            part.eigR.end = false;
+            part.rest = false;
+            if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
+            if ((rc = mail_copy(s))) return rc;
+            s->pend_side = 1;
+            s->pend_next = first;
+            *state = HOTRG_POLL_PASSES;
+            return HOTRG_OK;
+        }
         s->pend = false;
         if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
         *state = HOTRG_POLL_STEPPED;
         return HOTRG_OK;
     }
-    part.eig.last = std::min(s->pend_next + kPollChunk, s->eig_maxit);
-    part.eig.end = false;
+    cur.last = std::min(s->pend_next + kPollChunk, s->eig_maxit);
+    cur.end = false;
     part.rest = false;
     if ((rc = enqueue_step(s, s->pend_exchange, part))) return rc;
     if ((rc = mail_copy(s))) return rc;
-    s->pend_next = part.eig.last;
+    s->pend_next = cur.last;
     *state = HOTRG_POLL_PASSES;
     return HOTRG_OK;
 }

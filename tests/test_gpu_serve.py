@@ -258,3 +258,31 @@ def test_engine_server_results_identical_alone_and_in_the_mix(gpu_lib):
     for c in done:
         assert c.lnz_per_site == alone[c.rid], (c.rid, c.lnz_per_site, alone[c.rid])
     assert srv.in_use == 0
+
+
+@pytest.mark.parametrize("d,prec,n", [(24, "fp64", 16), (32, "bf16x6", 12)])
+def test_polled_and_engine_two_sided_with_observables(gpu_lib, d, prec, n):
+    """Two-sided handles with both impurity tensors: host-polled steps (the
+    left eigensolve, then the right one, then the products) and the progress
+    thread give bitwise the results of whole steps: ln Z, the observables,
+    both sides' truncation errors and the side applied, every c_n and
+    eigensolver record."""
+    from paper_2602_05900_amd import binding
+    kw = dict(model="ising", q=2, temperature=2.2, dmax=d, precision=prec, max_steps=n, field=1e-8,
+              two_sided=True, observables=("m", "e"))
+    ref = binding.Solve(**kw)
+    ref.coarse_grain(n)
+    polled = binding.Solve(**kw)
+    seen = _polled(polled, n)
+    assert seen.count(binding.POLL_STEPPED) + seen.count("whole") == n
+    engine = binding.Solve(**kw)
+    engine.coarse_grain_async(n)
+    for s in (polled, engine):
+        assert s.log_z() == ref.log_z()
+        assert s.observables() == ref.observables()
+        for k in range(1, n + 1):
+            assert s.step_sides(k) == ref.step_sides(k), k
+            assert s.step_info(k) == ref.step_info(k), k
+            assert s.eig_info(k) == ref.eig_info(k), k
+    for s in (ref, polled, engine):
+        s.close()
