@@ -10,7 +10,10 @@ overlap on the device (iteration-level scheduling, not run-to-completion).  A
 solve completes when the event recorded after its last step has fired; its
 ln Z / N is read, its latency recorded, and its memory and slot are released
 for the next request.  All device work goes through the C ABI (binding.py);
-this module only schedules.
+this module only schedules.  The steps themselves are whole steps (every
+eigensolver pass up to the cap enqueued), host-polled steps driven by this
+loop, or host-polled steps driven by the library's progress thread
+(`stepping`); the results are bitwise the same.
 
 Results do not depend on the mix: each solve's kernels use fixed-order
 reductions and no atomics, so a solve gives bitwise the same ln Z / N alone
