@@ -567,7 +567,7 @@ def main(argv=None):
     ap.add_argument("--cpu-sample-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--concurrency", type=int, default=4, help="solves in flight (streams)")
-    ap.add_argument("--stepping", default="whole", choices=["whole", "polled", "engine"],
+    ap.add_argument("--stepping", default="whole", choices=["whole", "polled", "engine", "hybrid"],
                     help="whole steps (every eigensolver pass up to the cap enqueued), host-polled steps "
                          "driven by the scheduler, or by the library's progress thread")
     ap.add_argument("--latency-stepping", default="engine", choices=["whole", "engine"],

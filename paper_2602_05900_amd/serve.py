@@ -67,6 +67,7 @@ class _Active:
     slot: int = -1
     enqueued: int = 0
     pending: bool = False     # a host-polled step waits for its eigensolve
+    mode: str = "whole"       # how this solve's steps are enqueued
     events: collections.deque = field(default_factory=collections.deque)
 
 
@@ -86,21 +87,24 @@ class Server:
                 its eigensolve stop, so no pass after convergence is
                 enqueued; "engine": the same steps driven by the library's
                 own progress thread (hotrg_coarse_grain_async), this loop
-                only admitting and completing solves
+                only admitting and completing solves; "hybrid": "engine" for
+                solves with D <= hybrid_dmax, "whole" for the others
     poll_extra  passes beyond a solve's history in a polled step's first group
     idle_sleep  seconds the scheduling loop sleeps when a round enqueued nothing
     """
 
-    STEPPINGS = ("whole", "polled", "engine")
+    STEPPINGS = ("whole", "polled", "engine", "hybrid")
 
     def __init__(self, slots: int = 8, budget: int = 64 << 30, depth: int = 2,
                  precision: str = "fp64", device: str = "cuda:0", timing: bool = False,
-                 stepping: str = "whole", poll_extra: int = 0, idle_sleep: float = 2e-4):
+                 stepping: str = "whole", poll_extra: int = 0, idle_sleep: float = 2e-4,
+                 hybrid_dmax: int = 32):
         if stepping not in self.STEPPINGS:
             raise ValueError(f"stepping must be one of {self.STEPPINGS}")
         binding.load()
         self.timing = timing
         self.stepping = stepping
+        self.hybrid_dmax = hybrid_dmax
         self.poll_extra = poll_extra
         self.idle_sleep = idle_sleep
         self.device = torch.device(device)
@@ -150,7 +154,10 @@ class Server:
                 solve.set_timing(True)
             a = _Active(req=req, solve=solve, stream=stream, workspace=ws, footprint=fp, admitted=self._now(),
                         slot=si)
-            if self.stepping == "engine":
+            a.mode = self.stepping
+            if a.mode == "hybrid":
+                a.mode = "engine" if req.dmax <= self.hybrid_dmax else "whole"
+            if a.mode == "engine":
                 solve.coarse_grain_async(req.nsteps, extra=self.poll_extra)
                 a.enqueued = req.nsteps
                 a.pending = True
@@ -167,6 +174,8 @@ class Server:
         none pending and room on its stream; True if anything was enqueued."""
         progressed = False
         for a in self.active:
+            if a.mode != "polled":
+                continue
             while a.events and a.events[0].query():
                 a.events.popleft()
             if a.pending:
@@ -191,7 +200,7 @@ class Server:
         event its completion waits for."""
         progressed = False
         for a in self.active:
-            if a.pending and not a.solve.async_busy():
+            if a.mode == "engine" and a.pending and not a.solve.async_busy():
                 a.pending = False
                 self._stepped(a)
                 progressed = True
@@ -200,18 +209,18 @@ class Server:
     def _advance(self) -> bool:
         """Enqueue at most one step per active solve, as one grouped call over
         the solves that have room; returns True if any step was enqueued."""
-        if self.stepping == "polled":
-            return self._advance_polled()
-        if self.stepping == "engine":
-            return self._advance_engine()
+        progressed = self._advance_polled()
+        progressed = self._advance_engine() or progressed
         ready = []
         for a in self.active:
+            if a.mode != "whole":
+                continue
             while a.events and a.events[0].query():
                 a.events.popleft()
             if a.enqueued < a.req.nsteps and len(a.events) < self.depth:
                 ready.append(a)
         if not ready:
-            return False
+            return progressed
         binding.coarse_grain_batch([a.solve for a in ready], 1)
         for a in ready:
             a.enqueued += 1

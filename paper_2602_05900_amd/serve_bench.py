@@ -30,7 +30,7 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=int, default=160)
     ap.add_argument("--seed", type=int, default=None)
-    ap.add_argument("--stepping", default="whole", choices=["whole", "polled", "engine"])
+    ap.add_argument("--stepping", default="whole", choices=["whole", "polled", "engine", "hybrid"])
     args = ap.parse_args()
 
     import torch

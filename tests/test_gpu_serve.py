@@ -239,7 +239,8 @@ def test_engine_quantum_chain_and_continuation(gpu_lib):
     ref.close()
 
 
-def test_engine_server_results_identical_alone_and_in_the_mix(gpu_lib):
+@pytest.mark.parametrize("stepping", ["engine", "hybrid"])
+def test_engine_server_results_identical_alone_and_in_the_mix(gpu_lib, stepping):
     from paper_2602_05900_amd import binding, serve, workloads
     reqs = [workloads.Request(rid=i, arrival=0.001 * i, model=m, q=q, temperature=t, dmax=d, nsteps=n)
             for i, (m, q, t, d, n) in enumerate([
@@ -252,7 +253,7 @@ def test_engine_server_results_identical_alone_and_in_the_mix(gpu_lib):
         s.coarse_grain(r.nsteps)
         alone[r.rid] = s.log_z()
         s.close()
-    srv = serve.Server(slots=4, budget=32 << 30, precision="fp16x3", stepping="engine")
+    srv = serve.Server(slots=4, budget=32 << 30, precision="fp16x3", stepping=stepping)
     done = srv.run(reqs, realtime=False)
     assert len(done) == len(reqs)
     for c in done:

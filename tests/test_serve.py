@@ -136,6 +136,20 @@ def test_engine_server_takes_every_step(fake_device):
         serve.Server(slots=1, device="cpu", stepping="sometimes")
 
 
+def test_hybrid_server_takes_every_step(fake_device):
+    """Small solves driven by the progress thread, large ones by whole steps,
+    in one server."""
+    reqs = workloads.request_stream(rate_hz=200.0, duration_s=0.3, seed=7)
+    assert {r.dmax <= 32 for r in reqs} == {True, False}
+    srv = serve.Server(slots=4, budget=1 << 40, precision="fp64", device="cpu", stepping="hybrid")
+    done = srv.run(reqs, realtime=False)
+    assert len(done) == len(reqs)
+    for c in done:
+        r = reqs[c.rid]
+        assert abs(c.lnz_per_site - (1.0 + r.temperature * 1e-3 + r.nsteps * 1e-6)) < 1e-12
+    assert srv.in_use == 0 and FakeSolve.live == 0
+
+
 def test_request_larger_than_budget_is_rejected(fake_device):
     reqs = [workloads.Request(rid=0, arrival=0.0, model="ising", q=2, temperature=2.0, dmax=48, nsteps=20)]
     srv = serve.Server(slots=2, budget=1000, device="cpu")
