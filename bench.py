@@ -668,6 +668,7 @@ def main(argv=None):
             "eigensolve": "FP64",
             "concurrency": args.concurrency,
             "stepping": args.stepping,
+            "latency_stepping": args.latency_stepping,
             "flops_per_solve": flops_solve,
         },
         "p50_solve_ms": serve.percentile(service, 50) * 1e3,
