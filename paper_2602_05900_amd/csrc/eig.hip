@@ -484,75 +484,40 @@ __global__ __launch_bounds__(1024) void eig_chol_kernel(const double* __restrict
         A[i * EIG_LDP + j] = v;
     }
     __syncthreads();
-    // right-looking Cholesky of the lower triangle, one barrier per column:
-    // every thread takes the pivot sqrt(A_jj) itself (A_jj is final at
-    // column j); the trailing update scales the column-j entries it needs on
-    // the fly (column j is only read in this phase), and the scaled column is
-    // written transposed into the free upper triangle (row j), then copied
-    // back into the lower triangle after the last column.
+    // Right-looking Cholesky of the lower triangle with the elimination
+    // applied to the identity beside it, one barrier per column: every thread
+    // takes the pivot L_jj = sqrt(A_jj) itself (A_jj is final at column j);
+    // the trailing update of A scales the column-j entries it needs on the
+    // fly (column j is only read in this phase), and the same row operations
+    // on R (= I at the start) leave R = L^{-1} (rows unscaled until the end:
+    // row j of R is read only at column j, scaled on the fly as well).
+    __shared__ double R[EIG_PMAX * EIG_LDP];
     __shared__ double ldiag[EIG_PMAX];
+    for (int e = tid; e < p * p; e += 1024) {
+        const int i = e / p, c = e - (e / p) * p;
+        if (c <= i) R[i * EIG_LDP + c] = i == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
     const int ty = tid >> 5, tx = tid & 31;
     for (int j = 0; j < p; ++j) {
         const double a = A[j * EIG_LDP + j];
         const double ljj = a > 1e-300 ? sqrt(a) : 1.0;
         const double inv = 1.0 / ljj;
         if (tid == 0) ldiag[j] = ljj;
-        // thread (ty, tx) of a 32 x 32 grid: rows i = j + 1 + ty, ..., columns l = j + 1 + tx, ... <= i
+        // thread (ty, tx) of a 32 x 32 grid: rows i = j + 1 + ty, ...; columns
+        // l = j + 1 + tx, ... <= i of A and c = tx, ... <= j of R
         for (int i = j + 1 + ty; i < p; i += 32) {
             const double lij = A[i * EIG_LDP + j] * inv;
-            if (tx == 0) A[j * EIG_LDP + i] = lij;
             for (int l = j + 1 + tx; l <= i; l += 32) A[i * EIG_LDP + l] -= lij * (A[l * EIG_LDP + j] * inv);
+            for (int c = tx; c <= j; c += 32) R[i * EIG_LDP + c] -= lij * (R[j * EIG_LDP + c] * inv);
         }
         __syncthreads();
     }
-    for (int e = tid; e < p * p; e += 1024) {
-        const int i = e / p, c = e - (e / p) * p;
-        if (c < i) A[i * EIG_LDP + c] = A[c * EIG_LDP + i];
-        else if (c == i) A[i * EIG_LDP + i] = ldiag[i];
-    }
-    __syncthreads();
-    // M = L^{-1} (lower), row by row: M[i][j] = -(sum_{m=j}^{i-1} L[i][m] M[m][j]) / L[i][i]
-    // kept in the strict upper triangle of A transposed (A[j][i] for j < i) and
-    // the diagonal in d2; L stays in the lower triangle.
-    __shared__ double d2[EIG_PMAX];
-    for (int i = tid; i < p; i += 1024) d2[i] = 1.0 / A[i * EIG_LDP + i];
-    __syncthreads();
-    // One column of M per group of four lanes: column j is the forward
-    // substitution L m = e_j, which reads only L and the column's own
-    // earlier entries, so the columns need no barriers between them.  The
-    // dot product of row i is four partial sums: lane r of the group takes
-    // the terms m = j + 1 + r + 4t of the whole groups of four, lane 0 also
-    // the first term (m = j) and the remaining terms after the last whole
-    // group, in order, and lane 0 combines them as ((a0 + a1) + (a2 + a3)).
-    // Every entry is the same sequence of operations as a single thread
-    // running the four sums would perform.
-    {
-        const int r = tid & 3;
-        const int gbase = tid & 60;        // first lane of this group within the wave
-        for (int j = tid >> 2; j < p; j += 256) {
-            const double* Mj = A + j * EIG_LDP;   // M[m][j] at A[j][m]
-            for (int i = j + 1; i < p; ++i) {
-                const double* Li = A + i * EIG_LDP;
-                const int groups = (i - j - 1) >> 2;
-                double a = r == 0 ? Li[j] * d2[j] : 0.0;
-                for (int t = 0, m = j + 1 + r; t < groups; ++t, m += 4) a = fma(Li[m], Mj[m], a);
-                if (r == 0)
-                    for (int m = j + 1 + 4 * groups; m < i; ++m) a = fma(Li[m], Mj[m], a);
-                const double a1 = __shfl(a, gbase + 1), a2 = __shfl(a, gbase + 2), a3 = __shfl(a, gbase + 3);
-                if (r == 0) A[j * EIG_LDP + i] = -((a + a1) + (a2 + a3)) * d2[i];
-                // the group's next row reads this entry: the write must land first
-                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-    }
-    __syncthreads();
-    // Q[r][c] = d_r * M[c][r] (X_new = X D L^{-T}); M[c][r] = 0 for r > c
+    // Q[r][c] = d_r * M[c][r] (X_new = X D L^{-T}), M = L^{-1} = R with row c
+    // scaled by 1 / L_cc; M[c][r] = 0 for r > c
     for (int e = tid; e < p * p; e += 1024) {
         const int r = e / p, c = e - (e / p) * p;
-        double m = 0.0;
-        if (r == c) m = d2[r];
-        else if (r < c) m = A[r * EIG_LDP + c];
+        const double m = r <= c ? R[c * EIG_LDP + r] * (1.0 / ldiag[c]) : 0.0;
         // a vanishing column is replaced by uniform(-1,1) entries of norm ~ sqrt(n/3)
         const double dr = d[r] != 0.0 ? d[r] : 1.0 / sqrt(n / 3.0);
         Lout[e] = dr * m;
